@@ -1,0 +1,232 @@
+/*
+ * pmrf.h -- C ABI of the MI355X (gfx950) EM optimisation path of DPP-PMRF
+ * (Lessley, Perciano, Heinemann, Camp, Childs, Bethel: "DPP-PMRF: Rethinking
+ * Optimization for a Probabilistic Graphical Model Using Data-Parallel
+ * Primitives", LDAV 2018, arXiv:1809.05018).
+ *
+ * The problem statement of Alg. 1 / Alg. 2 (inputs: image, oversegmentation,
+ * number of labels; outputs: segmentation and estimated parameters) is taken
+ * at the point where the paper says the optimisation consumes a graph
+ * (Sec. 5): the caller hands over the region-adjacency graph of the
+ * oversegmentation as CSR plus one intensity per region, and receives one
+ * label per region plus the per-label mean and standard deviation.
+ *
+ * Conventions for every call:
+ *  - Return value: PMRF_OK (0) or a negative pmrf_status.  On an error found
+ *    on the host, no caller-visible output has been written.  The message of
+ *    the last error on the calling thread is pmrf_last_error().
+ *  - "host" pointers are ordinary CPU memory; "device" pointers are HIP device
+ *    memory (for example torch tensors' data_ptr() on a ROCm device).
+ *  - The caller owns every buffer it passes.  The library owns only the opaque
+ *    host object pmrf_hoods (freed with pmrf_hoods_free).  The library never
+ *    allocates device memory: buffers it needs come in as a caller workspace.
+ *  - Device work is enqueued on the given HIP stream (hipStream_t passed as
+ *    void*, NULL = the null stream) and is asynchronous; results are valid
+ *    after the stream is synchronised.  Errors that only the device can see
+ *    (a starting label outside [0, L), a non-positive starting sigma, a
+ *    non-finite intensity) are reported in counters[PMRF_CTR_STATUS].
+ *  - Labels are int32; intensities, parameters and energies are IEEE double.
+ */
+#ifndef PMRF_H
+#define PMRF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pmrf_status;
+#define PMRF_OK 0
+#define PMRF_EINVAL (-1)       /* bad argument or malformed graph */
+#define PMRF_ENOMEM (-2)       /* a caller buffer is too small, or host allocation failed */
+#define PMRF_EDEVICE (-3)      /* a HIP runtime call failed */
+#define PMRF_EUNSUPPORTED (-4) /* valid request outside what this build supports (k != 1, L > 16, neighbourhood > 1024) */
+/* device-reported codes, in counters[PMRF_CTR_STATUS] */
+#define PMRF_EBADLABEL (-10)   /* a starting label outside [0, L) */
+#define PMRF_EBADPARAM (-11)   /* a starting sigma <= 0 or a non-finite mu / sigma */
+#define PMRF_ERANGE (-12)      /* an intensity or energy too large for the exact accumulators (|value| >= 2^62) */
+#define PMRF_ETIMEOUT (-13)    /* the persistent kernel's grid barrier did not complete (not co-resident) */
+
+/* Thread-local text of the last error (never NULL; "" if none). */
+const char *pmrf_last_error(void);
+
+/* Version of this ABI (incremented on any incompatible change). */
+int32_t pmrf_abi_version(void);
+
+/* ------------------------------------------------------------------------
+ * Neighbourhoods (Sec. 3.1: a k-neighbourhood is a maximal clique together
+ * with every vertex within k edges of it, here k = 1; Sec. 3.2.1 and the
+ * construction steps of Sec. 3.2.2, "Construction of Neighborhoods").
+ *
+ * Maximal cliques are listed in canonical order (each clique ascending, the
+ * list in lexicographic order), neighbourhood h belongs to clique h, and the
+ * members of a neighbourhood are in ascending vertex order.  An isolated
+ * vertex is a clique (and a neighbourhood) of its own.  Every vertex is
+ * "owned" by its position in the first clique that contains it; that element
+ * sees all of the vertex's neighbours and decides its label.
+ * ------------------------------------------------------------------------ */
+typedef struct pmrf_hoods pmrf_hoods;
+
+typedef struct {
+  int64_t n;            /* vertices */
+  int64_t H;            /* maximal cliques = neighbourhoods */
+  int64_t M;            /* neighbourhood elements, sum of sizes */
+  int64_t A;            /* in-neighbourhood adjacency entries */
+  int64_t max_hood;     /* largest neighbourhood */
+  int64_t tiles;        /* wave-sized work packets of the device layout */
+  int64_t device_bytes; /* exact size of the device copy written by pmrf_hoods_upload */
+} pmrf_hoods_info;
+
+/* Build the neighbourhoods of an undirected graph given as CSR (host).
+ * row_ptr[n+1] (row_ptr[0] = 0, non-decreasing) and col_idx[row_ptr[n]]
+ * with each row strictly ascending, no self loops, every edge present in both
+ * directions.  k is the neighbourhood radius; only k = 1 is supported.
+ * n = 0 is allowed (empty problem).  *out receives a new host object.
+ * Errors: PMRF_EINVAL (malformed CSR, NULL pointers), PMRF_EUNSUPPORTED
+ * (k != 1, a neighbourhood above 1024 members), PMRF_ENOMEM. */
+pmrf_status pmrf_build_neighborhoods(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, int32_t k,
+                                     pmrf_hoods **out);
+
+pmrf_status pmrf_hoods_get_info(const pmrf_hoods *hoods, pmrf_hoods_info *info);
+
+/* Host copies of the canonical structure (for inspection and tests):
+ * hood_ptr[H+1], hood_vid[M], clique_ptr[H+1], clique_vid[clique members],
+ * owner[n] = element index (into hood_vid) owning each vertex.  Any output
+ * may be NULL.  clique sizes total = clique_ptr[H]. */
+pmrf_status pmrf_hoods_export(const pmrf_hoods *hoods, int64_t *hood_ptr, int32_t *hood_vid, int64_t *clique_ptr,
+                              int32_t *clique_vid, int64_t *owner);
+
+/* Copy the device layout of the neighbourhoods into a caller device buffer of
+ * at least info.device_bytes bytes (256-byte aligned), enqueued on stream.
+ * The host object must outlive every run that uses this buffer. */
+pmrf_status pmrf_hoods_upload(const pmrf_hoods *hoods, void *d_buf, int64_t bytes, void *hip_stream);
+
+/* Replication by label (Sec. 3.2.2, "Replicate Neighborhoods By Label"), in the
+ * paper's layout: for each neighbourhood h, for each label l, its members in
+ * order; test_label = l, old_index = position in the flat neighbourhood array,
+ * hood_id = h.  Each output has L*M entries (host).  The HIP path never
+ * materialises these arrays; this call exports them for inspection. */
+pmrf_status pmrf_replicate_indices(const pmrf_hoods *hoods, int32_t L, int32_t *test_label, int64_t *old_index,
+                                   int32_t *hood_id);
+
+/* Same replication for an arbitrary flat neighbourhood array given by its
+ * offsets hood_ptr[H+1] (host). */
+pmrf_status pmrf_replicate_hood_array(int64_t H, const int64_t *hood_ptr, int32_t L, int32_t *test_label,
+                                      int64_t *old_index, int32_t *hood_id);
+
+void pmrf_hoods_free(pmrf_hoods *hoods);
+
+/* ------------------------------------------------------------------------
+ * EM optimisation (Alg. 2, EM loop; Sec. 3.2.2 "EM Parameter Estimation").
+ *
+ * Iteration t, from labels x_t and parameters theta_t = (mu_l, sigma_l):
+ *   E(h,j,l) = (y_v - mu_l)^2 / (2 sigma_l^2) + ln sigma_l
+ *              + beta * #{u in N(v), u in hood h : x_t(u) != l}
+ *     for every neighbourhood h, member v = hood_h[j], label l
+ *     (Gaussian likelihood energy plus Potts prior energy, Sec. 2.1)
+ *   m(h,j) = min_l E(h,j,l), lowest label on ties; S_h = sum_j m(h,j);
+ *   T_t = sum_h S_h                                  ("Neighborhood Energy Sums")
+ *   x_{t+1}(v) = argmin at the owner element of v    ("Update Output Labels")
+ *   theta_{t+1}: per label, mean and population standard deviation of y over
+ *   the vertices labelled l in x_{t+1} (floored at sigma_min; a label with no
+ *   vertex keeps its parameters)                     ("Update Parameters")
+ *   a neighbourhood has converged at t when |S_h^t - S_h^{t-w}| < conv_tol for
+ *   w = 1..conv_window; the total T likewise        ("MAP / EM Convergence Check")
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t L;                /* number of labels, 2..16 */
+  double beta;              /* Potts weight, finite, >= 0 */
+  int32_t max_iters;        /* EM iterations, >= 0 (the paper uses a fixed 20) */
+  int32_t conv_window;      /* convergence window, 1..8 (paper: 3) */
+  double conv_tol;          /* absolute convergence threshold, >= 0 (paper: 1e-4) */
+  int32_t early_exit;       /* 1: stop after the iteration at which every neighbourhood converged */
+  int32_t init_from_labels; /* 1: first replace (mu, sigma) by the parameter update of the starting labels */
+  double sigma_min;         /* floor of sigma, > 0 (default 1e-3) */
+  double tie_eps;           /* a label decision with energy gap below this is counted as a near tie (1e-9) */
+} pmrf_em_params;
+
+/* Fill p with the defaults: L = 2, beta = 0.5, max_iters = 20, conv_window = 3,
+ * conv_tol = 1e-4, early_exit = 0, init_from_labels = 0, sigma_min = 1e-3,
+ * tie_eps = 1e-9. */
+void pmrf_em_params_default(pmrf_em_params *p);
+
+/* counters[] layout (int64, device) */
+#define PMRF_CTR_STATUS 0      /* 0 or a device-reported PMRF_E* code */
+#define PMRF_CTR_ITERS 1       /* iterations executed */
+#define PMRF_CTR_MAP_CONV 2    /* first iteration at which every neighbourhood had converged, or -1 */
+#define PMRF_CTR_EM_CONV 3     /* first iteration at which the total T had converged, or -1 */
+#define PMRF_CTR_NEAR_TIES 4   /* near ties summed over iterations */
+#define PMRF_CTR_EVALS 5       /* energy evaluations = M * L * iterations */
+#define PMRF_NCOUNTERS 8
+
+/* Exact device workspace size for pmrf_em_run with these hoods and params. */
+pmrf_status pmrf_em_workspace_bytes(const pmrf_hoods *hoods, const pmrf_em_params *params, int64_t *bytes);
+
+/* Run params->max_iters EM iterations on one graph (device buffers, stream-ordered).
+ *  d_hoodbuf      the buffer filled by pmrf_hoods_upload for these hoods
+ *  d_y[n]         region intensities (read only)
+ *  d_labels[n]    in: starting labels x_0 in [0, L); out: labels after the last iteration
+ *  d_mu[L], d_sigma[L]  in: starting parameters; out: parameters after the last iteration
+ *  d_hood_energy[H]     out: S_h of the last iteration (NULL: not written)
+ *  d_trace[max_iters]   out: T_t per iteration (NULL: not written)
+ *  d_iter_stats[2*max_iters]  out: per iteration {near ties, neighbourhoods not converged} (NULL: not written)
+ *  d_counters[PMRF_NCOUNTERS] out: PMRF_CTR_* (required)
+ *  d_ws, ws_bytes       workspace of at least pmrf_em_workspace_bytes bytes, 256-byte aligned;
+ *                       its contents on entry do not matter
+ * Results do not depend on the launch configuration: every reduction is exact
+ * (integer fixed point) or runs in a fixed order.  Runs that share a workspace
+ * or outputs must not overlap in time. */
+pmrf_status pmrf_em_run(const pmrf_hoods *hoods, const void *d_hoodbuf, const double *d_y, int32_t *d_labels,
+                        double *d_mu, double *d_sigma, double *d_hood_energy, double *d_trace, int64_t *d_iter_stats,
+                        int64_t *d_counters, void *d_ws, int64_t ws_bytes, const pmrf_em_params *params,
+                        void *hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Batched optimisation: many graphs (for example the slices of a volume, which
+ * the paper processes one by one, Sec. 4.3.1) advanced together, one launch
+ * per EM iteration covering every graph.  Each item is exactly the argument
+ * set of pmrf_em_run; each graph's results are bitwise identical to running it
+ * alone.  Items may have different L, beta and iteration counts.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  const pmrf_hoods *hoods;
+  const void *d_hoodbuf;
+  const double *d_y;
+  int32_t *d_labels;
+  double *d_mu;
+  double *d_sigma;
+  double *d_hood_energy;
+  double *d_trace;
+  int64_t *d_iter_stats;
+  int64_t *d_counters;
+  pmrf_em_params params;
+} pmrf_em_item;
+
+pmrf_status pmrf_em_batch_workspace_bytes(int32_t B, const pmrf_em_item *items, int64_t *bytes);
+
+pmrf_status pmrf_em_batch(int32_t B, const pmrf_em_item *items, void *d_ws, int64_t ws_bytes, void *hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Launch configuration (does not change any result, only speed).
+ *  mode: 0 = automatic, 1 = one kernel launch per EM iteration (replayed as a
+ *        HIP graph), 2 = one persistent cooperative launch for all iterations
+ *  waves_per_block: 1..16 (0 = automatic)
+ *  tiles_per_wave: work packets per wave and launch in mode 1 (0 = automatic)
+ *  blocks_per_cu: resident blocks per compute unit in mode 2 (0 = automatic)
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t mode;
+  int32_t waves_per_block;
+  int32_t tiles_per_wave;
+  int32_t blocks_per_cu;
+} pmrf_launch;
+
+pmrf_status pmrf_set_launch(const pmrf_launch *launch);
+pmrf_status pmrf_get_launch(pmrf_launch *launch);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PMRF_H */

@@ -95,13 +95,20 @@ static int cmp_int(const void *x, const void *y) {
  * when nothing can extend it (P and X empty).  The outer loop starts one search
  * per vertex v with candidates = later neighbours and excluded = earlier ones,
  * which is exactly the first level of the textbook recursion in vertex order.
- * An isolated vertex is the clique {v}.
+ * An isolated vertex is the clique {v}.  A branch stops early when some
+ * excluded vertex is adjacent to every candidate: every clique the branch could
+ * report would then extend by that vertex, so none of them is maximal.
  */
 
 typedef struct { ivec members; lvec ptr; } clique_list;
 
 static void bk(const or_graph *g, int *R, int r, const int *P, int np, const int *X, int nx,
                clique_list *out) {
+  for (int i = 0; i < nx; ++i) {
+    int all = 1;
+    for (int k = 0; k < np && all; ++k) all = is_neighbor(g, X[i], P[k]);
+    if (all) return;
+  }
   if (np == 0 && nx == 0) {
     if (out->ptr.n == 0) lv_push(&out->ptr, 0);
     int *tmp = (int *)malloc((size_t)r * sizeof(int));

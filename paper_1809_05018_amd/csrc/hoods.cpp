@@ -1,0 +1,348 @@
+// Host side of the neighbourhood construction (Sec. 3.2.1 maximal cliques,
+// Sec. 3.1 and Sec. 3.2.2 "Construction of Neighborhoods": clique plus 1-ring,
+// duplicates removed, members ordered by vertex id) and the device layout the
+// EM kernels stream.
+//
+// The paper builds neighbourhoods with data-parallel primitives on the device
+// (a Map counting neighbours, a Scan, a Map writing them, then SortByKey and
+// Unique).  Here they are built once per graph on the host, outside the timed
+// EM loop, and uploaded as wave-sized work packets with one in-neighbourhood
+// adjacency bit mask per element.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+
+#include "pmrf_internal.h"
+
+using namespace pmrf;
+
+namespace {
+
+// ---------------------------------------------------------------- validation
+pmrf_status validate_csr(int32_t n, const int32_t *rp, const int32_t *ci) {
+  if (n < 0) return fail(PMRF_EINVAL, "n must be >= 0");
+  if (!rp) return fail(PMRF_EINVAL, "row_ptr is NULL");
+  if (rp[0] != 0) return fail(PMRF_EINVAL, "row_ptr[0] must be 0");
+  for (int32_t v = 0; v < n; ++v)
+    if (rp[v + 1] < rp[v]) return fail(PMRF_EINVAL, "row_ptr must be non-decreasing (row " + std::to_string(v) + ")");
+  if (rp[n] > 0 && !ci) return fail(PMRF_EINVAL, "col_idx is NULL");
+  for (int32_t v = 0; v < n; ++v) {
+    for (int32_t k = rp[v]; k < rp[v + 1]; ++k) {
+      int32_t u = ci[k];
+      if (u < 0 || u >= n) return fail(PMRF_EINVAL, "col_idx out of range in row " + std::to_string(v));
+      if (u == v) return fail(PMRF_EINVAL, "self loop at vertex " + std::to_string(v));
+      if (k > rp[v] && ci[k - 1] >= u)
+        return fail(PMRF_EINVAL, "row " + std::to_string(v) + " is not strictly ascending");
+    }
+  }
+  for (int32_t v = 0; v < n; ++v)
+    for (int32_t k = rp[v]; k < rp[v + 1]; ++k) {
+      int32_t u = ci[k];
+      if (!std::binary_search(ci + rp[u], ci + rp[u + 1], v))
+        return fail(PMRF_EINVAL, "edge " + std::to_string(v) + "-" + std::to_string(u) + " is missing its reverse");
+    }
+  return PMRF_OK;
+}
+
+// ------------------------------------------------ maximal clique enumeration
+// Bron-Kerbosch with Tomita pivoting, run from each vertex in a degeneracy
+// ordering (Eppstein, Loffler, Strash 2010): candidates are the later
+// neighbours, exclusions the earlier ones.
+struct Mce {
+  int32_t n;
+  const int32_t *rp, *ci;
+  std::vector<int32_t> out_vid;
+  std::vector<int64_t> out_ptr{0};
+  std::vector<int32_t> R;
+
+  bool adjacent(int32_t a, int32_t b) const { return std::binary_search(ci + rp[a], ci + rp[a + 1], b); }
+
+  static void intersect_row(const std::vector<int32_t> &S, const int32_t *row, int32_t len, std::vector<int32_t> &out) {
+    out.clear();
+    int32_t i = 0, j = 0, ns = (int32_t)S.size();
+    while (i < ns && j < len) {
+      if (S[i] < row[j]) ++i;
+      else if (S[i] > row[j]) ++j;
+      else { out.push_back(S[i]); ++i; ++j; }
+    }
+  }
+
+  void expand(std::vector<int32_t> &P, std::vector<int32_t> &X) {
+    if (P.empty() && X.empty()) {
+      std::vector<int32_t> c(R);
+      std::sort(c.begin(), c.end());
+      out_vid.insert(out_vid.end(), c.begin(), c.end());
+      out_ptr.push_back((int64_t)out_vid.size());
+      return;
+    }
+    // pivot: vertex of P u X with the most neighbours in P
+    int32_t pivot = -1, best = -1;
+    for (const std::vector<int32_t> *S : {&P, &X})
+      for (int32_t u : *S) {
+        int32_t cnt = 0;
+        const int32_t *row = ci + rp[u];
+        int32_t len = rp[u + 1] - rp[u];
+        int32_t i = 0, j = 0;
+        while (i < (int32_t)P.size() && j < len) {
+          if (P[i] < row[j]) ++i;
+          else if (P[i] > row[j]) ++j;
+          else { ++cnt; ++i; ++j; }
+        }
+        if (cnt > best) { best = cnt; pivot = u; }
+      }
+    std::vector<int32_t> cand;
+    for (int32_t v : P)
+      if (!adjacent(pivot, v)) cand.push_back(v);
+    std::vector<int32_t> P2, X2;
+    for (int32_t v : cand) {
+      intersect_row(P, ci + rp[v], rp[v + 1] - rp[v], P2);
+      intersect_row(X, ci + rp[v], rp[v + 1] - rp[v], X2);
+      R.push_back(v);
+      std::vector<int32_t> P3(P2), X3(X2);
+      expand(P3, X3);
+      R.pop_back();
+      P.erase(std::lower_bound(P.begin(), P.end(), v));
+      X.insert(std::lower_bound(X.begin(), X.end(), v), v);
+    }
+  }
+
+  void run() {
+    // degeneracy ordering by repeated removal of a minimum-degree vertex
+    std::vector<int32_t> deg(n), order;
+    order.reserve(n);
+    int32_t maxd = 0;
+    for (int32_t v = 0; v < n; ++v) { deg[v] = rp[v + 1] - rp[v]; maxd = std::max(maxd, deg[v]); }
+    std::vector<std::vector<int32_t>> bucket(maxd + 1);
+    for (int32_t v = 0; v < n; ++v) bucket[deg[v]].push_back(v);
+    std::vector<char> removed(n, 0);
+    int32_t d = 0;
+    for (int32_t done = 0; done < n;) {
+      d = std::max(0, d - 1);
+      while (d <= maxd && bucket[d].empty()) ++d;
+      int32_t v = bucket[d].back();
+      bucket[d].pop_back();
+      if (removed[v] || deg[v] != d) continue;  // stale bucket entry
+      removed[v] = 1;
+      order.push_back(v);
+      ++done;
+      for (int32_t k = rp[v]; k < rp[v + 1]; ++k) {
+        int32_t u = ci[k];
+        if (!removed[u]) bucket[--deg[u]].push_back(u);
+      }
+    }
+    std::vector<int32_t> pos(n);
+    for (int32_t i = 0; i < n; ++i) pos[order[i]] = i;
+    std::vector<int32_t> P, X;
+    for (int32_t v : order) {
+      P.clear();
+      X.clear();
+      for (int32_t k = rp[v]; k < rp[v + 1]; ++k) (pos[ci[k]] > pos[v] ? P : X).push_back(ci[k]);
+      R.assign(1, v);
+      expand(P, X);
+    }
+  }
+};
+
+}  // namespace
+
+// -------------------------------------------------------------------- build
+extern "C" pmrf_status pmrf_build_neighborhoods(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, int32_t k,
+                                                pmrf_hoods **out) {
+  clear_error();
+  if (!out) return fail(PMRF_EINVAL, "out is NULL");
+  if (k != 1) return fail(PMRF_EUNSUPPORTED, "only k = 1 neighbourhoods are supported");
+  pmrf_status st = validate_csr(n, row_ptr, col_idx);
+  if (st != PMRF_OK) return st;
+  pmrf_hoods *hd = nullptr;
+  try {
+    hd = new pmrf_hoods();
+    hd->n = n;
+    Mce mce{n, row_ptr, col_idx, {}, {0}, {}};
+    mce.run();
+    // canonical order: lexicographic over ascending cliques
+    int64_t H = (int64_t)mce.out_ptr.size() - 1;
+    std::vector<int64_t> idx(H);
+    for (int64_t h = 0; h < H; ++h) idx[h] = h;
+    const int32_t *cv = mce.out_vid.data();
+    const int64_t *cp = mce.out_ptr.data();
+    std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
+      return std::lexicographical_compare(cv + cp[a], cv + cp[a + 1], cv + cp[b], cv + cp[b + 1]);
+    });
+    hd->H = H;
+    hd->clique_ptr.assign(1, 0);
+    for (int64_t h = 0; h < H; ++h) {
+      int64_t a = idx[h];
+      hd->clique_vid.insert(hd->clique_vid.end(), cv + cp[a], cv + cp[a + 1]);
+      hd->clique_ptr.push_back((int64_t)hd->clique_vid.size());
+    }
+    // neighbourhood = clique u 1-ring, ascending, without repeats
+    std::vector<int64_t> stamp(n, -1);
+    hd->hood_ptr.assign(1, 0);
+    for (int64_t h = 0; h < H; ++h) {
+      size_t start = hd->hood_vid.size();
+      for (int64_t q = hd->clique_ptr[h]; q < hd->clique_ptr[h + 1]; ++q) {
+        int32_t c = hd->clique_vid[q];
+        if (stamp[c] != h) { stamp[c] = h; hd->hood_vid.push_back(c); }
+        for (int32_t e = row_ptr[c]; e < row_ptr[c + 1]; ++e) {
+          int32_t u = col_idx[e];
+          if (stamp[u] != h) { stamp[u] = h; hd->hood_vid.push_back(u); }
+        }
+      }
+      std::sort(hd->hood_vid.begin() + start, hd->hood_vid.end());
+      int64_t s = (int64_t)(hd->hood_vid.size() - start);
+      hd->max_hood = std::max<int32_t>(hd->max_hood, (int32_t)s);
+      hd->hood_ptr.push_back((int64_t)hd->hood_vid.size());
+    }
+    hd->M = (int64_t)hd->hood_vid.size();
+    if (hd->max_hood > kMaxHood) {
+      int mh = hd->max_hood;
+      delete hd;
+      return fail(PMRF_EUNSUPPORTED, "a neighbourhood has " + std::to_string(mh) + " members (limit 1024)");
+    }
+    if (hd->M >= (int64_t(1) << 31) / 2) {
+      delete hd;
+      return fail(PMRF_EUNSUPPORTED, "more than 2^30 neighbourhood elements in one graph");
+    }
+    // owner element: the vertex's place in the first clique holding it
+    hd->owner.assign(n, -1);
+    for (int64_t h = 0; h < H; ++h)
+      for (int64_t q = hd->clique_ptr[h]; q < hd->clique_ptr[h + 1]; ++q) {
+        int32_t v = hd->clique_vid[q];
+        if (hd->owner[v] >= 0) continue;
+        auto b = hd->hood_vid.begin() + hd->hood_ptr[h], e = hd->hood_vid.begin() + hd->hood_ptr[h + 1];
+        hd->owner[v] = hd->hood_ptr[h] + (std::lower_bound(b, e, v) - b);
+      }
+    // work packets and adjacency words
+    std::vector<int32_t> loc(n, -1);
+    auto open_tile = [&](uint8_t kind, uint8_t words, int64_t h) {
+      TileDesc t{};
+      t.start_mask = 0;
+      t.elem_start = (int32_t)hd->hood_ptr[h];
+      t.hood_start = (int32_t)h;
+      t.mask_start = (int32_t)hd->mask.size();
+      t.nelem = 0;
+      t.kind = kind;
+      t.words = words;
+      hd->tiles.push_back(t);
+    };
+    bool small_open = false;
+    for (int64_t h = 0; h < H; ++h) {
+      int64_t o = hd->hood_ptr[h];
+      int32_t s = (int32_t)(hd->hood_ptr[h + 1] - o);
+      uint8_t words;
+      if (s <= 32) {
+        words = 1;
+        if (!small_open || hd->tiles.back().nelem + s > kWave) { open_tile(kSmall, 1, h); small_open = true; }
+        TileDesc &t = hd->tiles.back();
+        t.start_mask |= uint64_t(1) << t.nelem;
+        t.nelem = (int16_t)(t.nelem + s);
+      } else {
+        small_open = false;
+        words = (uint8_t)((s + 31) / 32);
+        open_tile(s <= 64 ? kMid : kLarge, words, h);
+        hd->tiles.back().start_mask = 1;
+        hd->tiles.back().nelem = (int16_t)s;
+      }
+      for (int32_t j = 0; j < s; ++j) loc[hd->hood_vid[o + j]] = j;
+      size_t base = hd->mask.size();
+      hd->mask.resize(base + (size_t)s * words, 0u);
+      for (int32_t j = 0; j < s; ++j) {
+        int32_t v = hd->hood_vid[o + j];
+        uint32_t *w = hd->mask.data() + base + (size_t)j * words;
+        for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+          int32_t p = loc[col_idx[e]];
+          if (p >= 0) { w[p >> 5] |= 1u << (p & 31); hd->A++; }
+        }
+        if (hd->owner[v] == o + j) w[j >> 5] |= 1u << (j & 31);
+      }
+      for (int32_t j = 0; j < s; ++j) loc[hd->hood_vid[o + j]] = -1;
+    }
+    DeviceLayout &L = hd->layout;
+    L.tiles_off = 0;
+    L.vid_off = align_up((int64_t)hd->tiles.size() * (int64_t)sizeof(TileDesc), 256);
+    L.mask_off = L.vid_off + align_up(hd->M * 4, 256);
+    L.total = L.mask_off + align_up((int64_t)hd->mask.size() * 4, 256);
+    if (L.total == 0) L.total = 256;
+  } catch (const std::bad_alloc &) {
+    delete hd;
+    return fail(PMRF_ENOMEM, "host allocation failed while building neighbourhoods");
+  }
+  *out = hd;
+  return PMRF_OK;
+}
+
+extern "C" pmrf_status pmrf_hoods_get_info(const pmrf_hoods *h, pmrf_hoods_info *info) {
+  clear_error();
+  if (!h || !info) return fail(PMRF_EINVAL, "NULL argument");
+  info->n = h->n;
+  info->H = h->H;
+  info->M = h->M;
+  info->A = h->A;
+  info->max_hood = h->max_hood;
+  info->tiles = (int64_t)h->tiles.size();
+  info->device_bytes = h->layout.total;
+  return PMRF_OK;
+}
+
+extern "C" pmrf_status pmrf_hoods_export(const pmrf_hoods *h, int64_t *hood_ptr, int32_t *hood_vid,
+                                         int64_t *clique_ptr, int32_t *clique_vid, int64_t *owner) {
+  clear_error();
+  if (!h) return fail(PMRF_EINVAL, "hoods is NULL");
+  if (hood_ptr) std::memcpy(hood_ptr, h->hood_ptr.data(), h->hood_ptr.size() * sizeof(int64_t));
+  if (hood_vid && h->M) std::memcpy(hood_vid, h->hood_vid.data(), (size_t)h->M * sizeof(int32_t));
+  if (clique_ptr) std::memcpy(clique_ptr, h->clique_ptr.data(), h->clique_ptr.size() * sizeof(int64_t));
+  if (clique_vid && !h->clique_vid.empty())
+    std::memcpy(clique_vid, h->clique_vid.data(), h->clique_vid.size() * sizeof(int32_t));
+  if (owner && h->n) std::memcpy(owner, h->owner.data(), (size_t)h->n * sizeof(int64_t));
+  return PMRF_OK;
+}
+
+extern "C" pmrf_status pmrf_hoods_upload(const pmrf_hoods *h, void *d_buf, int64_t bytes, void *stream) {
+  clear_error();
+  if (!h || !d_buf) return fail(PMRF_EINVAL, "NULL argument");
+  if (bytes < h->layout.total) return fail(PMRF_ENOMEM, "device buffer smaller than info.device_bytes");
+  if (reinterpret_cast<uintptr_t>(d_buf) % 256) return fail(PMRF_EINVAL, "device buffer must be 256-byte aligned");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char *base = static_cast<char *>(d_buf);
+  hipError_t e = hipSuccess;
+  if (!h->tiles.empty())
+    e = hipMemcpyAsync(base + h->layout.tiles_off, h->tiles.data(), h->tiles.size() * sizeof(TileDesc),
+                       hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && h->M)
+    e = hipMemcpyAsync(base + h->layout.vid_off, h->hood_vid.data(), (size_t)h->M * 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && !h->mask.empty())
+    e = hipMemcpyAsync(base + h->layout.mask_off, h->mask.data(), h->mask.size() * 4, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return fail(PMRF_EDEVICE, std::string("hipMemcpyAsync: ") + hipGetErrorString(e));
+  return PMRF_OK;
+}
+
+extern "C" pmrf_status pmrf_replicate_hood_array(int64_t H, const int64_t *hood_ptr, int32_t L, int32_t *test_label,
+                                                 int64_t *old_index, int32_t *hood_id) {
+  clear_error();
+  if (H < 0 || !hood_ptr || !test_label || !old_index || !hood_id) return fail(PMRF_EINVAL, "NULL argument");
+  if (L < 1) return fail(PMRF_EINVAL, "L must be >= 1");
+  int64_t k = 0;
+  for (int64_t h = 0; h < H; ++h) {
+    int64_t s = hood_ptr[h + 1] - hood_ptr[h];
+    for (int32_t l = 0; l < L; ++l)
+      for (int64_t j = 0; j < s; ++j, ++k) {
+        test_label[k] = l;
+        old_index[k] = hood_ptr[h] + j;
+        hood_id[k] = (int32_t)h;
+      }
+  }
+  return PMRF_OK;
+}
+
+extern "C" pmrf_status pmrf_replicate_indices(const pmrf_hoods *h, int32_t L, int32_t *test_label, int64_t *old_index,
+                                              int32_t *hood_id) {
+  if (!h) {
+    clear_error();
+    return fail(PMRF_EINVAL, "hoods is NULL");
+  }
+  return pmrf_replicate_hood_array(h->H, h->hood_ptr.data(), L, test_label, old_index, hood_id);
+}
+
+extern "C" void pmrf_hoods_free(pmrf_hoods *h) { delete h; }

@@ -1,0 +1,67 @@
+// Internal data layout shared by the host builder and the HIP kernels.
+#pragma once
+
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/pmrf.h"
+
+namespace pmrf {
+
+constexpr int kWave = 64;
+constexpr int kMaxLabels = 16;
+constexpr int kMaxHood = 1024;
+constexpr int kMaxWindow = 8;
+
+// Work packet kinds.  A SMALL tile packs whole neighbourhoods of at most 32
+// members into the 64 lanes of one wave (one 32-bit adjacency word per
+// element); a MID tile holds one neighbourhood of 33..64 members (two words);
+// a LARGE tile holds one neighbourhood of 65..1024 members processed in
+// 64-element chunks (ceil(s/32) words per element).
+enum TileKind : uint8_t { kSmall = 0, kMid = 1, kLarge = 2 };
+
+// One wave-sized work packet.  Elements of the packet are contiguous in the
+// element arrays; neighbourhoods inside it are consecutive in canonical order.
+struct TileDesc {
+  uint64_t start_mask;  // bit i set: lane i starts a neighbourhood (SMALL/MID); 1 for LARGE
+  int32_t elem_start;   // first element
+  int32_t hood_start;   // canonical id of the first neighbourhood
+  int32_t mask_start;   // first adjacency word
+  int16_t nelem;        // elements in the packet (<= 64, or the neighbourhood size for LARGE)
+  uint8_t kind;         // TileKind
+  uint8_t words;        // adjacency words per element
+};
+static_assert(sizeof(TileDesc) == 24, "TileDesc layout");
+
+// Offsets (bytes) of the arrays inside the uploaded device buffer.
+struct DeviceLayout {
+  int64_t tiles_off, vid_off, mask_off, total;
+};
+
+inline int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace pmrf
+
+// Host object behind the opaque pmrf_hoods handle.
+struct pmrf_hoods {
+  int32_t n = 0;
+  int64_t H = 0, M = 0, A = 0;
+  int32_t max_hood = 0;
+  std::vector<int64_t> clique_ptr;
+  std::vector<int32_t> clique_vid;
+  std::vector<int64_t> hood_ptr;
+  std::vector<int32_t> hood_vid;
+  std::vector<int64_t> owner;  // element owning each vertex
+  // device layout, built once
+  std::vector<pmrf::TileDesc> tiles;
+  std::vector<uint32_t> mask;  // adjacency words (bit j' = in-hood neighbour j'; own bit = owner flag)
+  pmrf::DeviceLayout layout{};
+};
+
+namespace pmrf {
+// error state (abi.cpp)
+pmrf_status fail(pmrf_status code, const std::string &msg);
+void clear_error();
+}  // namespace pmrf

@@ -8,3 +8,14 @@ if ROOT not in sys.path:
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (HIP device) and the built HIP library")
+
+
+import pytest  # noqa: E402
+
+
+@pytest.fixture(autouse=True)
+def _announce_gpu_case(request):
+    """Name each GPU case on stdout before it touches the device."""
+    if request.node.get_closest_marker("gpu"):
+        print(f"\n[gpu-case] {request.node.nodeid}", flush=True)
+    yield

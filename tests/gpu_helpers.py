@@ -1,0 +1,99 @@
+"""Shared helpers of the GPU parity tests: run both sides on the same inputs and
+compare them to the stated bar (labels bit-exact outside near ties, FP64
+quantities within 1e-10 relative)."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+from paper_1809_05018_amd import pmrf, synth
+
+REL = 1e-10
+TIE = 1e-9
+
+
+def rel_err(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    if a.size == 0:
+        return 0.0
+    den = np.maximum(np.maximum(np.abs(a), np.abs(b)), 1e-300)
+    return float(np.max(np.abs(a - b) / den))
+
+
+def assert_close(a, b, what, rel=REL):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    assert a.shape == b.shape, (what, a.shape, b.shape)
+    e = rel_err(a, b)
+    assert e <= rel, f"{what}: max relative error {e:.3e} > {rel:.0e}"
+
+
+def owner_gaps(og: oracle.OracleGraph, y, L, beta, x, mu, sigma):
+    out = og.em_step(y, L, beta, x, mu, sigma, per_element=True)
+    return out, out["gap"][og.owner()]
+
+
+def init_state(g: synth.GraphInput, L):
+    """Threshold labels and their parameter update (from the oracle)."""
+    x0 = synth.threshold_labels(g.y, L)
+    mu0, s0 = oracle.mstep(g.y, L, x0, np.linspace(40, 220, L), np.full(L, 20.0))
+    return x0, mu0, s0
+
+
+def gpu_run(prob: pmrf.Problem, x, mu, sigma, **kw):
+    params = pmrf.pmrf_em_params(L=prob.L, **kw)
+    prob.set_state(x, mu, sigma)
+    prob.run(params)
+    return prob.results(params)
+
+
+def compare_runs(gpu, ref, what, check_labels=True):
+    assert gpu["status"] == 0, f"{what}: device status {gpu['status']}"
+    assert gpu["iters"] == ref["iters"], (what, gpu["iters"], ref["iters"])
+    if check_labels:
+        assert np.array_equal(gpu["x"], ref["x"]), f"{what}: labels differ at {np.flatnonzero(gpu['x'] != ref['x'])[:10]}"
+    assert_close(gpu["mu"], ref["mu"], what + " mu")
+    assert_close(gpu["sigma"], ref["sigma"], what + " sigma")
+    assert_close(gpu["trace"], ref["trace"], what + " trace")
+    if ref["iters"] > 0:
+        assert_close(gpu["S"], ref["S"], what + " S_h")
+    assert np.array_equal(gpu["near_ties"], ref["near_ties"]), what
+    assert np.array_equal(gpu["nonconv"], ref["nonconv"]), what
+    assert gpu["map_conv_iter"] == ref["map_conv_iter"], what
+    assert gpu["em_conv_iter"] == ref["em_conv_iter"], what
+    assert gpu["total_near_ties"] == ref["total_near_ties"], what
+
+
+def end_to_end(g: synth.GraphInput, L, beta, iters, what, device="cuda", **kw):
+    """Same start on both sides, ``iters`` iterations each, full comparison."""
+    x0, mu0, s0 = init_state(g, L)
+    og = oracle.OracleGraph(g.n, g.row_ptr, g.col_idx)
+    ref = og.em_run(g.y, L, beta, x0, mu0, s0, iters, **kw)
+    prob = pmrf.Problem(g.n, g.row_ptr, g.col_idx, g.y, L, device)
+    gpu = gpu_run(prob, x0, mu0, s0, beta=beta, max_iters=iters, **kw)
+    compare_runs(gpu, ref, what, check_labels=ref["total_near_ties"] == 0)
+    return gpu, ref
+
+
+def lockstep(g: synth.GraphInput, L, beta, iters, what, device="cuda"):
+    """Feed both sides the GPU's state each iteration; compare one step."""
+    x, mu, s = init_state(g, L)
+    og = oracle.OracleGraph(g.n, g.row_ptr, g.col_idx)
+    prob = pmrf.Problem(g.n, g.row_ptr, g.col_idx, g.y, L, device)
+    ties_seen = 0
+    for t in range(iters):
+        ref, gaps = owner_gaps(og, g.y, L, beta, x, mu, s)
+        gpu = gpu_run(prob, x, mu, s, beta=beta, max_iters=1)
+        assert gpu["status"] == 0
+        clear = gaps >= TIE
+        ties_seen += int((~clear).sum())
+        assert np.array_equal(gpu["x"][clear], ref["x"][clear]), f"{what} t={t}: labels differ"
+        assert gpu["near_ties"][0] == ref["near_ties"], (what, t)
+        assert_close(gpu["S"], ref["S"], f"{what} t={t} S_h")
+        assert_close(gpu["trace"], [ref["T"]], f"{what} t={t} T")
+        if (~clear).sum() == 0:
+            assert_close(gpu["mu"], ref["mu"], f"{what} t={t} mu")
+            assert_close(gpu["sigma"], ref["sigma"], f"{what} t={t} sigma")
+        x, mu, s = gpu["x"], gpu["mu"], gpu["sigma"]
+    return ties_seen

@@ -1,0 +1,147 @@
+"""HIP path against the oracle, through the C ABI (needs the GPU)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1809_05018_amd import pmrf, synth
+from tests import pins
+from tests.gpu_helpers import (assert_close, compare_runs, end_to_end, gpu_run, init_state, lockstep)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def device():
+    assert torch.cuda.is_available(), "gpu tests need a HIP device"
+    return "cuda"
+
+
+def test_lockstep_small():
+    g = synth.workload_small()
+    lockstep(g, 2, 0.5, 20, "slice256_1k")
+
+
+def test_lockstep_multilabel_powerlaw():
+    g = synth.powerlaw_graph(4242, 6000, phases=4, dmax=45)
+    lockstep(g, 4, 0.8, 6, "powerlaw6k_L4")
+
+
+def test_end_to_end_small():
+    end_to_end(synth.workload_small(), 2, 0.5, 20, "slice256_1k")
+
+
+def test_end_to_end_large():
+    gpu, ref = end_to_end(synth.workload_large(), 2, 0.5, 30, "slice2048_100k")
+    assert gpu["evals"] == 30 * 2 * pmrf.pmrf_build_neighborhoods(
+        synth.workload_large().n, synth.workload_large().row_ptr, synth.workload_large().col_idx).M
+
+
+def test_end_to_end_three_phase():
+    end_to_end(synth.image_graph(77, 512, 5000, 3), 3, 0.5, 15, "slice512_5k_L3")
+
+
+def test_end_to_end_large_hoods():
+    # degrees up to 80 give neighbourhoods above 64 members (multi-chunk packets)
+    g = synth.powerlaw_graph(99, 20000, phases=4, dmax=80, exponent=2.0)
+    h = pmrf.pmrf_build_neighborhoods(g.n, g.row_ptr, g.col_idx)
+    assert h.max_hood > 64
+    end_to_end(g, 4, 0.8, 8, "powerlaw20k_dmax80")
+
+
+@pytest.mark.parametrize("L", [5, 8, 16])
+def test_end_to_end_many_labels(L):
+    g = synth.image_graph(31 + L, 256, 1500, 4)
+    end_to_end(g, L, 0.3, 6, f"slice256_L{L}")
+
+
+def test_beta_zero_and_early_exit():
+    g = synth.workload_small()
+    end_to_end(g, 2, 0.0, 20, "beta0")
+    gpu, ref = end_to_end(g, 2, 0.0, 20, "beta0_early", early_exit=True)
+    assert ref["iters"] < 20
+
+
+def test_init_from_labels():
+    g = synth.workload_small()
+    x0 = synth.threshold_labels(g.y, 2)
+    og = oracle.OracleGraph(g.n, g.row_ptr, g.col_idx)
+    ref = og.em_run(g.y, 2, 0.5, x0, [1.0, 2.0], [3.0, 4.0], 5, init_from_labels=True)
+    prob = pmrf.Problem(g.n, g.row_ptr, g.col_idx, g.y, 2)
+    gpu = gpu_run(prob, x0, [1.0, 2.0], [3.0, 4.0], beta=0.5, max_iters=5, init_from_labels=True)
+    compare_runs(gpu, ref, "init_from_labels")
+    # zero iterations: only the starting update runs
+    ref0 = og.em_run(g.y, 2, 0.5, x0, [1.0, 2.0], [3.0, 4.0], 0, init_from_labels=True)
+    gpu0 = gpu_run(prob, x0, [1.0, 2.0], [3.0, 4.0], beta=0.5, max_iters=0, init_from_labels=True)
+    assert gpu0["iters"] == 0 and np.array_equal(gpu0["x"], x0)
+    assert_close(gpu0["mu"], ref0["mu"], "init mu")
+    assert_close(gpu0["sigma"], ref0["sigma"], "init sigma")
+
+
+@pytest.mark.parametrize("case", ["single", "isolated", "clique40", "star101", "path", "empty"])
+def test_edge_graphs(case):
+    rng = np.random.default_rng(5)
+    if case == "single":
+        n, (rp, ci) = 1, pins.csr(1, [])
+    elif case == "isolated":
+        n, (rp, ci) = 7, pins.csr(7, [])
+    elif case == "clique40":
+        n, (rp, ci) = 40, pins.csr(40, [(a, b) for a in range(40) for b in range(a + 1, 40)])
+    elif case == "star101":
+        n, (rp, ci) = 101, pins.csr(101, [(0, i) for i in range(1, 101)])
+    elif case == "path":
+        n, (rp, ci) = 300, pins.csr(300, [(i, i + 1) for i in range(299)])
+    else:
+        n, (rp, ci) = 0, (np.zeros(1, np.int32), np.zeros(0, np.int32))
+    y = rng.uniform(0, 255, n)
+    g = synth.GraphInput(n=n, row_ptr=rp, col_idx=ci, y=y, name=case)
+    if n == 0:
+        prob = pmrf.Problem(0, rp, ci, y, 2)
+        out = gpu_run(prob, np.zeros(0, np.int32), [50.0, 150.0], [20.0, 20.0], beta=0.5, max_iters=3)
+        assert out["status"] == 0 and out["iters"] == 3 and out["trace"].tolist() == [0.0, 0.0, 0.0]
+        return
+    end_to_end(g, 2, 0.7, 6, case)
+
+
+def test_device_reported_errors():
+    g = synth.workload_small()
+    prob = pmrf.Problem(g.n, g.row_ptr, g.col_idx, g.y, 2)
+    x = synth.threshold_labels(g.y, 2)
+    x[17] = 2
+    out = gpu_run(prob, x, [80.0, 170.0], [20.0, 20.0], max_iters=3)
+    assert out["status"] == pmrf.PMRF_EBADLABEL and out["iters"] == 0
+    x[17] = 0
+    out = gpu_run(prob, x, [80.0, 170.0], [20.0, 0.0], max_iters=3)
+    assert out["status"] == pmrf.PMRF_EBADPARAM
+    out = gpu_run(prob, x, [80.0, 170.0], [20.0, 20.0], max_iters=3)  # the same buffers recover
+    assert out["status"] == 0 and out["iters"] == 3
+
+
+def test_determinism_and_launch_shape_invariance():
+    g = synth.image_graph(8, 1024, 25000, 2)
+    x0, mu0, s0 = init_state(g, 2)
+    prob = pmrf.Problem(g.n, g.row_ptr, g.col_idx, g.y, 2)
+    old = pmrf.pmrf_get_launch()
+    outs = []
+    try:
+        for shape in [(1, 0, 0, 0), (1, 0, 0, 0), (1, 1, 1, 0), (1, 16, 2, 0), (1, 8, 64, 0), (1, 2, 5, 0)]:
+            pmrf.pmrf_set_launch(*shape)
+            outs.append(gpu_run(prob, x0, mu0, s0, beta=0.5, max_iters=12))
+    finally:
+        pmrf.pmrf_set_launch(**old)
+    for o in outs[1:]:
+        for k in ("x", "mu", "sigma", "S", "trace", "near_ties", "nonconv"):
+            assert np.array_equal(o[k], outs[0][k]), k
+
+
+def test_resume_equals_uninterrupted():
+    g = synth.workload_small()
+    x0, mu0, s0 = init_state(g, 2)
+    prob = pmrf.Problem(g.n, g.row_ptr, g.col_idx, g.y, 2)
+    full = gpu_run(prob, x0, mu0, s0, beta=0.5, max_iters=30)
+    a = gpu_run(prob, x0, mu0, s0, beta=0.5, max_iters=15)
+    b = gpu_run(prob, a["x"], a["mu"], a["sigma"], beta=0.5, max_iters=15)
+    assert np.array_equal(b["x"], full["x"])
+    assert np.array_equal(b["mu"], full["mu"]) and np.array_equal(b["sigma"], full["sigma"])
+    assert np.array_equal(np.concatenate([a["trace"], b["trace"]]), full["trace"])
+    assert np.array_equal(b["S"], full["S"])

@@ -1,0 +1,165 @@
+"""Host side of libpmrf on the CPU: exports, neighbourhood builder, validation.
+
+No device call is made here; the HIP path itself is covered by the gpu tests.
+The library's neighbourhood builder (its own Bron-Kerbosch with pivoting) is
+compared with the oracle's independent construction, element by element."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1809_05018_amd import pmrf, synth
+from tests import pins
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "pmrf.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pmrf_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol():
+    names = declared_symbols()
+    assert len(names) >= 16
+    lib = ctypes.CDLL(pmrf.LIB_PATH)
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(pmrf.EXPORTED)
+    assert pmrf.lib.pmrf_abi_version() == 1
+
+
+def compare_with_oracle(n, rp, ci):
+    h = pmrf.pmrf_build_neighborhoods(n, rp, ci)
+    og = oracle.OracleGraph(n, rp, ci)
+    ex = h.export()
+    ocp, ocv = og.cliques()
+    ohp, ohv = og.hoods()
+    assert (h.n, h.H, h.M, h.A, h.max_hood) == (og.n, og.H, og.M, og.A, og.max_hood)
+    assert np.array_equal(ex["clique_ptr"], ocp) and np.array_equal(ex["clique_vid"], ocv)
+    assert np.array_equal(ex["hood_ptr"], ohp) and np.array_equal(ex["hood_vid"], ohv)
+    assert np.array_equal(ex["owner"], og.owner())
+    return h
+
+
+def test_builder_matches_oracle_small_graphs():
+    for n, rp, ci in pins.random_small_graphs(count=80):
+        compare_with_oracle(n, rp, ci)
+
+
+def test_builder_matches_oracle_workloads():
+    g = synth.workload_small()
+    h = compare_with_oracle(g.n, g.row_ptr, g.col_idx)
+    assert h.max_hood <= 32 and h.tiles * 64 >= h.M
+    p = synth.powerlaw_graph(41, 4000, phases=4, dmax=60)
+    h = compare_with_oracle(p.n, p.row_ptr, p.col_idx)
+    assert h.max_hood > 64  # exercises the multi-chunk packet layout
+
+
+def test_builder_edge_cases():
+    h = pmrf.pmrf_build_neighborhoods(0, np.zeros(1, np.int32), np.zeros(0, np.int32))
+    assert (h.n, h.H, h.M) == (0, 0, 0) and h.device_bytes >= 256
+    rp, ci = pins.csr(5, [])
+    h = compare_with_oracle(5, rp, ci)
+    assert h.H == 5 and h.M == 5
+    rp, ci = pins.csr(40, [(a, b) for a in range(40) for b in range(a + 1, 40)])  # K_40: one hood of 40
+    h = compare_with_oracle(40, rp, ci)
+    assert h.H == 1 and h.max_hood == 40
+    rp, ci = pins.csr(101, [(0, i) for i in range(1, 101)])  # star: 100 hoods of 101
+    h = compare_with_oracle(101, rp, ci)
+    assert h.max_hood == 101
+
+
+def test_neighbourhood_limit():
+    rp, ci = pins.csr(1100, [(0, i) for i in range(1, 1100)])
+    with pytest.raises(pmrf.PmrfError) as e:
+        pmrf.pmrf_build_neighborhoods(1100, rp, ci)
+    assert e.value.code == pmrf.PMRF_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("case", ["asym", "selfloop", "unsorted", "range", "rowptr", "k2"])
+def test_validation_errors(case):
+    rp, ci = pins.csr(4, [(0, 1), (1, 2), (2, 3)])
+    rp, ci = rp.copy(), ci.copy()
+    k = 1
+    if case == "asym":
+        ci = np.array([1, 0, 2, 1, 3, 3], np.int32)  # row 3 lists 3? use asymmetric: 2->3 without 3->2
+        rp = np.array([0, 1, 3, 5, 5], np.int32)
+        ci = np.array([1, 0, 2, 1, 3], np.int32)
+    elif case == "selfloop":
+        ci[0] = 0
+    elif case == "unsorted":
+        ci[1], ci[2] = ci[2], ci[1]
+    elif case == "range":
+        ci[-1] = 7
+    elif case == "rowptr":
+        rp[2] = rp[1] - 1
+    elif case == "k2":
+        k = 2
+    with pytest.raises(pmrf.PmrfError) as e:
+        pmrf.pmrf_build_neighborhoods(4, rp, ci, k)
+    assert e.value.code in (pmrf.PMRF_EINVAL, pmrf.PMRF_EUNSUPPORTED)
+    assert pmrf.lib.pmrf_last_error().decode()
+
+
+def test_replicate_worked_example():
+    g = pins.read_golden("replicate_worked_example.txt")
+    tl, oi, hi = pmrf.pmrf_replicate_hood_array(g["hood_ptr"].astype(np.int64), int(g["L"][0]))
+    assert np.array_equal(tl, g["testLabel"].astype(int))
+    assert np.array_equal(oi, g["oldIndex"].astype(int))
+    assert np.array_equal(hi, g["hoodId"].astype(int))
+
+
+def test_replicate_indices_match_oracle():
+    g = synth.workload_small()
+    h = pmrf.pmrf_build_neighborhoods(g.n, g.row_ptr, g.col_idx)
+    for L in (2, 3):
+        tl, oi, hi = h.replicate(L)
+        otl, ooi, ohi = oracle.replicate(h.export()["hood_ptr"], L)
+        assert np.array_equal(tl, otl) and np.array_equal(oi, ooi) and np.array_equal(hi, ohi)
+
+
+def test_params_and_workspace():
+    g = synth.workload_small()
+    h = pmrf.pmrf_build_neighborhoods(g.n, g.row_ptr, g.col_idx)
+    p = pmrf.pmrf_em_params()
+    assert (p.L, p.beta, p.max_iters, p.conv_window, p.conv_tol, p.sigma_min, p.tie_eps) == (
+        2, 0.5, 20, 3, 1e-4, 1e-3, 1e-9)
+    b = pmrf.pmrf_em_workspace_bytes(h, p)
+    assert b % 256 == 0 and b >= 4 * g.n + 8 * 4 * h.H
+    p2 = pmrf.pmrf_em_params(max_iters=40)
+    assert pmrf.pmrf_em_workspace_bytes(h, p2) >= b
+    for bad in (dict(L=1), dict(L=17), dict(beta=-1.0), dict(max_iters=-1), dict(conv_window=0),
+                dict(conv_window=9), dict(sigma_min=0.0), dict(tie_eps=-1.0)):
+        with pytest.raises(pmrf.PmrfError) as e:
+            pmrf.pmrf_em_workspace_bytes(h, pmrf.pmrf_em_params(**bad))
+        assert e.value.code in (pmrf.PMRF_EINVAL, pmrf.PMRF_EUNSUPPORTED)
+
+
+def test_run_rejects_bad_host_arguments_without_device():
+    g = synth.workload_small()
+    h = pmrf.pmrf_build_neighborhoods(g.n, g.row_ptr, g.col_idx)
+    p = pmrf.pmrf_em_params()
+    # NULL required buffers are rejected on the host before anything is enqueued
+    rc = pmrf.lib.pmrf_em_run(h.handle, None, None, None, None, None, None, None, None, None, None, 0,
+                              ctypes.byref(p), None)
+    assert rc == pmrf.PMRF_EINVAL
+    rc = pmrf.lib.pmrf_em_batch(0, None, None, 0, None)
+    assert rc == pmrf.PMRF_EINVAL
+
+
+def test_launch_config_roundtrip():
+    old = pmrf.pmrf_get_launch()
+    try:
+        pmrf.pmrf_set_launch(1, 8, 4, 2)
+        assert pmrf.pmrf_get_launch() == {"mode": 1, "waves_per_block": 8, "tiles_per_wave": 4, "blocks_per_cu": 2}
+        with pytest.raises(pmrf.PmrfError):
+            pmrf.pmrf_set_launch(3, 0, 0, 0)
+        with pytest.raises(pmrf.PmrfError):
+            pmrf.pmrf_set_launch(0, 17, 0, 0)
+    finally:
+        pmrf.pmrf_set_launch(**old)

@@ -34,7 +34,8 @@ MUTANTS = {
     "conv_window_short": ("for (int w = 1; w <= W; ++w)", "for (int w = 1; w < W; ++w)"),
     "replicate_label_major": ("for (int h = 0; h < H; ++h)\n    for (int l = 0; l < L; ++l)",
                               "for (int l = 0; l < L; ++l)\n    for (int h = 0; h < H; ++h)"),
-    "clique_not_maximal": ("if (np == 0 && nx == 0) {", "if (np == 0) {"),
+    "clique_not_maximal": ("if (np == 0 && nx == 0) {", "if (nx == 0) {"),
+    "clique_no_exclusion": ("    Xl[xn++] = u;\n", "\n"),
     "gap_sign": ("gap_elem[e] = second - m;", "gap_elem[e] = second + m;"),
     "mstep_old_labels": ("return or_mstep(g->n, y, L, x_out,", "return or_mstep(g->n, y, L, x_in,"),
 }
