@@ -208,12 +208,17 @@ pmrf_status pmrf_em_batch_workspace_bytes(int32_t B, const pmrf_em_item *items, 
 pmrf_status pmrf_em_batch(int32_t B, const pmrf_em_item *items, void *d_ws, int64_t ws_bytes, void *hip_stream);
 
 /* ------------------------------------------------------------------------
- * Launch configuration (does not change any result, only speed).
- *  mode: 0 = automatic, 1 = one kernel launch per EM iteration (replayed as a
- *        HIP graph), 2 = one persistent cooperative launch for all iterations
- *  waves_per_block: 1..16 (0 = automatic)
- *  tiles_per_wave: work packets per wave and launch in mode 1 (0 = automatic)
- *  blocks_per_cu: resident blocks per compute unit in mode 2 (0 = automatic)
+ * Launch configuration (does not change any result, only speed: every
+ * reduction order is fixed by the graph, not by the launch shape).
+ *  mode: 0 = automatic (currently 1); 1 = the run's kernels are captured once
+ *        per distinct argument set into a HIP graph (kept in a small cache) and
+ *        the graph is replayed on the caller's stream; 2 = reserved for a
+ *        persistent launch (PMRF_EUNSUPPORTED in this build); 3 = direct
+ *        launches on the caller's stream.  While kernel timing is on
+ *        (pmrf_profile_begin), runs use direct launches.
+ *  waves_per_block: 1..16 (0 = automatic: 4)
+ *  tiles_per_wave: chunks of 8 work packets per wave and launch (0 = automatic: 1)
+ *  blocks_per_cu: reserved (0)
  * ------------------------------------------------------------------------ */
 typedef struct {
   int32_t mode;
@@ -224,6 +229,18 @@ typedef struct {
 
 pmrf_status pmrf_set_launch(const pmrf_launch *launch);
 pmrf_status pmrf_get_launch(pmrf_launch *launch);
+
+/* ------------------------------------------------------------------------
+ * Kernel timing for measurement.  Between pmrf_profile_begin and
+ * pmrf_profile_end every EM-iteration launch (the energy / argmin / sum /
+ * label / statistics kernel) made by this process is bracketed by a pair of
+ * HIP events recorded on the launch's stream.  pmrf_profile_end waits for the
+ * last recorded event and returns the summed event-to-event time in
+ * milliseconds and the number of bracketed launches.  Timing does not change
+ * any result.  Not thread safe: one measuring thread at a time.
+ * ------------------------------------------------------------------------ */
+pmrf_status pmrf_profile_begin(void);
+pmrf_status pmrf_profile_end(double *total_ms, int64_t *launches);
 
 #ifdef __cplusplus
 }

@@ -1,31 +1,44 @@
 // EM optimisation of DPP-PMRF on gfx950 (Alg. 2, EM loop; Sec. 3.2.2 "EM
 // Parameter Estimation").
 //
-// One launch per EM iteration.  Each wave takes 64-lane work packets of whole
-// neighbourhoods and, per element (neighbourhood h, member v, every label l):
-//   - gathers y_v and the current labels of the packet (label bit planes from
+// Each EM iteration is two launches.
+//
+// k_iter works through chunks of 8 consecutive work packets (a packet is up to
+// 64 elements of whole neighbourhoods).  For every packet, one lane per element
+// (neighbourhood h, member v) does, for every label l:
+//   - gather y_v and the current labels of the packet (label bit planes from
 //     __ballot, so every lane sees its neighbourhood's labels without LDS);
-//   - counts in-neighbourhood neighbours per label with popcounts of its
+//   - count in-neighbourhood neighbours per label with popcounts of its
 //     adjacency bit mask against the planes (the Potts term);
-//   - forms the Gaussian energy for each label, keeps the minimum, the lowest
-//     arg-minimum and the gap to the runner-up (the paper's SortByKey +
-//     ReduceByKey<Min>, done in registers: no replicated arrays exist);
-//   - sums the minima of each neighbourhood in member order through LDS (the
-//     paper's ReduceByKey<Add>) and checks the neighbourhood's convergence
-//     window;
+//   - form the Gaussian energy and keep the minimum, the lowest arg-minimum and
+//     the gap to the runner-up (the paper's SortByKey + ReduceByKey<Min>, in
+//     registers: no replicated arrays exist);
 //   - the owner element of each vertex writes the vertex's new label (the
-//     paper's Scatter, without write conflicts) and adds its intensity to the
-//     per-label statistics of the parameter update.
-// Every cross-lane and cross-block sum of the M-step and of the total energy is
-// an integer sum of fixed-point limbs, so the result is independent of the
-// launch shape and of how graphs are batched.  The last block of a graph to
-// finish turns the sums into the next parameters (mean, standard deviation)
-// and the per-iteration records.
+//     paper's Scatter, without write conflicts) and adds y - mu to its lane's
+//     per-label statistics of the parameter update;
+//   - the minimum goes to LDS.
+// After up to 8 packets, one lane per neighbourhood sums its members' minima in
+// member order (the paper's ReduceByKey<Add>), checks the neighbourhood's
+// convergence window and adds the sum to its lane's energy total.  At the end
+// of a chunk the wave reduces its lanes' statistics with a fixed butterfly and
+// stores one record for the chunk.  There is no cross-block communication and
+// no memory fence inside the launch.
+//
+// k_fin_iter (one block per graph) adds the chunk records in a fixed order and
+// turns them into the next parameters (mean, standard deviation) and the
+// per-iteration records.
+//
+// Chunks and their order are fixed by the graph alone, so the results do not
+// depend on the launch shape or on how graphs are batched.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
+#include <list>
+#include <map>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "pmrf_internal.h"
@@ -34,24 +47,32 @@ using namespace pmrf;
 
 namespace {
 
+// Pointers read from descriptors carry no address space; casting them to the
+// global space keeps loads and stores off the flat path (whose waits would
+// also stall LDS traffic).
+template <typename T>
+using gptr = __attribute__((address_space(1))) T *;
+template <typename T>
+__device__ __forceinline__ gptr<T> gbl(T *p) {
+  return (gptr<T>)p;
+}
+
 // ------------------------------------------------------------ device records
-// accumulator words of one graph (int64):
-//   per label l: [9l] count, [9l+1 .. 9l+4] sum of (y - c_l) limbs,
-//                [9l+5 .. 9l+8] sum of (y - c_l)^2 limbs   (c_l = current mean)
-//   [9L .. 9L+3] total energy limbs, [9L+4] near ties, [9L+5] neighbourhoods not
-//   converged, [9L+6] error bits (1: label out of range, 2: value out of range)
-constexpr int kAccWords = 9 * kMaxLabels + 7;
-__host__ __device__ constexpr int acc_t(int L) { return 9 * L; }
-__host__ __device__ constexpr int acc_ties(int L) { return 9 * L + 4; }
-__host__ __device__ constexpr int acc_nonconv(int L) { return 9 * L + 5; }
-__host__ __device__ constexpr int acc_err(int L) { return 9 * L + 6; }
-__host__ __device__ constexpr int acc_words(int L) { return 9 * L + 7; }
+// statistics record (8-byte words; counts as int64, sums as double bits), stored
+// word-major: word w of record r at rec[w * nrec + r]:
+//   per label l: [3l] count, [3l+1] sum of (y - c_l), [3l+2] sum of (y - c_l)^2
+//                (c_l = the mean used in this iteration)
+//   [3L] total energy, [3L+1] near ties, [3L+2] neighbourhoods not converged,
+//   [3L+3] error bits (1: label out of range, 2: non-finite value)
+__host__ __device__ constexpr int rec_words(int L) { return 3 * L + 4; }
+constexpr int kRecMax = 3 * kMaxLabels + 4;
+constexpr int kChunkTiles = 8;     // packets per statistics chunk (fixed: part of the result's definition)
+constexpr int kGroupTiles = 8;     // packets per neighbourhood-sum group (LDS buffer of 512 minima)
+constexpr int kVertPerBlock = 1024;
 
 struct GraphState {
   double mu[kMaxLabels], sigma[kMaxLabels], w[kMaxLabels], lg[kMaxLabels];
-  unsigned long long acc[kAccWords];
-  unsigned int arrivals;  // blocks of the current launch that have finished
-  int32_t done;           // 1: no further iterations (early exit or error)
+  int32_t done;  // 1: no further iterations (early exit or error)
   int32_t status;
   int32_t iters;
   int32_t map_conv, em_conv;
@@ -62,21 +83,23 @@ struct GraphDev {
   const TileDesc *tiles;
   const int32_t *vid;
   const uint32_t *mask;
+  const int32_t *hood_ptr;  // element offset of each neighbourhood, H+1 entries
   const double *y;
-  int32_t *x0;  // caller labels (even iterations read here)
-  int32_t *x1;  // workspace labels (odd iterations read here)
-  double *ring; // (W+1) x H neighbourhood sums
+  int32_t *x0;   // caller labels (even iterations read here)
+  int32_t *x1;   // workspace labels (odd iterations read here)
+  double *ring;  // (W+1) x H neighbourhood sums
   double *thist;
   GraphState *st;
+  long long *rec;  // statistics records (chunks, or vertex blocks)
   const double *in_mu, *in_sigma;
   double *out_mu, *out_sigma, *out_S, *out_trace;
   int64_t *out_stats, *out_ctr;
   int64_t M;
-  int32_t n, H, ntiles, L, P, W, max_iters, early_exit, init_from_labels;
+  int32_t n, H, ntiles, nchunks, L, P, W, max_iters, early_exit, init_from_labels;
   double beta, tol, sigma_min, tie_eps;
   int32_t block0, nblocks;    // blocks of this graph in an iteration launch
   int32_t vblock0, vnblocks;  // blocks of this graph in a vertex-parallel launch
-  int32_t tiles_per_block;
+  int32_t chunks_per_block;
 };
 
 constexpr int kDescPerPack = 12;
@@ -85,88 +108,143 @@ struct DescPack {
   int32_t first, count;
 };
 
-// -------------------------------------------------------- fixed-point sums
-// A value t is accumulated as round(|t| * 2^64) split into four base-2^32 limbs,
-// each added (with the sign of t) into its own int64 word; the words are
-// combined exactly at the end.  Integer addition is associative, so the sum
-// does not depend on order or grouping.
-__device__ __forceinline__ void fx_add(unsigned long long *acc, double t, int &err) {
-  double v = fabs(t) * 0x1p64;
-  if (!(v < 0x1p126)) {  // also rejects NaN
-    err |= 2;
-    return;
-  }
-  double a3 = floor(v * 0x1p-96);
-  v = v - a3 * 0x1p96;
-  double a2 = floor(v * 0x1p-64);
-  v = v - a2 * 0x1p64;
-  double a1 = floor(v * 0x1p-32);
-  v = v - a1 * 0x1p32;
-  double a0 = rint(v);
-  long long s = t < 0.0 ? -1 : 1;
-  if (a0 != 0.0) atomicAdd(acc + 0, (unsigned long long)(s * (long long)a0));
-  if (a1 != 0.0) atomicAdd(acc + 1, (unsigned long long)(s * (long long)a1));
-  if (a2 != 0.0) atomicAdd(acc + 2, (unsigned long long)(s * (long long)a2));
-  if (a3 != 0.0) atomicAdd(acc + 3, (unsigned long long)(s * (long long)a3));
+// Order the wave's own LDS writes before its LDS reads (a single wave executes
+// its LDS instructions in order; this also stops the compiler moving them).
+__device__ __forceinline__ void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+// Butterfly sums across the 64 lanes: every lane ends with the same value and
+// the order of additions is fixed.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v = v + __shfl_xor(v, m);
+  return v;
+}
+__device__ __forceinline__ long long wave_sum(long long v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v = v + __shfl_xor(v, m);
+  return v;
 }
 
-__device__ double fx_value(const unsigned long long *a) {
-  unsigned long long w0 = 0, w1 = 0, w2 = 0;
-  auto add3 = [&](unsigned long long x0, unsigned long long x1, unsigned long long x2) {
-    unsigned long long s0 = w0 + x0;
-    unsigned long long c0 = s0 < x0;
-    unsigned long long t1 = w1 + x1;
-    unsigned long long c1 = t1 < x1;
-    unsigned long long s1 = t1 + c0;
-    c1 += s1 < t1;
-    w2 = w2 + x2 + c1;
-    w0 = s0;
-    w1 = s1;
-  };
-  for (int k = 0; k < 4; ++k) {
-    long long v = (long long)a[k];
-    unsigned long long sx = v < 0 ? ~0ull : 0ull;
-    unsigned long long u = (unsigned long long)v;
-    unsigned long long hi = (unsigned long long)(v >> 32);
-    if (k == 0) add3(u, sx, sx);
-    else if (k == 1) add3(u << 32, hi, sx);
-    else if (k == 2) add3(0, u, sx);
-    else add3(0, u << 32, hi);
+template <int LMAX>
+struct LaneStats {
+  int cnt[LMAX];
+  double s1[LMAX], s2[LMAX];
+  double T;
+  int ties, nonconv, err;
+  __device__ void clear() {
+#pragma unroll
+    for (int l = 0; l < LMAX; ++l) {
+      cnt[l] = 0;
+      s1[l] = 0.0;
+      s2[l] = 0.0;
+    }
+    T = 0.0;
+    ties = nonconv = err = 0;
   }
-  bool neg = (long long)w2 < 0;
-  if (neg) {
-    w0 = ~w0;
-    w1 = ~w1;
-    w2 = ~w2;
-    w0 += 1;
-    unsigned long long c = w0 == 0;
-    w1 += c;
-    c = c && w1 == 0;
-    w2 += c;
+  // owner element with label a and d = y - mu_a
+  __device__ __forceinline__ void add_owner(int a, double d) {
+    const double d2 = d * d;
+#pragma unroll
+    for (int l = 0; l < LMAX; ++l)
+      if (a == l) {
+        cnt[l] += 1;
+        s1[l] = s1[l] + d;
+        s2[l] = s2[l] + d2;
+      }
   }
-  double r = ((double)w2 * 0x1p128 + (double)w1 * 0x1p64) + (double)w0;
-  r *= 0x1p-64;
-  return neg ? -r : r;
+  // wave-reduce and store one record (lane 0 writes word w at rec[w * stride]);
+  // Ptr is a global or LDS pointer
+  template <typename Ptr>
+  __device__ void store(Ptr rec, size_t stride, int L, int lane) {
+#pragma unroll
+    for (int l = 0; l < LMAX; ++l)
+      if (l < L) {
+        long long c = wave_sum((long long)cnt[l]);
+        double a = wave_sum(s1[l]);
+        double b = wave_sum(s2[l]);
+        if (lane == 0) {
+          rec[(3 * l) * stride] = c;
+          rec[(3 * l + 1) * stride] = __double_as_longlong(a);
+          rec[(3 * l + 2) * stride] = __double_as_longlong(b);
+        }
+      }
+    double t = wave_sum(T);
+    long long ti = wave_sum((long long)ties), nc = wave_sum((long long)nonconv);
+    unsigned long long e = __ballot(err & 1) ? 1ull : 0ull;
+    e |= __ballot(err & 2) ? 2ull : 0ull;
+    if (lane == 0) {
+      rec[(3 * L) * stride] = __double_as_longlong(t);
+      rec[(3 * L + 1) * stride] = ti;
+      rec[(3 * L + 2) * stride] = nc;
+      rec[(3 * L + 3) * stride] = (long long)e;
+    }
+  }
+};
+
+// Sum of a graph's records in a fixed order by a block of 16 waves: thread i
+// adds records i, i + 1024, i + 2048, ... in that order; the lanes of a wave are
+// combined with the butterfly and the waves in wave order.  Thread 0 returns
+// the totals in out[0 .. rec_words(L)).
+constexpr int kFinWaves = 16;
+constexpr int kFinThreads = 64 * kFinWaves;
+__device__ __forceinline__ bool word_is_double(int w, int L) { return (w < 3 * L && (w % 3) != 0) || w == 3 * L; }
+
+template <int LMAX>
+__device__ void sum_records(gptr<const long long> rec, int nrec, int L, long long *out,
+                            long long (*part)[kRecMax]) {
+  constexpr int WMAX = rec_words(LMAX);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int words = rec_words(L);
+  long long acc[WMAX];
+#pragma unroll
+  for (int w = 0; w < WMAX; ++w) acc[w] = 0;
+#pragma unroll 4
+  for (int r = threadIdx.x; r < nrec; r += kFinThreads) {
+    long long v[WMAX];
+#pragma unroll
+    for (int w = 0; w < WMAX; ++w) v[w] = w < words ? rec[(size_t)w * nrec + r] : 0;
+#pragma unroll
+    for (int w = 0; w < WMAX; ++w) {
+      if (w >= words) continue;
+      if (word_is_double(w, L))
+        acc[w] = __double_as_longlong(__longlong_as_double(acc[w]) + __longlong_as_double(v[w]));
+      else if (w == 3 * L + 3)
+        acc[w] |= v[w];
+      else
+        acc[w] += v[w];
+    }
+  }
+#pragma unroll
+  for (int w = 0; w < WMAX; ++w) {
+    if (w >= words) continue;
+    long long r;
+    if (word_is_double(w, L))
+      r = __double_as_longlong(wave_sum(__longlong_as_double(acc[w])));
+    else if (w == 3 * L + 3)
+      r = (long long)((__ballot(acc[w] & 1) ? 1ull : 0ull) | (__ballot(acc[w] & 2) ? 2ull : 0ull));
+    else
+      r = wave_sum(acc[w]);
+    if (lane == 0) part[wave][w] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int w = 0; w < words; ++w) {
+    if (word_is_double(w, L)) {
+      double x = 0.0;
+      for (int k = 0; k < kFinWaves; ++k) x = x + __longlong_as_double(part[k][w]);
+      out[w] = __double_as_longlong(x);
+    } else if (w == 3 * L + 3) {
+      long long x = 0;
+      for (int k = 0; k < kFinWaves; ++k) x |= part[k][w];
+      out[w] = x;
+    } else {
+      long long x = 0;
+      for (int k = 0; k < kFinWaves; ++k) x += part[k][w];
+      out[w] = x;
+    }
+  }
 }
 
-__device__ __forceinline__ void wave_sync_lds() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ __forceinline__ void block_acc_flush(unsigned long long *lacc, unsigned long long *gacc, int words) {
-  for (int i = threadIdx.x; i < words; i += blockDim.x) {
-    unsigned long long v = lacc[i];
-    if (v) __hip_atomic_fetch_add(gacc + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-}
-
-// Parameters for the next iteration from the exact per-label sums
-// ("Update Parameters"): mu = c + D1, sigma^2 = D2 - D1^2 with
-// D1 = sum(y - c)/n, D2 = sum((y - c)^2)/n, c = the mean used this iteration
-// (pass 0 of the starting update uses c = 0 and keeps sigma).  A label with no
-// vertex keeps its parameters.  Updated in place, one label at a time.
 __device__ void set_label_theta(GraphState *st, int l, double mu, double sigma) {
   st->mu[l] = mu;
   st->sigma[l] = sigma;
@@ -174,42 +252,26 @@ __device__ void set_label_theta(GraphState *st, int l, double mu, double sigma) 
   st->lg[l] = log(sigma);
 }
 
-__device__ __forceinline__ unsigned long long acc_load(unsigned long long *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ void acc_store(unsigned long long *p, unsigned long long v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ double fx_load_value(unsigned long long *p) {
-  unsigned long long a[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) a[k] = acc_load(p + k);
-  return fx_value(a);
-}
-
-__device__ void update_theta(GraphState *st, int L, double sigma_min, bool mean_only) {
+// Parameters for the next iteration from the per-label sums ("Update
+// Parameters"): mu = c + D1, sigma^2 = D2 - D1^2 with D1 = sum(y - c)/n,
+// D2 = sum((y - c)^2)/n, c = the mean used this iteration (pass 0 of the
+// starting update uses c = 0 and keeps sigma).  A label with no vertex keeps
+// its parameters.
+__device__ void update_theta(GraphState *st, const long long *tot, int L, double sigma_min, bool mean_only) {
   for (int l = 0; l < L; ++l) {
-    long long cnt = (long long)acc_load(st->acc + 9 * l);
+    long long cnt = tot[3 * l];
     if (cnt <= 0) continue;
     double nd = (double)cnt;
-    double d1 = fx_load_value(st->acc + 9 * l + 1) / nd;
+    double d1 = __longlong_as_double(tot[3 * l + 1]) / nd;
     if (mean_only) {
       set_label_theta(st, l, d1, st->sigma[l]);
       continue;
     }
-    double d2 = fx_load_value(st->acc + 9 * l + 5) / nd;
+    double d2 = __longlong_as_double(tot[3 * l + 2]) / nd;
     double var = d2 - d1 * d1;
     double sg = sqrt(var > 0.0 ? var : 0.0);
     set_label_theta(st, l, st->mu[l] + d1, sg < sigma_min ? sigma_min : sg);
   }
-}
-
-__device__ void clear_acc(GraphState *st, int L) {
-  for (int i = 0; i < acc_words(L); ++i) acc_store(st->acc + i, 0ull);
-  __hip_atomic_store(&st->arrivals, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __threadfence();
 }
 
 // Graph owning a block: the last graph whose first block is <= block.
@@ -229,7 +291,34 @@ struct Theta {
   double mu[LMAX], w[LMAX], lg[LMAX];
 };
 
-// Energies of one element under every label; returns min, argmin, gap.
+// What one iteration launch needs of a graph, in registers.
+struct Ctx {
+  gptr<const TileDesc> tiles;
+  gptr<const int32_t> vid;
+  gptr<const uint32_t> mask;
+  gptr<const int32_t> hood_ptr;
+  gptr<const double> y;
+  gptr<const int32_t> xr;
+  gptr<int32_t> xw;
+  gptr<double> ring;
+  int H, W, L, P, t, ntiles, nchunks;
+  double beta, tol, tie_eps;
+};
+
+__device__ __forceinline__ TileDesc load_tile(gptr<const TileDesc> p) {
+  TileDesc td;
+  td.start_mask = p->start_mask;
+  td.elem_start = p->elem_start;
+  td.hood_start = p->hood_start;
+  td.mask_start = p->mask_start;
+  td.nelem = p->nelem;
+  td.kind = p->kind;
+  td.words = p->words;
+  return td;
+}
+
+// Energies of one element under every label; returns min, argmin, gap and
+// y - mu of the argmin label.
 template <int LMAX>
 __device__ __forceinline__ void element_energy(const Theta<LMAX> &th, int L, double beta, double yv, int deg,
                                                const int *cnt, double &m, int &a, double &gap, double &dsel) {
@@ -259,65 +348,69 @@ __device__ __forceinline__ void element_energy(const Theta<LMAX> &th, int L, dou
   gap = second - m;
 }
 
-// Owner-element work: label write, parameter statistics, near-tie flag.
-__device__ __forceinline__ void owner_update(unsigned long long *lacc, int32_t *xw, int v, int a, double dsel,
-                                             int &err) {
-  xw[v] = a;
-  atomicAdd(lacc + 9 * a, 1ull);
-  fx_add(lacc + 9 * a + 1, dsel, err);
-  fx_add(lacc + 9 * a + 5, dsel * dsel, err);
-}
-
-// Neighbourhood total: convergence window and energy total.
-__device__ __forceinline__ bool hood_done(const GraphDev &G, int t, int h, double S, unsigned long long *lacc,
-                                          int &err) {
-  const int slots = G.W + 1;
-  G.ring[(size_t)(t % slots) * G.H + h] = S;
-  bool conv = t >= G.W;
-  if (conv) {
-    for (int w = 1; w <= G.W; ++w) {
-      double prev = G.ring[(size_t)((t - w) % slots) * G.H + h];
-      if (!(fabs(S - prev) < G.tol)) conv = false;
-    }
+// Convergence window of one neighbourhood: |S - S^{t-w}| < tol for w = 1..W.
+__device__ __forceinline__ bool hood_converged(const Ctx &c, int h, double S) {
+  const int slots = c.W + 1;
+  c.ring[(size_t)(c.t % slots) * c.H + h] = S;
+  if (c.t < c.W) return false;
+  bool conv = true;
+  for (int w = 1; w <= c.W; ++w) {
+    double prev = c.ring[(size_t)((c.t - w) % slots) * c.H + h];
+    if (!(fabs(S - prev) < c.tol)) conv = false;
   }
-  fx_add(lacc + acc_t(G.L), S, err);
   return conv;
 }
 
-// Packets of whole neighbourhoods of at most 64 members (kinds SMALL, MID).
-template <int LMAX>
-__device__ void do_packed(const GraphDev &G, const TileDesc &td, int t, const int32_t *__restrict__ xr,
-                          int32_t *__restrict__ xw, const Theta<LMAX> &th, unsigned long long *lacc, double *mb,
-                          int lane, int &err) {
-  const bool valid = lane < td.nelem;
-  int v = 0, xv = 0;
-  double yv = 0.0;
-  uint64_t am = 0;
-  if (valid) {
-    const int e = td.elem_start + lane;
-    v = G.vid[e];
-    xv = xr[v];
-    yv = G.y[v];
-    if (td.words == 1) {
-      am = G.mask[td.mask_start + lane];
-    } else {
-      const uint32_t *mw = G.mask + td.mask_start + 2 * lane;
-      am = (uint64_t)mw[0] | ((uint64_t)mw[1] << 32);
-    }
-    if ((unsigned)xv >= (unsigned)G.L) err |= 1;
+// Per-lane data of one packet, loaded ahead of its computation.
+struct Stream {
+  int v;
+  uint64_t am;
+};
+struct Gather {
+  int xv;
+  double yv;
+};
+
+__device__ __forceinline__ Stream load_stream(const Ctx &c, const TileDesc &td, int lane) {
+  Stream r{0, 0};
+  if (td.kind != kLarge && lane < td.nelem) {
+    r.v = c.vid[td.elem_start + lane];
+    if (td.words == 1)
+      r.am = c.mask[td.mask_start + lane];
+    else
+      r.am = (uint64_t)c.mask[td.mask_start + 2 * lane] | ((uint64_t)c.mask[td.mask_start + 2 * lane + 1] << 32);
   }
+  return r;
+}
+
+__device__ __forceinline__ Gather load_gather(const Ctx &c, const TileDesc &td, const Stream &st, int lane) {
+  Gather r{0, 0.0};
+  if (td.kind != kLarge && lane < td.nelem) {
+    r.xv = c.xr[st.v];
+    r.yv = c.y[st.v];
+  }
+  return r;
+}
+
+// Element pass of a packet of whole neighbourhoods of at most 64 members
+// (kinds SMALL, MID): minimum energies into mb[e - gstart].
+template <int LMAX>
+__device__ __forceinline__ void elem_pass(const Ctx &c, const TileDesc &td, const Stream &sd, const Gather &gd,
+                                          int gstart, const Theta<LMAX> &th, LaneStats<LMAX> &ls, double *mb,
+                                          int lane) {
+  const bool valid = lane < td.nelem;
+  const int e = td.elem_start + lane;
+  const int v = sd.v, xv = gd.xv;
+  const uint64_t am = sd.am;
+  const double yv = gd.yv;
+  if (valid && (unsigned)xv >= (unsigned)c.L) ls.err |= 1;
   uint64_t planes[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k)
-    if (k < G.P) planes[k] = __ballot(valid && ((xv >> k) & 1));
+    if (k < c.P) planes[k] = __ballot(valid && ((xv >> k) & 1));
   const uint64_t below = (2ull << lane) - 1ull;  // lanes 0..lane
-  const uint64_t sm = td.start_mask;
-  const int base = 63 - __clzll(sm & below);
-  const uint64_t after = sm & ~below;
-  const int end = after ? (__ffsll((long long)after) - 1) : td.nelem;
-  const int j = lane - base;
-  const int s = end - base;
-  const uint64_t self = 1ull << j;
+  const int base = 63 - __clzll(td.start_mask & below);
+  const uint64_t self = 1ull << (lane - base);
   const bool owner = valid && (am & self);
   const uint64_t nbr = am & ~self;
   const int deg = __popcll(nbr);
@@ -327,7 +420,7 @@ __device__ void do_packed(const GraphDev &G, const TileDesc &td, int t, const in
     uint64_t eq = ~0ull;
 #pragma unroll
     for (int k = 0; k < 4; ++k)
-      if (k < G.P) {
+      if (k < c.P) {
         uint64_t pk = planes[k] >> base;
         eq &= ((l >> k) & 1) ? pk : ~pk;
       }
@@ -335,55 +428,86 @@ __device__ void do_packed(const GraphDev &G, const TileDesc &td, int t, const in
   }
   double m, gap, dsel;
   int a;
-  element_energy<LMAX>(th, G.L, G.beta, yv, deg, cnt, m, a, gap, dsel);
-  if (owner) owner_update(lacc, xw, v, a, dsel, err);
-  const uint64_t ties = __ballot(owner && gap < G.tie_eps);
-  mb[lane] = valid ? m : 0.0;
-  wave_sync_lds();
-  bool leader = valid && j == 0;
-  bool conv = true;
-  if (leader) {
+  element_energy<LMAX>(th, c.L, c.beta, yv, deg, cnt, m, a, gap, dsel);
+  if (owner) {
+    c.xw[v] = a;
+    ls.add_owner(a, dsel);
+    if (gap < c.tie_eps) ls.ties += 1;
+  }
+  if (valid) mb[e - gstart] = m;
+}
+
+// Neighbourhood pass: neighbourhoods [h0, h1) whose elements start at gstart,
+// one lane each: member-order sum, convergence window, energy total.
+template <int LMAX>
+__device__ __forceinline__ void hood_pass(const Ctx &c, int h0, int h1, int gstart, LaneStats<LMAX> &ls,
+                                          const double *mb, int lane) {
+  wave_lds_sync();
+  const int slots = c.W + 1;
+  const bool window = c.t >= c.W;
+  for (int hb = h0; hb < h1; hb += 64) {
+    const int h = hb + lane;
+    const bool act = h < h1;
+    int o = 0, s = 0;
+    double prev[kMaxWindow];
+    if (act) {
+      const int p0 = c.hood_ptr[h];
+      o = p0 - gstart;
+      s = c.hood_ptr[h + 1] - p0;
+      if (window) {
+#pragma unroll
+        for (int w = 1; w <= kMaxWindow; ++w)
+          if (w <= c.W) prev[w - 1] = c.ring[(size_t)((c.t - w) % slots) * c.H + h];
+      }
+    }
     double S = 0.0;
-    for (int k = 0; k < s; ++k) S = S + mb[base + k];
-    const int h = td.hood_start + __popcll(sm & below) - 1;
-    conv = hood_done(G, t, h, S, lacc, err);
+    for (int k = 0; __ballot(k < s); k += 4) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (k + i < s) S = S + mb[o + k + i];
+    }
+    if (act) {
+      c.ring[(size_t)(c.t % slots) * c.H + h] = S;
+      bool conv = window;
+      if (window) {
+#pragma unroll
+        for (int w = 1; w <= kMaxWindow; ++w)
+          if (w <= c.W && !(fabs(S - prev[w - 1]) < c.tol)) conv = false;
+      }
+      if (!conv) ls.nonconv += 1;
+      ls.T = ls.T + S;
+    }
   }
-  const uint64_t nonconv = __ballot(leader && !conv);
-  if (lane == 0) {
-    if (ties) atomicAdd(lacc + acc_ties(G.L), (unsigned long long)__popcll(ties));
-    if (nonconv) atomicAdd(lacc + acc_nonconv(G.L), (unsigned long long)__popcll(nonconv));
-  }
-  wave_sync_lds();
+  wave_lds_sync();
 }
 
 // One neighbourhood of 65..1024 members, in chunks of 64 (kind LARGE).
 template <int LMAX>
-__device__ void do_large(const GraphDev &G, const TileDesc &td, int t, const int32_t *__restrict__ xr,
-                         int32_t *__restrict__ xw, const Theta<LMAX> &th, unsigned long long *lacc, double *mb,
-                         uint64_t *pl /* 4 x 16 words */, int lane, int &err) {
+__device__ void do_large(const Ctx &c, const TileDesc &td, const Theta<LMAX> &th, LaneStats<LMAX> &ls, double *mb,
+                         uint64_t *pl /* 4 x 16 words */, int lane) {
   const int s = td.nelem;
   const int W = td.words;
   const int chunks = (s + 63) >> 6;
-  for (int c = 0; c < chunks; ++c) {
-    const int jj = c * 64 + lane;
+  wave_lds_sync();
+  for (int ch = 0; ch < chunks; ++ch) {
+    const int jj = ch * 64 + lane;
     int xv = 0;
     const bool valid = jj < s;
     if (valid) {
-      xv = xr[G.vid[td.elem_start + jj]];
-      if ((unsigned)xv >= (unsigned)G.L) err |= 1;
+      xv = c.xr[c.vid[td.elem_start + jj]];
+      if ((unsigned)xv >= (unsigned)c.L) ls.err |= 1;
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k)
-      if (k < G.P) {
+      if (k < c.P) {
         uint64_t b = __ballot(valid && ((xv >> k) & 1));
-        if (lane == 0) pl[k * 16 + c] = b;
+        if (lane == 0) pl[k * 16 + ch] = b;
       }
   }
-  wave_sync_lds();
+  wave_lds_sync();
   double S = 0.0;  // lane 0 accumulates in member order
-  unsigned long long ties = 0;
-  for (int c = 0; c < chunks; ++c) {
-    const int jj = c * 64 + lane;
+  for (int ch = 0; ch < chunks; ++ch) {
+    const int jj = ch * 64 + lane;
     const bool valid = jj < s;
     int v = 0;
     double yv = 0.0;
@@ -393,9 +517,9 @@ __device__ void do_large(const GraphDev &G, const TileDesc &td, int t, const int
     int deg = 0;
     bool owner = false;
     if (valid) {
-      v = G.vid[td.elem_start + jj];
-      yv = G.y[v];
-      const uint32_t *mw = G.mask + td.mask_start + (size_t)jj * W;
+      v = c.vid[td.elem_start + jj];
+      yv = c.y[v];
+      gptr<const uint32_t> mw = c.mask + td.mask_start + (size_t)jj * W;
       for (int wi = 0; wi < W; ++wi) {
         uint32_t word = mw[wi];
         if (wi == (jj >> 5)) {
@@ -409,7 +533,7 @@ __device__ void do_large(const GraphDev &G, const TileDesc &td, int t, const int
           uint32_t eq = ~0u;
 #pragma unroll
           for (int k = 0; k < 4; ++k)
-            if (k < G.P) {
+            if (k < c.P) {
               uint32_t pk = (uint32_t)(pl[k * 16 + (wi >> 1)] >> ((wi & 1) * 32));
               eq &= ((l >> k) & 1) ? pk : ~pk;
             }
@@ -419,56 +543,76 @@ __device__ void do_large(const GraphDev &G, const TileDesc &td, int t, const int
     }
     double m, gap, dsel;
     int a;
-    element_energy<LMAX>(th, G.L, G.beta, yv, deg, cnt, m, a, gap, dsel);
-    if (owner) owner_update(lacc, xw, v, a, dsel, err);
-    ties += __popcll(__ballot(owner && gap < G.tie_eps));
+    element_energy<LMAX>(th, c.L, c.beta, yv, deg, cnt, m, a, gap, dsel);
+    if (owner) {
+      c.xw[v] = a;
+      ls.add_owner(a, dsel);
+      if (gap < c.tie_eps) ls.ties += 1;
+    }
     mb[lane] = valid ? m : 0.0;
-    wave_sync_lds();
+    wave_lds_sync();
     if (lane == 0) {
-      const int lim = min(64, s - c * 64);
+      const int lim = min(64, s - ch * 64);
       for (int k = 0; k < lim; ++k) S = S + mb[k];
     }
-    wave_sync_lds();
+    wave_lds_sync();
   }
   if (lane == 0) {
-    bool conv = hood_done(G, t, td.hood_start, S, lacc, err);
-    if (ties) atomicAdd(lacc + acc_ties(G.L), ties);
-    if (!conv) atomicAdd(lacc + acc_nonconv(G.L), 1ull);
+    if (!hood_converged(c, td.hood_start, S)) ls.nonconv += 1;
+    ls.T = ls.T + S;
   }
 }
 
-// The last block of a graph: fold the sums into the next parameters and the
-// per-iteration records; clear the sums for the next launch.
-__device__ void finalize_iteration(const GraphDev &G, int t) {
-  GraphState *st = G.st;
-  const int L = G.L;
-  unsigned long long errbits = acc_load(st->acc + acc_err(L));
-  if (errbits) {
-    st->status = (errbits & 1) ? PMRF_EBADLABEL : PMRF_ERANGE;
-    st->done = 1;
-  } else {
-    double T = fx_load_value(st->acc + acc_t(L));
-    long long ties = (long long)acc_load(st->acc + acc_ties(L));
-    long long nonconv = (long long)acc_load(st->acc + acc_nonconv(L));
-    G.thist[t] = T;
-    if (G.out_trace) G.out_trace[t] = T;
-    if (G.out_stats) {
-      G.out_stats[2 * t] = ties;
-      G.out_stats[2 * t + 1] = nonconv;
-    }
-    st->ties_total += ties;
-    if (nonconv == 0 && t >= G.W && st->map_conv < 0) st->map_conv = t;
-    if (t >= G.W && st->em_conv < 0) {
-      bool ok = true;
-      for (int w = 1; w <= G.W; ++w)
-        if (!(fabs(T - G.thist[t - w]) < G.tol)) ok = false;
-      if (ok) st->em_conv = t;
-    }
-    update_theta(st, L, G.sigma_min, false);
-    st->iters = t + 1;
-    if (G.early_exit && nonconv == 0 && t >= G.W) st->done = 1;
+// One statistics chunk: packets [ck*8, min(ntiles, ck*8+8)).  Packet data is
+// loaded ahead: the stream of packet i+2 and the gathers of packet i+1 are in
+// flight while packet i is computed.
+template <int LMAX>
+__device__ void do_chunk(const Ctx &c, int ck, const Theta<LMAX> &th, gptr<long long> rec, double *mb, uint64_t *pl,
+                         int lane) {
+  LaneStats<LMAX> ls;
+  ls.clear();
+  const int tb = ck * kChunkTiles, te = min(c.ntiles, tb + kChunkTiles);
+  int g0 = tb;  // first packet of the pending neighbourhood group
+  int gstart = 0, ghood = 0;
+  TileDesc tdC = load_tile(c.tiles + tb), tdB{}, tdA{};
+  Stream sC = load_stream(c, tdC, lane), sB{0, 0}, sA{0, 0};
+  Gather gC = load_gather(c, tdC, sC, lane), gB{0, 0.0};
+  if (tb + 1 < te) {
+    tdB = load_tile(c.tiles + tb + 1);
+    sB = load_stream(c, tdB, lane);
   }
-  clear_acc(st, L);
+  for (int ti = tb; ti < te; ++ti) {
+    if (ti + 1 < te) gB = load_gather(c, tdB, sB, lane);
+    if (ti + 2 < te) {
+      tdA = load_tile(c.tiles + ti + 2);
+      sA = load_stream(c, tdA, lane);
+    }
+    if (tdC.kind == kLarge) {
+      if (ti > g0) hood_pass<LMAX>(c, ghood, tdC.hood_start, gstart, ls, mb, lane);
+      do_large<LMAX>(c, tdC, th, ls, mb, pl, lane);
+      g0 = ti + 1;
+    } else {
+      if (ti - g0 == kGroupTiles) {
+        hood_pass<LMAX>(c, ghood, tdC.hood_start, gstart, ls, mb, lane);
+        g0 = ti;
+      }
+      if (ti == g0) {
+        gstart = tdC.elem_start;
+        ghood = tdC.hood_start;
+      }
+      elem_pass<LMAX>(c, tdC, sC, gC, gstart, th, ls, mb, lane);
+    }
+    tdC = tdB;
+    sC = sB;
+    gC = gB;
+    tdB = tdA;
+    sB = sA;
+  }
+  if (te > g0) {
+    const int hend = te < c.ntiles ? load_tile(c.tiles + te).hood_start : c.H;
+    hood_pass<LMAX>(c, ghood, hend, gstart, ls, mb, lane);
+  }
+  ls.store(rec + ck, (size_t)c.nchunks, c.L, lane);
 }
 
 // ------------------------------------------------------------------ kernels
@@ -489,8 +633,6 @@ __global__ void k_setup(const GraphDev *graphs, int B) {
   st->map_conv = -1;
   st->em_conv = -1;
   st->ties_total = 0;
-  st->arrivals = 0u;
-  for (int i = 0; i < kAccWords; ++i) st->acc[i] = 0ull;
   bool ok = true;
   for (int l = 0; l < G.L; ++l) {
     double mu = G.in_mu[l], sigma = G.in_sigma[l];
@@ -508,99 +650,158 @@ __global__ void k_setup(const GraphDev *graphs, int B) {
 
 // Parameter update from the starting labels (used when init_from_labels is
 // set): pass 0 sums y per label (mean), pass 1 sums (y - mean) and (y - mean)^2.
-__global__ void k_mstep_init(const GraphDev *graphs, int B, int pass) {
-  __shared__ unsigned long long lacc[kAccWords];
-  __shared__ int last;
+// Block b covers vertices [b*1024, b*1024 + 1024), thread t the vertices
+// t, t+256, ... of that range; one record per block.
+__global__ __launch_bounds__(256) void k_mstep_init(const GraphDev *graphs, int B, int pass) {
+  __shared__ long long part[4][kRecMax];
   const int g = find_graph(graphs, B, blockIdx.x, true);
   const GraphDev &G = graphs[g];
-  GraphState *st = G.st;
+  gptr<const GraphState> st = gbl((const GraphState *)G.st);
   if (!G.init_from_labels || st->done) return;
-  const int words = acc_words(G.L);
-  for (int i = threadIdx.x; i < words; i += blockDim.x) lacc[i] = 0ull;
-  __syncthreads();
-  int err = 0;
+  const int L = G.L, words = rec_words(L);
   const int b = blockIdx.x - G.vblock0;
-  const int per = (G.n + G.vnblocks - 1) / G.vnblocks;
-  const int v0 = b * per, v1 = min(G.n, v0 + per);
+  const int v0 = b * kVertPerBlock, v1 = min(G.n, v0 + kVertPerBlock);
+  gptr<const int32_t> x = gbl((const int32_t *)G.x0);
+  gptr<const double> y = gbl(G.y);
+  LaneStats<kMaxLabels> ls;
+  ls.clear();
+  double c[kMaxLabels];
+  for (int l = 0; l < kMaxLabels; ++l) c[l] = (pass == 0 || l >= L) ? 0.0 : st->mu[l];
   for (int v = v0 + threadIdx.x; v < v1; v += blockDim.x) {
-    int x = G.x0[v];
-    if ((unsigned)x >= (unsigned)G.L) {
-      err |= 1;
+    int xv = x[v];
+    if ((unsigned)xv >= (unsigned)L) {
+      ls.err |= 1;
       continue;
     }
-    double d = G.y[v] - (pass == 0 ? 0.0 : st->mu[x]);
-    atomicAdd(lacc + 9 * x, 1ull);
-    fx_add(lacc + 9 * x + 1, d, err);
-    if (pass == 1) fx_add(lacc + 9 * x + 5, d * d, err);
+    double cv = 0.0;
+    for (int l = 0; l < L; ++l)
+      if (l == xv) cv = c[l];
+    ls.add_owner(xv, y[v] - cv);
   }
-  if (err) atomicOr(lacc + acc_err(G.L), (unsigned long long)err);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  ls.store(&part[wave][0], 1, L, lane);
   __syncthreads();
-  block_acc_flush(lacc, st->acc, words);
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0)
-    last = __hip_atomic_fetch_add(&st->arrivals, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) ==
-           (unsigned)(G.vnblocks - 1);
-  __syncthreads();
-  if (!last || threadIdx.x != 0) return;
-  __threadfence();
-  unsigned long long errbits = acc_load(st->acc + acc_err(G.L));
+  if (threadIdx.x >= 64) return;
+  // the four waves in order
+  if (lane < words) {
+    long long out;
+    const int w = lane;
+    if (word_is_double(w, L)) {
+      double acc = 0.0;
+      for (int k = 0; k < 4; ++k) acc = acc + __longlong_as_double(part[k][w]);
+      out = __double_as_longlong(acc);
+    } else if (w == 3 * L + 3) {
+      out = part[0][w] | part[1][w] | part[2][w] | part[3][w];
+    } else {
+      out = part[0][w] + part[1][w] + part[2][w] + part[3][w];
+    }
+    gbl(G.rec)[(size_t)w * G.vnblocks + b] = out;
+  }
+}
+
+template <int LMAX>
+__global__ __launch_bounds__(1024) void k_fin_init(const GraphDev *graphs, int B, int pass) {
+  __shared__ long long tot[kRecMax];
+  __shared__ long long part[kFinWaves][kRecMax];
+  const GraphDev &G = graphs[blockIdx.x];
+  GraphState *st = G.st;
+  if (!G.init_from_labels || st->done) return;
+  sum_records<LMAX>(gbl((const long long *)G.rec), G.vnblocks, G.L, tot, part);
+  if (threadIdx.x != 0) return;
+  long long errbits = tot[3 * G.L + 3];
   if (errbits) {
     st->status = (errbits & 1) ? PMRF_EBADLABEL : PMRF_ERANGE;
     st->done = 1;
-  } else {
-    update_theta(st, G.L, G.sigma_min, pass == 0);
+    return;
   }
-  clear_acc(st, G.L);
+  update_theta(st, tot, G.L, G.sigma_min, pass == 0);
 }
 
-// One EM iteration over every graph of the launch.
+// One EM iteration over every graph of the launch.  Dynamic LDS per wave: 512
+// minima and 64 label-plane words.
 template <int LMAX>
 __global__ __launch_bounds__(1024) void k_iter(const GraphDev *__restrict__ graphs, int B, int t) {
-  __shared__ unsigned long long lacc[acc_words(LMAX)];
-  __shared__ double mbuf[16][64];
-  __shared__ uint64_t planes[16][64];
-  __shared__ int last;
+  extern __shared__ double smem[];
   const int g = find_graph(graphs, B, blockIdx.x, false);
   const GraphDev &G = graphs[g];
-  GraphState *st = G.st;
-  if (t >= G.max_iters || st->done) return;
-  const int words = acc_words(G.L);
-  for (int i = threadIdx.x; i < words; i += blockDim.x) lacc[i] = 0ull;
+  if (t >= G.max_iters) return;
+  gptr<const GraphState> st = gbl((const GraphState *)G.st);
+  if (st->done) return;
+  const int nw = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double *mb = smem + wave * (kGroupTiles * 64 + 64);
+  uint64_t *pl = reinterpret_cast<uint64_t *>(mb + kGroupTiles * 64);
+  Ctx c;
+  c.tiles = gbl(G.tiles);
+  c.vid = gbl(G.vid);
+  c.mask = gbl(G.mask);
+  c.hood_ptr = gbl(G.hood_ptr);
+  c.y = gbl(G.y);
+  c.xr = gbl((const int32_t *)((t & 1) ? G.x1 : G.x0));
+  c.xw = gbl((t & 1) ? G.x0 : G.x1);
+  c.ring = gbl(G.ring);
+  c.H = G.H;
+  c.W = G.W;
+  c.L = G.L;
+  c.P = G.P;
+  c.t = t;
+  c.ntiles = G.ntiles;
+  c.nchunks = G.nchunks;
+  c.beta = G.beta;
+  c.tol = G.tol;
+  c.tie_eps = G.tie_eps;
   Theta<LMAX> th;
 #pragma unroll
   for (int l = 0; l < LMAX; ++l) {
-    th.mu[l] = l < G.L ? st->mu[l] : 0.0;
-    th.w[l] = l < G.L ? st->w[l] : 0.0;
-    th.lg[l] = l < G.L ? st->lg[l] : 0.0;
+    th.mu[l] = l < c.L ? st->mu[l] : 0.0;
+    th.w[l] = l < c.L ? st->w[l] : 0.0;
+    th.lg[l] = l < c.L ? st->lg[l] : 0.0;
   }
-  __syncthreads();
-  const int32_t *xr = (t & 1) ? G.x1 : G.x0;
-  int32_t *xw = (t & 1) ? G.x0 : G.x1;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
   const int b = blockIdx.x - G.block0;
-  const int t0 = b * G.tiles_per_block;
-  const int t1 = min(G.ntiles, t0 + G.tiles_per_block);
-  int err = 0;
-  for (int ti = t0 + wave; ti < t1; ti += nw) {
-    const TileDesc td = G.tiles[ti];
-    if (td.kind == kLarge)
-      do_large<LMAX>(G, td, t, xr, xw, th, lacc, mbuf[wave], planes[wave], lane, err);
-    else
-      do_packed<LMAX>(G, td, t, xr, xw, th, lacc, mbuf[wave], lane, err);
+  const int c0 = b * G.chunks_per_block;
+  const int c1 = min(G.nchunks, c0 + G.chunks_per_block);
+  gptr<long long> rec = gbl(G.rec);
+  for (int ck = c0 + wave; ck < c1; ck += nw) do_chunk<LMAX>(c, ck, th, rec, mb, pl, lane);
+}
+
+// Fold one graph's chunk records into the next parameters and the
+// per-iteration records (one block per graph).
+template <int LMAX>
+__global__ __launch_bounds__(1024) void k_fin_iter(const GraphDev *graphs, int B, int t) {
+  __shared__ long long tot[kRecMax];
+  __shared__ long long part[kFinWaves][kRecMax];
+  const GraphDev &G = graphs[blockIdx.x];
+  if (t >= G.max_iters) return;
+  GraphState *st = G.st;
+  if (st->done) return;
+  const int L = G.L;
+  sum_records<LMAX>(gbl((const long long *)G.rec), G.nchunks, L, tot, part);
+  if (threadIdx.x != 0) return;
+  long long errbits = tot[3 * L + 3];
+  if (errbits) {
+    st->status = (errbits & 1) ? PMRF_EBADLABEL : PMRF_ERANGE;
+    st->done = 1;
+    return;
   }
-  if (err) atomicOr(lacc + acc_err(G.L), (unsigned long long)err);
-  __syncthreads();
-  block_acc_flush(lacc, st->acc, words);
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0)
-    last = __hip_atomic_fetch_add(&st->arrivals, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) ==
-           (unsigned)(G.nblocks - 1);
-  __syncthreads();
-  if (!last || threadIdx.x != 0) return;
-  __threadfence();
-  finalize_iteration(G, t);
+  double T = __longlong_as_double(tot[3 * L]);
+  long long ties = tot[3 * L + 1];
+  long long nonconv = tot[3 * L + 2];
+  G.thist[t] = T;
+  if (G.out_trace) G.out_trace[t] = T;
+  if (G.out_stats) {
+    G.out_stats[2 * t] = ties;
+    G.out_stats[2 * t + 1] = nonconv;
+  }
+  st->ties_total += ties;
+  if (nonconv == 0 && t >= G.W && st->map_conv < 0) st->map_conv = t;
+  if (t >= G.W && st->em_conv < 0) {
+    bool ok = true;
+    for (int w = 1; w <= G.W; ++w)
+      if (!(fabs(T - G.thist[t - w]) < G.tol)) ok = false;
+    if (ok) st->em_conv = t;
+  }
+  update_theta(st, tot, L, G.sigma_min, false);
+  st->iters = t + 1;
+  if (G.early_exit && nonconv == 0 && t >= G.W) st->done = 1;
 }
 
 // Copy results to the caller's buffers.
@@ -638,20 +839,65 @@ __global__ void k_final(const GraphDev *graphs, int B) {
 std::mutex g_launch_mu;
 pmrf_launch g_launch{0, 0, 0, 0};
 
+// event pairs bracketing iteration launches while profiling is on
+struct Profiler {
+  bool on = false;
+  size_t used = 0;
+  std::vector<hipEvent_t> start, stop;
+} g_prof;
+
+hipError_t prof_mark(hipStream_t stream, bool begin) {
+  if (!g_prof.on) return hipSuccess;
+  if (begin && g_prof.used == g_prof.start.size()) {
+    hipEvent_t a, b;
+    hipError_t e = hipEventCreate(&a);
+    if (e != hipSuccess) return e;
+    e = hipEventCreate(&b);
+    if (e != hipSuccess) return e;
+    g_prof.start.push_back(a);
+    g_prof.stop.push_back(b);
+  }
+  if (begin) return hipEventRecord(g_prof.start[g_prof.used], stream);
+  return hipEventRecord(g_prof.stop[g_prof.used++], stream);
+}
+
+constexpr int kModeGraph = 1, kModePersistent = 2, kModeDirect = 3;
+
 struct LaunchShape {
-  int waves_per_block, tiles_per_wave;
+  int mode, waves_per_block, tiles_per_wave;
 };
 
 LaunchShape resolve_shape() {
   std::lock_guard<std::mutex> lk(g_launch_mu);
-  LaunchShape s{g_launch.waves_per_block > 0 ? g_launch.waves_per_block : 4,
-                g_launch.tiles_per_wave > 0 ? g_launch.tiles_per_wave : 8};
+  LaunchShape s{g_launch.mode > 0 ? g_launch.mode : kModeGraph,
+                g_launch.waves_per_block > 0 ? g_launch.waves_per_block : 4,
+                g_launch.tiles_per_wave > 0 ? g_launch.tiles_per_wave : 1};
+  return s;
+}
+
+// Instantiated HIP graphs of recent argument sets (most recent first).
+struct GraphEntry {
+  std::string key;
+  hipGraphExec_t exec;
+  hipEvent_t done;  // recorded after each replay: the entry is idle once it completes
+};
+constexpr size_t kGraphCacheSize = 16;
+std::mutex g_graph_mu;
+std::list<GraphEntry> g_graphs;
+std::map<int, hipStream_t> g_capture_streams;
+
+hipStream_t capture_stream(int dev) {
+  auto it = g_capture_streams.find(dev);
+  if (it != g_capture_streams.end()) return it->second;
+  hipStream_t s = nullptr;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+  g_capture_streams[dev] = s;
   return s;
 }
 
 struct WsPlan {
   int64_t desc_off = 0;
-  std::vector<int64_t> state_off, x1_off, ring_off, thist_off;
+  std::vector<int64_t> state_off, x1_off, ring_off, thist_off, rec_off;
   int64_t total = 0;
 };
 
@@ -680,6 +926,10 @@ pmrf_status check_item(const pmrf_em_item &it, int idx) {
   return PMRF_OK;
 }
 
+int64_t n_chunks(const pmrf_hoods *h) { return ((int64_t)h->tiles.size() + kChunkTiles - 1) / kChunkTiles; }
+int64_t vert_blocks(const pmrf_hoods *h) { return std::max<int64_t>(1, ((int64_t)h->n + kVertPerBlock - 1) / kVertPerBlock); }
+int64_t max_records(const pmrf_hoods *h) { return std::max<int64_t>(std::max<int64_t>(1, n_chunks(h)), vert_blocks(h)); }
+
 WsPlan plan_workspace(int B, const pmrf_em_item *items) {
   WsPlan p;
   int64_t off = 0;
@@ -695,6 +945,8 @@ WsPlan plan_workspace(int B, const pmrf_em_item *items) {
     off += align_up((int64_t)(items[i].params.conv_window + 1) * h->H * 8, 256);
     p.thist_off.push_back(off);
     off += align_up((int64_t)std::max(1, items[i].params.max_iters) * 8, 256);
+    p.rec_off.push_back(off);
+    off += align_up(max_records(h) * rec_words(items[i].params.L) * 8, 256);
   }
   p.total = std::max<int64_t>(off, 256);
   return p;
@@ -714,7 +966,8 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
   if (ws_bytes < plan.total) return fail(PMRF_ENOMEM, "workspace smaller than the required size");
   if (reinterpret_cast<uintptr_t>(d_ws) % 256) return fail(PMRF_EINVAL, "workspace must be 256-byte aligned");
   const LaunchShape shape = resolve_shape();
-  const int tpb = shape.waves_per_block * shape.tiles_per_wave;
+  if (shape.mode == kModePersistent) return fail(PMRF_EUNSUPPORTED, "the persistent launch mode is not available");
+  const int cpb = shape.waves_per_block * shape.tiles_per_wave;  // chunks per block
   const int threads = shape.waves_per_block * kWave;
   char *ws = static_cast<char *>(d_ws);
   std::vector<GraphDev> desc(B);
@@ -727,12 +980,14 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
     G.tiles = reinterpret_cast<const TileDesc *>(hb + h->layout.tiles_off);
     G.vid = reinterpret_cast<const int32_t *>(hb + h->layout.vid_off);
     G.mask = reinterpret_cast<const uint32_t *>(hb + h->layout.mask_off);
+    G.hood_ptr = reinterpret_cast<const int32_t *>(hb + h->layout.hptr_off);
     G.y = it.d_y;
     G.x0 = it.d_labels;
     G.x1 = reinterpret_cast<int32_t *>(ws + plan.x1_off[i]);
     G.ring = reinterpret_cast<double *>(ws + plan.ring_off[i]);
     G.thist = reinterpret_cast<double *>(ws + plan.thist_off[i]);
     G.st = reinterpret_cast<GraphState *>(ws + plan.state_off[i]);
+    G.rec = reinterpret_cast<long long *>(ws + plan.rec_off[i]);
     G.in_mu = it.d_mu;
     G.in_sigma = it.d_sigma;
     G.out_mu = it.d_mu;
@@ -755,48 +1010,131 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
     G.tol = it.params.conv_tol;
     G.sigma_min = it.params.sigma_min;
     G.tie_eps = it.params.tie_eps;
-    G.tiles_per_block = tpb;
     G.block0 = blocks_iter;
-    G.nblocks = std::max(1, (G.ntiles + tpb - 1) / tpb);
+    G.nchunks = (int32_t)n_chunks(h);
+    G.chunks_per_block = cpb;
+    G.nblocks = std::max(1, (G.nchunks + cpb - 1) / cpb);
     blocks_iter += G.nblocks;
     G.vblock0 = blocks_vert;
-    G.vnblocks = std::max(1, std::min(1024, (G.n + 1023) / 1024));
+    G.vnblocks = (int32_t)vert_blocks(h);
     blocks_vert += G.vnblocks;
     max_iters = std::max(max_iters, G.max_iters);
     Lmax = std::max(Lmax, G.L);
   }
   GraphDev *d_desc = reinterpret_cast<GraphDev *>(ws + plan.desc_off);
-  // descriptors travel as kernel arguments, so no host buffer must outlive the call
-  for (int first = 0; first < B; first += kDescPerPack) {
-    DescPack pack{};
-    pack.first = first;
-    pack.count = std::min(kDescPerPack, B - first);
-    for (int k = 0; k < pack.count; ++k) pack.d[k] = desc[first + k];
-    hipLaunchKernelGGL(k_write_desc, dim3(1), dim3(64), 0, stream, pack, d_desc);
-    HIP_TRY(hipGetLastError());
-  }
-  hipLaunchKernelGGL(k_setup, dim3((B + 63) / 64), dim3(64), 0, stream, (const GraphDev *)d_desc, B);
-  HIP_TRY(hipGetLastError());
   bool any_init = false;
   for (int i = 0; i < B; ++i) any_init |= desc[i].init_from_labels != 0;
-  if (any_init) {
-    for (int pass = 0; pass < 2; ++pass) {
-      hipLaunchKernelGGL(k_mstep_init, dim3(blocks_vert), dim3(256), 0, stream, (const GraphDev *)d_desc, B, pass);
+  const int lm = lmax_for(Lmax);
+  const size_t lds = (size_t)((kGroupTiles + 1) * 64 * shape.waves_per_block) * 8;
+  const bool events = g_prof.on;
+
+  // Everything the run enqueues; descriptors travel as kernel arguments, so no
+  // host buffer must outlive the call and the sequence can be captured.
+  auto enqueue = [&](hipStream_t s) -> pmrf_status {
+    for (int first = 0; first < B; first += kDescPerPack) {
+      DescPack pack{};
+      pack.first = first;
+      pack.count = std::min(kDescPerPack, B - first);
+      for (int k = 0; k < pack.count; ++k) pack.d[k] = desc[first + k];
+      hipLaunchKernelGGL(k_write_desc, dim3(1), dim3(64), 0, s, pack, d_desc);
       HIP_TRY(hipGetLastError());
     }
-  }
-  const int lm = lmax_for(Lmax);
-  for (int t = 0; t < max_iters; ++t) {
-    switch (lm) {
-      case 2: hipLaunchKernelGGL(k_iter<2>, dim3(blocks_iter), dim3(threads), 0, stream, (const GraphDev *)d_desc, B, t); break;
-      case 4: hipLaunchKernelGGL(k_iter<4>, dim3(blocks_iter), dim3(threads), 0, stream, (const GraphDev *)d_desc, B, t); break;
-      case 8: hipLaunchKernelGGL(k_iter<8>, dim3(blocks_iter), dim3(threads), 0, stream, (const GraphDev *)d_desc, B, t); break;
-      default: hipLaunchKernelGGL(k_iter<16>, dim3(blocks_iter), dim3(threads), 0, stream, (const GraphDev *)d_desc, B, t); break;
-    }
+    const GraphDev *gd = d_desc;
+    hipLaunchKernelGGL(k_setup, dim3((B + 63) / 64), dim3(64), 0, s, gd, B);
     HIP_TRY(hipGetLastError());
+    if (any_init) {
+      for (int pass = 0; pass < 2; ++pass) {
+        hipLaunchKernelGGL(k_mstep_init, dim3(blocks_vert), dim3(256), 0, s, gd, B, pass);
+        HIP_TRY(hipGetLastError());
+        switch (lm) {
+          case 2: hipLaunchKernelGGL(k_fin_init<2>, dim3(B), dim3(kFinThreads), 0, s, gd, B, pass); break;
+          case 4: hipLaunchKernelGGL(k_fin_init<4>, dim3(B), dim3(kFinThreads), 0, s, gd, B, pass); break;
+          case 8: hipLaunchKernelGGL(k_fin_init<8>, dim3(B), dim3(kFinThreads), 0, s, gd, B, pass); break;
+          default: hipLaunchKernelGGL(k_fin_init<16>, dim3(B), dim3(kFinThreads), 0, s, gd, B, pass); break;
+        }
+        HIP_TRY(hipGetLastError());
+      }
+    }
+    for (int t = 0; t < max_iters; ++t) {
+      if (events) HIP_TRY(prof_mark(s, true));
+      switch (lm) {
+        case 2: hipLaunchKernelGGL(k_iter<2>, dim3(blocks_iter), dim3(threads), lds, s, gd, B, t); break;
+        case 4: hipLaunchKernelGGL(k_iter<4>, dim3(blocks_iter), dim3(threads), lds, s, gd, B, t); break;
+        case 8: hipLaunchKernelGGL(k_iter<8>, dim3(blocks_iter), dim3(threads), lds, s, gd, B, t); break;
+        default: hipLaunchKernelGGL(k_iter<16>, dim3(blocks_iter), dim3(threads), lds, s, gd, B, t); break;
+      }
+      HIP_TRY(hipGetLastError());
+      if (events) HIP_TRY(prof_mark(s, false));
+      switch (lm) {
+        case 2: hipLaunchKernelGGL(k_fin_iter<2>, dim3(B), dim3(kFinThreads), 0, s, gd, B, t); break;
+        case 4: hipLaunchKernelGGL(k_fin_iter<4>, dim3(B), dim3(kFinThreads), 0, s, gd, B, t); break;
+        case 8: hipLaunchKernelGGL(k_fin_iter<8>, dim3(B), dim3(kFinThreads), 0, s, gd, B, t); break;
+        default: hipLaunchKernelGGL(k_fin_iter<16>, dim3(B), dim3(kFinThreads), 0, s, gd, B, t); break;
+      }
+      HIP_TRY(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_final, dim3(blocks_vert), dim3(256), 0, s, gd, B);
+    HIP_TRY(hipGetLastError());
+    return PMRF_OK;
+  };
+
+  // Direct launches when asked for, or while kernel timing is on (the timing
+  // events sit between launches); otherwise one cached HIP graph per distinct
+  // argument set, replayed on the caller's stream.
+  if (shape.mode == kModeDirect || events) return enqueue(stream);
+  std::string key;
+  auto put = [&](const void *p, size_t n) { key.append(static_cast<const char *>(p), n); };
+  put(&B, sizeof B);
+  put(&max_iters, sizeof max_iters);
+  put(&lm, sizeof lm);
+  put(&blocks_iter, sizeof blocks_iter);
+  put(&blocks_vert, sizeof blocks_vert);
+  put(&threads, sizeof threads);
+  put(&lds, sizeof lds);
+  put(&any_init, sizeof any_init);
+  put(&d_desc, sizeof d_desc);
+  put(desc.data(), desc.size() * sizeof(GraphDev));
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  put(&dev, sizeof dev);
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  GraphEntry *entry = nullptr;
+  for (auto it = g_graphs.begin(); it != g_graphs.end(); ++it)
+    if (it->key == key) {
+      g_graphs.splice(g_graphs.begin(), g_graphs, it);
+      entry = &g_graphs.front();
+      break;
+    }
+  if (!entry) {
+    hipStream_t cap = capture_stream(dev);
+    if (!cap) return fail(PMRF_EDEVICE, "could not create the capture stream");
+    HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    pmrf_status st = enqueue(cap);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(cap, &graph);
+    if (st != PMRF_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st;
+    }
+    if (e != hipSuccess) return fail(PMRF_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(PMRF_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    hipEvent_t done = nullptr;
+    HIP_TRY(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+    if (g_graphs.size() >= kGraphCacheSize) {
+      GraphEntry &old = g_graphs.back();
+      (void)hipEventSynchronize(old.done);
+      (void)hipGraphExecDestroy(old.exec);
+      (void)hipEventDestroy(old.done);
+      g_graphs.pop_back();
+    }
+    g_graphs.push_front(GraphEntry{key, exec, done});
+    entry = &g_graphs.front();
   }
-  hipLaunchKernelGGL(k_final, dim3(blocks_vert), dim3(256), 0, stream, (const GraphDev *)d_desc, B);
-  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipGraphLaunch(entry->exec, stream));
+  HIP_TRY(hipEventRecord(entry->done, stream));
   return PMRF_OK;
 }
 
@@ -855,7 +1193,7 @@ extern "C" pmrf_status pmrf_em_batch(int32_t B, const pmrf_em_item *items, void 
 extern "C" pmrf_status pmrf_set_launch(const pmrf_launch *l) {
   clear_error();
   if (!l) return fail(PMRF_EINVAL, "launch is NULL");
-  if (l->mode < 0 || l->mode > 2) return fail(PMRF_EINVAL, "mode must be 0, 1 or 2");
+  if (l->mode < 0 || l->mode > 3) return fail(PMRF_EINVAL, "mode must be 0..3");
   if (l->waves_per_block < 0 || l->waves_per_block > 16) return fail(PMRF_EINVAL, "waves_per_block must be 0..16");
   if (l->tiles_per_wave < 0 || l->tiles_per_wave > 4096) return fail(PMRF_EINVAL, "tiles_per_wave must be 0..4096");
   if (l->blocks_per_cu < 0 || l->blocks_per_cu > 32) return fail(PMRF_EINVAL, "blocks_per_cu must be 0..32");
@@ -869,5 +1207,29 @@ extern "C" pmrf_status pmrf_get_launch(pmrf_launch *l) {
   if (!l) return fail(PMRF_EINVAL, "launch is NULL");
   std::lock_guard<std::mutex> lk(g_launch_mu);
   *l = g_launch;
+  return PMRF_OK;
+}
+
+extern "C" pmrf_status pmrf_profile_begin(void) {
+  clear_error();
+  g_prof.on = true;
+  g_prof.used = 0;
+  return PMRF_OK;
+}
+
+extern "C" pmrf_status pmrf_profile_end(double *total_ms, int64_t *launches) {
+  clear_error();
+  if (!total_ms || !launches) return fail(PMRF_EINVAL, "NULL argument");
+  g_prof.on = false;
+  double sum = 0.0;
+  if (g_prof.used) HIP_TRY(hipEventSynchronize(g_prof.stop[g_prof.used - 1]));
+  for (size_t i = 0; i < g_prof.used; ++i) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, g_prof.start[i], g_prof.stop[i]));
+    sum += ms;
+  }
+  *total_ms = sum;
+  *launches = (int64_t)g_prof.used;
+  g_prof.used = 0;
   return PMRF_OK;
 }

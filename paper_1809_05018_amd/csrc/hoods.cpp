@@ -261,7 +261,9 @@ extern "C" pmrf_status pmrf_build_neighborhoods(int32_t n, const int32_t *row_pt
     }
     DeviceLayout &L = hd->layout;
     L.tiles_off = 0;
-    L.vid_off = align_up((int64_t)hd->tiles.size() * (int64_t)sizeof(TileDesc), 256);
+    L.hptr_off = align_up((int64_t)hd->tiles.size() * (int64_t)sizeof(TileDesc), 256);
+    L.vid_off = L.hptr_off + align_up((hd->H + 1) * 4, 256);
+    hd->hood_ptr32.assign(hd->hood_ptr.begin(), hd->hood_ptr.end());
     L.mask_off = L.vid_off + align_up(hd->M * 4, 256);
     L.total = L.mask_off + align_up((int64_t)hd->mask.size() * 4, 256);
     if (L.total == 0) L.total = 256;
@@ -309,6 +311,9 @@ extern "C" pmrf_status pmrf_hoods_upload(const pmrf_hoods *h, void *d_buf, int64
   hipError_t e = hipSuccess;
   if (!h->tiles.empty())
     e = hipMemcpyAsync(base + h->layout.tiles_off, h->tiles.data(), h->tiles.size() * sizeof(TileDesc),
+                       hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(base + h->layout.hptr_off, h->hood_ptr32.data(), h->hood_ptr32.size() * 4,
                        hipMemcpyHostToDevice, s);
   if (e == hipSuccess && h->M)
     e = hipMemcpyAsync(base + h->layout.vid_off, h->hood_vid.data(), (size_t)h->M * 4, hipMemcpyHostToDevice, s);

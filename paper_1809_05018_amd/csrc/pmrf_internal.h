@@ -37,7 +37,7 @@ static_assert(sizeof(TileDesc) == 24, "TileDesc layout");
 
 // Offsets (bytes) of the arrays inside the uploaded device buffer.
 struct DeviceLayout {
-  int64_t tiles_off, vid_off, mask_off, total;
+  int64_t tiles_off, hptr_off, vid_off, mask_off, total;
 };
 
 inline int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
@@ -53,6 +53,7 @@ struct pmrf_hoods {
   std::vector<int32_t> clique_vid;
   std::vector<int64_t> hood_ptr;
   std::vector<int32_t> hood_vid;
+  std::vector<int32_t> hood_ptr32;  // device copy of hood_ptr
   std::vector<int64_t> owner;  // element owning each vertex
   // device layout, built once
   std::vector<pmrf::TileDesc> tiles;

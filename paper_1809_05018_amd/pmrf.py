@@ -35,6 +35,7 @@ EXPORTED = (
     "pmrf_hoods_export", "pmrf_hoods_upload", "pmrf_replicate_indices", "pmrf_replicate_hood_array",
     "pmrf_hoods_free", "pmrf_em_params_default", "pmrf_em_workspace_bytes", "pmrf_em_run",
     "pmrf_em_batch_workspace_bytes", "pmrf_em_batch", "pmrf_set_launch", "pmrf_get_launch",
+    "pmrf_profile_begin", "pmrf_profile_end",
 )
 
 
@@ -90,6 +91,8 @@ def _load():
     lib.pmrf_em_batch.argtypes = [c_int32, P(EmItem), c_void_p, c_int64, c_void_p]
     lib.pmrf_set_launch.argtypes = [P(Launch)]
     lib.pmrf_get_launch.argtypes = [P(Launch)]
+    lib.pmrf_profile_begin.argtypes = []
+    lib.pmrf_profile_end.argtypes = [P(c_double), P(c_int64)]
     for name in EXPORTED:
         if name not in ("pmrf_last_error", "pmrf_abi_version", "pmrf_hoods_free", "pmrf_em_params_default"):
             getattr(lib, name).restype = c_int32
@@ -257,6 +260,17 @@ def pmrf_get_launch():
             "blocks_per_cu": out.blocks_per_cu}
 
 
+def pmrf_profile_begin():
+    _check(lib.pmrf_profile_begin())
+
+
+def pmrf_profile_end():
+    """(summed milliseconds, launches) of the bracketed EM-iteration launches."""
+    ms, n = c_double(), c_int64()
+    _check(lib.pmrf_profile_end(ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
 # --------------------------------------------------------------------------
 # Convenience: one problem with its device buffers (allocation + marshalling)
 # --------------------------------------------------------------------------
@@ -271,7 +285,8 @@ class Problem:
         self.device = torch.device(device)
         self.n, self.L = int(n), int(L)
         self.hoodbuf = self.hoods.upload(self.device)
-        self.y = torch.as_tensor(np.ascontiguousarray(y, dtype=np.float64)).to(self.device)
+        self.y = torch.zeros(max(1, self.n), dtype=torch.float64, device=self.device)
+        self.y[: self.n].copy_(torch.as_tensor(np.ascontiguousarray(y, dtype=np.float64)))
         self.labels = torch.zeros(max(1, self.n), dtype=torch.int32, device=self.device)
         self.mu = torch.zeros(self.L, dtype=torch.float64, device=self.device)
         self.sigma = torch.ones(self.L, dtype=torch.float64, device=self.device)

@@ -124,7 +124,7 @@ def test_determinism_and_launch_shape_invariance():
     old = pmrf.pmrf_get_launch()
     outs = []
     try:
-        for shape in [(1, 0, 0, 0), (1, 0, 0, 0), (1, 1, 1, 0), (1, 16, 2, 0), (1, 8, 64, 0), (1, 2, 5, 0)]:
+        for shape in [(3, 0, 0, 0), (1, 0, 0, 0), (1, 1, 1, 0), (3, 16, 2, 0), (1, 8, 64, 0), (3, 2, 5, 0)]:
             pmrf.pmrf_set_launch(*shape)
             outs.append(gpu_run(prob, x0, mu0, s0, beta=0.5, max_iters=12))
     finally:
@@ -145,3 +145,24 @@ def test_resume_equals_uninterrupted():
     assert np.array_equal(b["mu"], full["mu"]) and np.array_equal(b["sigma"], full["sigma"])
     assert np.array_equal(np.concatenate([a["trace"], b["trace"]]), full["trace"])
     assert np.array_equal(b["S"], full["S"])
+
+
+def test_graph_replays_match_direct_launches():
+    """The cached HIP graph, replayed several times with eager device work and
+    synchronisation between replays, gives the direct-launch result every time."""
+    g = synth.image_graph(21, 512, 6000, 2)
+    x0, mu0, s0 = init_state(g, 2)
+    prob = pmrf.Problem(g.n, g.row_ptr, g.col_idx, g.y, 2)
+    old = pmrf.pmrf_get_launch()
+    try:
+        pmrf.pmrf_set_launch(3, 0, 0, 0)
+        eager = gpu_run(prob, x0, mu0, s0, beta=0.5, max_iters=10)
+        pmrf.pmrf_set_launch(1, 0, 0, 0)
+        for rep in range(4):
+            scratch = torch.randn(1 << 20, device="cuda", dtype=torch.float64)  # eager work between replays
+            scratch.mul_(2.0).sum().item()
+            out = gpu_run(prob, x0, mu0, s0, beta=0.5, max_iters=10)
+            for k in ("x", "mu", "sigma", "S", "trace", "near_ties", "nonconv"):
+                assert np.array_equal(out[k], eager[k]), (rep, k)
+    finally:
+        pmrf.pmrf_set_launch(**old)

@@ -158,7 +158,7 @@ def test_launch_config_roundtrip():
         pmrf.pmrf_set_launch(1, 8, 4, 2)
         assert pmrf.pmrf_get_launch() == {"mode": 1, "waves_per_block": 8, "tiles_per_wave": 4, "blocks_per_cu": 2}
         with pytest.raises(pmrf.PmrfError):
-            pmrf.pmrf_set_launch(3, 0, 0, 0)
+            pmrf.pmrf_set_launch(4, 0, 0, 0)
         with pytest.raises(pmrf.PmrfError):
             pmrf.pmrf_set_launch(0, 17, 0, 0)
     finally:
