@@ -84,6 +84,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--iters", type=int, default=30, help="EM iterations per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="slice2048_100k",
+                    choices=["slice2048_100k", "batch64", "powerlaw16", "serving"],
+                    help="default: the single 100k-region slice; the others print their own JSON line")
+    ap.add_argument("--requests", type=int, default=128, help="serving: number of requests")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -99,6 +103,10 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     dev = torch.device("cuda:0")
+    if args.workload in ("batch64", "powerlaw16"):
+        return bench_batched(args, dev)
+    if args.workload == "serving":
+        return bench_serving(args, dev)
     L, beta, iters = 2, 0.5, args.iters
     log("generating the 2048x2048 / 100k-region slice")
     g = synth.workload_large()
@@ -178,6 +186,152 @@ def main():
                             "trace_rel": rel(out["trace"], ref["trace"])}
         result["speedup_vs_oracle"] = value / cpu["value"]
     print(json.dumps(result), flush=True)
+
+
+def build_all(graphs, workers=8):
+    """Neighbourhoods of many graphs on host threads (the builder releases the GIL)."""
+    import concurrent.futures as cf
+
+    from paper_1809_05018_amd import pmrf
+
+    with cf.ThreadPoolExecutor(workers) as ex:
+        return list(ex.map(lambda g: pmrf.pmrf_build_neighborhoods(g.n, g.row_ptr, g.col_idx), graphs))
+
+
+def bench_batched(args, dev):
+    """Many graphs: one pmrf_em_run per graph in sequence ("plain") against one
+    pmrf_em_batch over all of them ("batched"), same starting state, same
+    iterations; results must be bitwise equal."""
+    import numpy as np
+    import torch
+
+    from paper_1809_05018_amd import pmrf, synth
+
+    if args.workload == "batch64":
+        L, beta, iters = 2, 0.5, 30
+        log("generating 64 slices (sides log-uniform in [512, 2560])")
+        graphs = synth.workload_batch(64, 3)
+        cfg = {"workload": "batch64", "slices": 64, "sides": "log-uniform 512..2560, seed 3",
+               "regions_per_slice": "side^2/26.2", "labels": L, "beta": beta, "em_iters": iters}
+    else:
+        L, beta, iters = 4, 0.8, 40
+        log("generating 16 power-law graphs of 500k vertices")
+        graphs = synth.workload_skewed(16, 500_000, 4)
+        cfg = {"workload": "powerlaw16", "graphs": 16, "vertices": 500_000, "degrees": "P(d)~d^-2.5 on [3,30]",
+               "labels": L, "beta": beta, "em_iters": iters}
+    t0 = time.perf_counter()
+    hoods = build_all(graphs)
+    log(f"neighbourhoods built in {time.perf_counter() - t0:.1f} s")
+    probs, starts = [], []
+    for g, h in zip(graphs, hoods):
+        prob = pmrf.Problem(g.n, g.row_ptr, g.col_idx, g.y, L, dev, hoods=h)
+        x0 = synth.threshold_labels(g.y, L)
+        prob.set_state(x0, np.zeros(L), np.ones(L))
+        prob.run(pmrf.pmrf_em_params(L=L, beta=beta, max_iters=0, init_from_labels=True))
+        starts.append((prob.labels.clone(), prob.mu.clone(), prob.sigma.clone()))
+        probs.append(prob)
+    torch.cuda.synchronize()
+    params = pmrf.pmrf_em_params(L=L, beta=beta, max_iters=iters)
+    for p in probs:
+        p.prepare(params)
+    M = sum(h.M for h in hoods)
+    b_iter = sum(alg_bytes(h.info) for h in hoods)
+    evals = M * L * iters
+    log(f"graphs={len(graphs)} n={sum(h.n for h in hoods)} M={M} alg bytes/iter={b_iter / 1e9:.3f} GB")
+
+    def reset():
+        for p, (x, mu, sg) in zip(probs, starts):
+            p.labels.copy_(x)
+            p.mu.copy_(mu)
+            p.sigma.copy_(sg)
+
+    def plain():
+        reset()
+        for p in probs:
+            p.run(params)
+
+    items = [p.item(params) for p in probs]
+    ws = torch.empty(pmrf.pmrf_em_batch_workspace_bytes(items), dtype=torch.uint8, device=dev)
+
+    def batched():
+        reset()
+        pmrf.pmrf_em_batch(items, ws)
+
+    def timed(fn, steps):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / steps
+
+    steps = max(1, min(args.steps, 5))
+    t_plain = timed(plain, steps)
+    res_plain = [p.results(params) for p in probs]
+    t_batch = timed(batched, steps)
+    res_batch = [p.results(params) for p in probs]
+    same = all(np.array_equal(a[k], b[k]) for a, b in zip(res_plain, res_batch) for k in ("x", "mu", "sigma", "trace"))
+    pmrf.pmrf_profile_begin()
+    batched()
+    torch.cuda.synchronize()
+    ev_ms, launches = pmrf.pmrf_profile_end()
+    avg = ev_ms * 1e-3 / max(1, launches)
+    achieved = b_iter / avg / 1e9
+    log(f"plain {t_plain * 1e3:.2f} ms/step, batched {t_batch * 1e3:.2f} ms/step, ratio {t_plain / t_batch:.2f}, "
+        f"k_iter {avg * 1e6:.1f} us")
+    out = {"metric": METRIC, "value": evals / t_batch, "unit": "evals/s", "n_gpus": 1, "steps": steps,
+           "warmup": args.warmup, "ms_per_step": t_batch * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic", "config": cfg,
+           "plain": {"value": evals / t_plain, "ms_per_step": t_plain * 1e3},
+           "batched_over_plain": t_plain / t_batch, "bitwise_equal_plain_batched": same,
+           "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": f"k_iter<{4 if L > 2 else 2}>",
+                        "alg_bytes_per_launch": b_iter, "avg_launch_us": avg * 1e6, "launches_timed": launches}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_serving(args, dev):
+    """Continuous batching: requests (slices with 1k..1M regions, log-uniform,
+    L in {2,3,4}, beta 0.5, 30 iterations) arrive as a Poisson process at 70 %
+    of the capacity measured with all requests queued at time 0."""
+    import numpy as np
+
+    from paper_1809_05018_amd import serve, synth
+
+    rng = np.random.default_rng(5)
+    pool_n = 24
+    log(f"generating a pool of {pool_n} slices (regions log-uniform in [1k, 1M])")
+    desc = synth.serving_requests(pool_n, 5)
+    pool = [synth.image_graph(d["seed"], d["side"], d["regions"], 2) for d in desc]
+    reqs_spec = [(int(rng.integers(0, pool_n)), int(rng.integers(2, 5))) for _ in range(args.requests)]
+
+    def make(arrivals):
+        return [serve.Request(rid=j, n=pool[k].n, row_ptr=pool[k].row_ptr, col_idx=pool[k].col_idx, y=pool[k].y,
+                              L=L, beta=0.5, iters=30, arrival=float(a))
+                for j, ((k, L), a) in enumerate(zip(reqs_spec, arrivals))]
+
+    ex = serve.GpuExecutor(dev)
+    budget = 64 << 30
+    warm = serve.Server(ex, budget, iters_per_step=10)
+    warm.run(make(np.zeros(min(8, args.requests))))
+    closed = serve.Server(ex, budget, iters_per_step=10)
+    cap = closed.run(make(np.zeros(args.requests)))
+    lam = 0.7 * cap.throughput_rps
+    log(f"capacity {cap.throughput_rps:.1f} req/s ({cap.evals_per_s:.3g} evals/s); arrivals at {lam:.1f} req/s")
+    arr = synth.poisson_arrivals(args.requests, lam, 5)
+    srv = serve.Server(ex, budget, iters_per_step=10)
+    st = srv.run(make(arr))
+    out = {"metric": "serving latency p50/p99 and throughput", "value": st.evals_per_s, "unit": "evals/s",
+           "n_gpus": 1, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "serving", "requests": args.requests, "pool": pool_n,
+                      "regions": "log-uniform 1k..1M", "labels": "uniform {2,3,4}", "beta": 0.5, "em_iters": 30,
+                      "iters_per_step": 10, "arrival_rate_rps": lam, "hbm_budget_bytes": budget},
+           "p50_s": st.p50_s, "p99_s": st.p99_s, "mean_s": st.mean_s, "throughput_rps": st.throughput_rps,
+           "capacity_rps": cap.throughput_rps, "max_active": st.max_active, "steps": st.steps,
+           "host_build_s_mean": st.build_s_mean, "wall_s": st.wall_s}
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

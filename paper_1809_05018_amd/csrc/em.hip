@@ -67,6 +67,7 @@ __device__ __forceinline__ gptr<T> gbl(T *p) {
 __host__ __device__ constexpr int rec_words(int L) { return 3 * L + 4; }
 constexpr int kRecMax = 3 * kMaxLabels + 4;
 constexpr int kChunkTiles = 8;     // packets per statistics chunk (fixed: part of the result's definition)
+constexpr int kSuperChunks = 8;    // chunks per block and record (fixed: part of the result's definition)
 constexpr int kGroupTiles = 8;     // packets per neighbourhood-sum group (LDS buffer of 512 minima)
 constexpr int kVertPerBlock = 1024;
 
@@ -95,11 +96,10 @@ struct GraphDev {
   double *out_mu, *out_sigma, *out_S, *out_trace;
   int64_t *out_stats, *out_ctr;
   int64_t M;
-  int32_t n, H, ntiles, nchunks, L, P, W, max_iters, early_exit, init_from_labels;
+  int32_t n, H, ntiles, nchunks, nsuper, L, P, W, max_iters, early_exit, init_from_labels;
   double beta, tol, sigma_min, tie_eps;
-  int32_t block0, nblocks;    // blocks of this graph in an iteration launch
+  int32_t block0, nblocks;    // blocks of this graph in an iteration launch (one per superchunk)
   int32_t vblock0, vnblocks;  // blocks of this graph in a vertex-parallel launch
-  int32_t chunks_per_block;
 };
 
 constexpr int kDescPerPack = 12;
@@ -182,7 +182,8 @@ struct LaneStats {
 };
 
 // Sum of a graph's records in a fixed order by a block of 16 waves: thread i
-// adds records i, i + 1024, i + 2048, ... in that order; the lanes of a wave are
+// adds records i, i + 1024, i + 2048, ... in that order (16 words at a time);
+// the lanes of a wave are
 // combined with the butterfly and the waves in wave order.  Thread 0 returns
 // the totals in out[0 .. rec_words(L)).
 constexpr int kFinWaves = 16;
@@ -192,39 +193,40 @@ __device__ __forceinline__ bool word_is_double(int w, int L) { return (w < 3 * L
 template <int LMAX>
 __device__ void sum_records(gptr<const long long> rec, int nrec, int L, long long *out,
                             long long (*part)[kRecMax]) {
-  constexpr int WMAX = rec_words(LMAX);
+  constexpr int WG = rec_words(LMAX) < 16 ? rec_words(LMAX) : 16;  // words per pass
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int words = rec_words(L);
-  long long acc[WMAX];
+  for (int w0 = 0; w0 < words; w0 += WG) {
+    long long acc[WG];
 #pragma unroll
-  for (int w = 0; w < WMAX; ++w) acc[w] = 0;
-#pragma unroll 4
-  for (int r = threadIdx.x; r < nrec; r += kFinThreads) {
-    long long v[WMAX];
+    for (int j = 0; j < WG; ++j) acc[j] = 0;
+    for (int r = threadIdx.x; r < nrec; r += kFinThreads) {
 #pragma unroll
-    for (int w = 0; w < WMAX; ++w) v[w] = w < words ? rec[(size_t)w * nrec + r] : 0;
-#pragma unroll
-    for (int w = 0; w < WMAX; ++w) {
-      if (w >= words) continue;
-      if (word_is_double(w, L))
-        acc[w] = __double_as_longlong(__longlong_as_double(acc[w]) + __longlong_as_double(v[w]));
-      else if (w == 3 * L + 3)
-        acc[w] |= v[w];
-      else
-        acc[w] += v[w];
+      for (int j = 0; j < WG; ++j) {
+        const int w = w0 + j;
+        if (w >= words) continue;
+        const long long v = rec[(size_t)w * nrec + r];
+        if (word_is_double(w, L))
+          acc[j] = __double_as_longlong(__longlong_as_double(acc[j]) + __longlong_as_double(v));
+        else if (w == 3 * L + 3)
+          acc[j] |= v;
+        else
+          acc[j] += v;
+      }
     }
-  }
 #pragma unroll
-  for (int w = 0; w < WMAX; ++w) {
-    if (w >= words) continue;
-    long long r;
-    if (word_is_double(w, L))
-      r = __double_as_longlong(wave_sum(__longlong_as_double(acc[w])));
-    else if (w == 3 * L + 3)
-      r = (long long)((__ballot(acc[w] & 1) ? 1ull : 0ull) | (__ballot(acc[w] & 2) ? 2ull : 0ull));
-    else
-      r = wave_sum(acc[w]);
-    if (lane == 0) part[wave][w] = r;
+    for (int j = 0; j < WG; ++j) {
+      const int w = w0 + j;
+      if (w >= words) continue;
+      long long r;
+      if (word_is_double(w, L))
+        r = __double_as_longlong(wave_sum(__longlong_as_double(acc[j])));
+      else if (w == 3 * L + 3)
+        r = (long long)((__ballot(acc[j] & 1) ? 1ull : 0ull) | (__ballot(acc[j] & 2) ? 2ull : 0ull));
+      else
+        r = wave_sum(acc[j]);
+      if (lane == 0) part[wave][w] = r;
+    }
   }
   __syncthreads();
   if (threadIdx.x != 0) return;
@@ -563,56 +565,150 @@ __device__ void do_large(const Ctx &c, const TileDesc &td, const Theta<LMAX> &th
   }
 }
 
-// One statistics chunk: packets [ck*8, min(ntiles, ck*8+8)).  Packet data is
-// loaded ahead: the stream of packet i+2 and the gathers of packet i+1 are in
-// flight while packet i is computed.
+// Neighbourhood pass over [h0, h1) with the first 64 neighbourhoods' offsets
+// and window values already loaded, used by the chunk fast path.
+constexpr int kPreWindow = 4;  // window values prefetched (larger windows take the plain pass)
+struct HoodPre {
+  int o, s;
+  double prev[kPreWindow];
+};
+
 template <int LMAX>
-__device__ void do_chunk(const Ctx &c, int ck, const Theta<LMAX> &th, gptr<long long> rec, double *mb, uint64_t *pl,
+__device__ __forceinline__ void hood_pass_pre(const Ctx &c, int h0, int h1, int gstart, const HoodPre &pre,
+                                              LaneStats<LMAX> &ls, const double *mb, int lane) {
+  wave_lds_sync();
+  const int slots = c.W + 1;
+  const bool window = c.t >= c.W;
+  {
+    const int h = h0 + lane;
+    const bool act = h < h1;
+    const int o = pre.o - gstart, s = act ? pre.s : 0;
+    double S = 0.0;
+    for (int k = 0; __ballot(k < s); k += 4) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (k + i < s) S = S + mb[o + k + i];
+    }
+    if (act) {
+      c.ring[(size_t)(c.t % slots) * c.H + h] = S;
+      bool conv = window;
+      if (window) {
+#pragma unroll
+        for (int w = 1; w <= kPreWindow; ++w)
+          if (w <= c.W && !(fabs(S - pre.prev[w - 1]) < c.tol)) conv = false;
+      }
+      if (!conv) ls.nonconv += 1;
+      ls.T = ls.T + S;
+    }
+  }
+  wave_lds_sync();
+  if (h0 + 64 < h1) hood_pass<LMAX>(c, h0 + 64, h1, gstart, ls, mb, lane);
+}
+
+__device__ __forceinline__ int bcast(int v, int lane_src) { return __builtin_amdgcn_readlane(v, lane_src); }
+
+// One statistics chunk: packets [ck*8, min(ntiles, ck*8+8)).
+//
+// Fast path (no LARGE packet, window <= 4): the loads of the whole chunk are
+// issued before any computation -- packet descriptors (one per lane), then the
+// id and mask streams of all packets together with the offsets and window
+// values of the chunk's first 64 neighbourhoods, then the label and intensity
+// gathers of all packets -- so a wave waits for memory a few times per chunk
+// instead of at every dependent load of every packet.  The other path goes
+// packet by packet.  Both compute the same values in the same order.
+template <int LMAX>
+__device__ void do_chunk(const Ctx &c, int ck, const Theta<LMAX> &th, long long *part, double *mb, uint64_t *pl,
                          int lane) {
   LaneStats<LMAX> ls;
   ls.clear();
   const int tb = ck * kChunkTiles, te = min(c.ntiles, tb + kChunkTiles);
-  int g0 = tb;  // first packet of the pending neighbourhood group
-  int gstart = 0, ghood = 0;
-  TileDesc tdC = load_tile(c.tiles + tb), tdB{}, tdA{};
-  Stream sC = load_stream(c, tdC, lane), sB{0, 0}, sA{0, 0};
-  Gather gC = load_gather(c, tdC, sC, lane), gB{0, 0.0};
-  if (tb + 1 < te) {
-    tdB = load_tile(c.tiles + tb + 1);
-    sB = load_stream(c, tdB, lane);
-  }
-  for (int ti = tb; ti < te; ++ti) {
-    if (ti + 1 < te) gB = load_gather(c, tdB, sB, lane);
-    if (ti + 2 < te) {
-      tdA = load_tile(c.tiles + ti + 2);
-      sA = load_stream(c, tdA, lane);
-    }
-    if (tdC.kind == kLarge) {
-      if (ti > g0) hood_pass<LMAX>(c, ghood, tdC.hood_start, gstart, ls, mb, lane);
-      do_large<LMAX>(c, tdC, th, ls, mb, pl, lane);
-      g0 = ti + 1;
-    } else {
-      if (ti - g0 == kGroupTiles) {
-        hood_pass<LMAX>(c, ghood, tdC.hood_start, gstart, ls, mb, lane);
-        g0 = ti;
+  const int nt = te - tb;
+  // lane i < nt holds packet i's descriptor; lane nt the next chunk's first
+  TileDesc mine{};
+  if (lane <= nt && tb + lane < c.ntiles) mine = load_tile(c.tiles + tb + lane);
+  const bool any_large = __ballot(lane < nt && mine.kind == kLarge) != 0;
+  const int hend = te < c.ntiles ? bcast(mine.hood_start, nt) : c.H;
+  if (!any_large && c.W <= kPreWindow) {
+    const int h0 = bcast(mine.hood_start, 0), gstart = bcast(mine.elem_start, 0);
+    int v[kChunkTiles];
+    uint32_t am[kChunkTiles];
+#pragma unroll
+    for (int i = 0; i < kChunkTiles; ++i) {
+      v[i] = 0;
+      am[i] = 0;
+      if (i < nt) {
+        const int ne = bcast((int)mine.nelem, i), es = bcast(mine.elem_start, i);
+        const int ms = bcast(mine.mask_start, i), wd = bcast((int)mine.words, i);
+        if (lane < ne) {
+          v[i] = c.vid[es + lane];
+          am[i] = c.mask[ms + wd * lane];
+        }
       }
-      if (ti == g0) {
-        gstart = tdC.elem_start;
-        ghood = tdC.hood_start;
-      }
-      elem_pass<LMAX>(c, tdC, sC, gC, gstart, th, ls, mb, lane);
     }
-    tdC = tdB;
-    sC = sB;
-    gC = gB;
-    tdB = tdA;
-    sB = sA;
+    HoodPre pre{0, 0, {}};
+    {
+      const int h = h0 + lane;
+      if (h < hend) {
+        pre.o = c.hood_ptr[h];
+        pre.s = c.hood_ptr[h + 1] - pre.o;
+        if (c.t >= c.W) {
+          const int slots = c.W + 1;
+#pragma unroll
+          for (int w = 1; w <= kPreWindow; ++w)
+            if (w <= c.W) pre.prev[w - 1] = c.ring[(size_t)((c.t - w) % slots) * c.H + h];
+        }
+      }
+    }
+    int xv[kChunkTiles];
+    double yv[kChunkTiles];
+#pragma unroll
+    for (int i = 0; i < kChunkTiles; ++i) {
+      xv[i] = 0;
+      yv[i] = 0.0;
+      if (i < nt && lane < bcast((int)mine.nelem, i)) {
+        xv[i] = c.xr[v[i]];
+        yv[i] = c.y[v[i]];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kChunkTiles; ++i)
+      if (i < nt) {
+        TileDesc t;
+        t.start_mask = ((uint64_t)(uint32_t)bcast((int)(uint32_t)(mine.start_mask >> 32), i) << 32) |
+                       (uint64_t)(uint32_t)bcast((int)(uint32_t)mine.start_mask, i);
+        t.elem_start = bcast(mine.elem_start, i);
+        t.hood_start = bcast(mine.hood_start, i);
+        t.mask_start = bcast(mine.mask_start, i);
+        t.nelem = (int16_t)bcast((int)mine.nelem, i);
+        t.kind = (uint8_t)bcast((int)mine.kind, i);
+        t.words = (uint8_t)bcast((int)mine.words, i);
+        Stream sd{v[i], am[i]};
+        if (t.words == 2 && lane < t.nelem) sd.am |= (uint64_t)c.mask[t.mask_start + 2 * lane + 1] << 32;
+        elem_pass<LMAX>(c, t, sd, Gather{xv[i], yv[i]}, gstart, th, ls, mb, lane);
+      }
+    hood_pass_pre<LMAX>(c, h0, hend, gstart, pre, ls, mb, lane);
+  } else {
+    int g0 = tb;  // first packet of the pending neighbourhood group
+    int gstart = 0, ghood = 0;
+    for (int i = 0; i < nt; ++i) {
+      const int ti = tb + i;
+      const TileDesc t = load_tile(c.tiles + ti);
+      if (t.kind == kLarge) {
+        if (ti > g0) hood_pass<LMAX>(c, ghood, t.hood_start, gstart, ls, mb, lane);
+        do_large<LMAX>(c, t, th, ls, mb, pl, lane);
+        g0 = ti + 1;
+      } else {
+        if (ti == g0) {
+          gstart = t.elem_start;
+          ghood = t.hood_start;
+        }
+        const Stream sd = load_stream(c, t, lane);
+        elem_pass<LMAX>(c, t, sd, load_gather(c, t, sd, lane), gstart, th, ls, mb, lane);
+      }
+    }
+    if (te > g0) hood_pass<LMAX>(c, ghood, hend, gstart, ls, mb, lane);
   }
-  if (te > g0) {
-    const int hend = te < c.ntiles ? load_tile(c.tiles + te).hood_start : c.H;
-    hood_pass<LMAX>(c, ghood, hend, gstart, ls, mb, lane);
-  }
-  ls.store(rec + ck, (size_t)c.nchunks, c.L, lane);
+  ls.store(part, 1, c.L, lane);
 }
 
 // ------------------------------------------------------------------ kernels
@@ -717,50 +813,89 @@ __global__ __launch_bounds__(1024) void k_fin_init(const GraphDev *graphs, int B
   update_theta(st, tot, G.L, G.sigma_min, pass == 0);
 }
 
-// One EM iteration over every graph of the launch.  Dynamic LDS per wave: 512
-// minima and 64 label-plane words.
+// One EM iteration over every graph of the launch.  Block b of a graph owns
+// superchunk b (chunks 8b .. 8b+7); its waves take the chunks in turn, leave
+// each chunk's statistics in LDS, and the block adds them in chunk order into
+// the superchunk's record.  Dynamic LDS per wave: 512 minima and 64 label-plane
+// words.
 template <int LMAX>
-__global__ __launch_bounds__(1024) void k_iter(const GraphDev *__restrict__ graphs, int B, int t) {
+__device__ __forceinline__ void iter_superchunk(const GraphDev *__restrict__ graphs, int B, int sc, int t,
+                                                long long (*part)[rec_words(LMAX)], double *mb, uint64_t *pl,
+                                                int nw, int wave, int lane) {
+  {
+    const int g = find_graph(graphs, B, sc, false);
+    const GraphDev &G = graphs[g];
+    if (t >= G.max_iters) return;
+    gptr<const GraphState> st = gbl((const GraphState *)G.st);
+    if (st->done) return;
+    Ctx c;
+    c.tiles = gbl(G.tiles);
+    c.vid = gbl(G.vid);
+    c.mask = gbl(G.mask);
+    c.hood_ptr = gbl(G.hood_ptr);
+    c.y = gbl(G.y);
+    c.xr = gbl((const int32_t *)((t & 1) ? G.x1 : G.x0));
+    c.xw = gbl((t & 1) ? G.x0 : G.x1);
+    c.ring = gbl(G.ring);
+    c.H = G.H;
+    c.W = G.W;
+    c.L = G.L;
+    c.P = G.P;
+    c.t = t;
+    c.ntiles = G.ntiles;
+    c.nchunks = G.nchunks;
+    c.beta = G.beta;
+    c.tol = G.tol;
+    c.tie_eps = G.tie_eps;
+    Theta<LMAX> th;
+#pragma unroll
+    for (int l = 0; l < LMAX; ++l) {
+      th.mu[l] = l < c.L ? st->mu[l] : 0.0;
+      th.w[l] = l < c.L ? st->w[l] : 0.0;
+      th.lg[l] = l < c.L ? st->lg[l] : 0.0;
+    }
+    const int b = sc - G.block0;
+    const int c0 = b * kSuperChunks;
+    const int c1 = min(G.nchunks, c0 + kSuperChunks);
+    for (int ck = c0 + wave; ck < c1; ck += nw) do_chunk<LMAX>(c, ck, th, part[ck - c0], mb, pl, lane);
+    __syncthreads();
+    const int words = rec_words(c.L);
+    if (threadIdx.x < words) {
+      const int w = threadIdx.x;
+      long long out;
+      if (word_is_double(w, c.L)) {
+        double acc = 0.0;
+        for (int k = 0; k < c1 - c0; ++k) acc = acc + __longlong_as_double(part[k][w]);
+        out = __double_as_longlong(acc);
+      } else if (w == 3 * c.L + 3) {
+        out = 0;
+        for (int k = 0; k < c1 - c0; ++k) out |= part[k][w];
+      } else {
+        out = 0;
+        for (int k = 0; k < c1 - c0; ++k) out += part[k][w];
+      }
+      gbl(G.rec)[(size_t)w * G.nsuper + b] = out;
+    }
+  }
+}
+
+// PERSIST = false: block b works on superchunk b.  PERSIST = true: a grid sized
+// to the machine whose blocks walk all superchunks.
+template <int LMAX, bool PERSIST>
+__global__ __launch_bounds__(1024) void k_iter(const GraphDev *__restrict__ graphs, int B, int nsuper_total, int t) {
   extern __shared__ double smem[];
-  const int g = find_graph(graphs, B, blockIdx.x, false);
-  const GraphDev &G = graphs[g];
-  if (t >= G.max_iters) return;
-  gptr<const GraphState> st = gbl((const GraphState *)G.st);
-  if (st->done) return;
+  __shared__ long long part[kSuperChunks][rec_words(LMAX)];
   const int nw = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   double *mb = smem + wave * (kGroupTiles * 64 + 64);
   uint64_t *pl = reinterpret_cast<uint64_t *>(mb + kGroupTiles * 64);
-  Ctx c;
-  c.tiles = gbl(G.tiles);
-  c.vid = gbl(G.vid);
-  c.mask = gbl(G.mask);
-  c.hood_ptr = gbl(G.hood_ptr);
-  c.y = gbl(G.y);
-  c.xr = gbl((const int32_t *)((t & 1) ? G.x1 : G.x0));
-  c.xw = gbl((t & 1) ? G.x0 : G.x1);
-  c.ring = gbl(G.ring);
-  c.H = G.H;
-  c.W = G.W;
-  c.L = G.L;
-  c.P = G.P;
-  c.t = t;
-  c.ntiles = G.ntiles;
-  c.nchunks = G.nchunks;
-  c.beta = G.beta;
-  c.tol = G.tol;
-  c.tie_eps = G.tie_eps;
-  Theta<LMAX> th;
-#pragma unroll
-  for (int l = 0; l < LMAX; ++l) {
-    th.mu[l] = l < c.L ? st->mu[l] : 0.0;
-    th.w[l] = l < c.L ? st->w[l] : 0.0;
-    th.lg[l] = l < c.L ? st->lg[l] : 0.0;
+  if constexpr (!PERSIST) {
+    iter_superchunk<LMAX>(graphs, B, blockIdx.x, t, part, mb, pl, nw, wave, lane);
+  } else {
+    for (int sc = blockIdx.x; sc < nsuper_total; sc += gridDim.x) {
+      iter_superchunk<LMAX>(graphs, B, sc, t, part, mb, pl, nw, wave, lane);
+      __syncthreads();  // part[] is reused by the next superchunk
+    }
   }
-  const int b = blockIdx.x - G.block0;
-  const int c0 = b * G.chunks_per_block;
-  const int c1 = min(G.nchunks, c0 + G.chunks_per_block);
-  gptr<long long> rec = gbl(G.rec);
-  for (int ck = c0 + wave; ck < c1; ck += nw) do_chunk<LMAX>(c, ck, th, rec, mb, pl, lane);
 }
 
 // Fold one graph's chunk records into the next parameters and the
@@ -774,7 +909,7 @@ __global__ __launch_bounds__(1024) void k_fin_iter(const GraphDev *graphs, int B
   GraphState *st = G.st;
   if (st->done) return;
   const int L = G.L;
-  sum_records<LMAX>(gbl((const long long *)G.rec), G.nchunks, L, tot, part);
+  sum_records<LMAX>(gbl((const long long *)G.rec), G.nsuper, L, tot, part);
   if (threadIdx.x != 0) return;
   long long errbits = tot[3 * L + 3];
   if (errbits) {
@@ -864,14 +999,15 @@ hipError_t prof_mark(hipStream_t stream, bool begin) {
 constexpr int kModeGraph = 1, kModePersistent = 2, kModeDirect = 3;
 
 struct LaunchShape {
-  int mode, waves_per_block, tiles_per_wave;
+  int mode, waves_per_block, tiles_per_wave, blocks_per_cu;
 };
 
 LaunchShape resolve_shape() {
   std::lock_guard<std::mutex> lk(g_launch_mu);
   LaunchShape s{g_launch.mode > 0 ? g_launch.mode : kModeGraph,
-                g_launch.waves_per_block > 0 ? g_launch.waves_per_block : 4,
-                g_launch.tiles_per_wave > 0 ? g_launch.tiles_per_wave : 1};
+                g_launch.waves_per_block > 0 ? g_launch.waves_per_block : 8,
+                g_launch.tiles_per_wave > 0 ? g_launch.tiles_per_wave : 1,
+                g_launch.blocks_per_cu > 0 ? g_launch.blocks_per_cu : 2};
   return s;
 }
 
@@ -928,7 +1064,8 @@ pmrf_status check_item(const pmrf_em_item &it, int idx) {
 
 int64_t n_chunks(const pmrf_hoods *h) { return ((int64_t)h->tiles.size() + kChunkTiles - 1) / kChunkTiles; }
 int64_t vert_blocks(const pmrf_hoods *h) { return std::max<int64_t>(1, ((int64_t)h->n + kVertPerBlock - 1) / kVertPerBlock); }
-int64_t max_records(const pmrf_hoods *h) { return std::max<int64_t>(std::max<int64_t>(1, n_chunks(h)), vert_blocks(h)); }
+int64_t n_super(const pmrf_hoods *h) { return std::max<int64_t>(1, (n_chunks(h) + kSuperChunks - 1) / kSuperChunks); }
+int64_t max_records(const pmrf_hoods *h) { return std::max<int64_t>(n_super(h), vert_blocks(h)); }
 
 WsPlan plan_workspace(int B, const pmrf_em_item *items) {
   WsPlan p;
@@ -966,8 +1103,6 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
   if (ws_bytes < plan.total) return fail(PMRF_ENOMEM, "workspace smaller than the required size");
   if (reinterpret_cast<uintptr_t>(d_ws) % 256) return fail(PMRF_EINVAL, "workspace must be 256-byte aligned");
   const LaunchShape shape = resolve_shape();
-  if (shape.mode == kModePersistent) return fail(PMRF_EUNSUPPORTED, "the persistent launch mode is not available");
-  const int cpb = shape.waves_per_block * shape.tiles_per_wave;  // chunks per block
   const int threads = shape.waves_per_block * kWave;
   char *ws = static_cast<char *>(d_ws);
   std::vector<GraphDev> desc(B);
@@ -1012,8 +1147,8 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
     G.tie_eps = it.params.tie_eps;
     G.block0 = blocks_iter;
     G.nchunks = (int32_t)n_chunks(h);
-    G.chunks_per_block = cpb;
-    G.nblocks = std::max(1, (G.nchunks + cpb - 1) / cpb);
+    G.nsuper = (int32_t)n_super(h);
+    G.nblocks = G.nsuper;
     blocks_iter += G.nblocks;
     G.vblock0 = blocks_vert;
     G.vnblocks = (int32_t)vert_blocks(h);
@@ -1027,6 +1162,16 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
   const int lm = lmax_for(Lmax);
   const size_t lds = (size_t)((kGroupTiles + 1) * 64 * shape.waves_per_block) * 8;
   const bool events = g_prof.on;
+  // grid of the iteration kernel: one block per superchunk, or in persistent
+  // mode a machine-sized grid whose blocks walk the superchunks
+  int grid_iter = blocks_iter;
+  const bool persist = shape.mode == kModePersistent;
+  if (persist) {
+    int dev = 0, cus = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    grid_iter = std::max(1, std::min(blocks_iter, cus * shape.blocks_per_cu));
+  }
 
   // Everything the run enqueues; descriptors travel as kernel arguments, so no
   // host buffer must outlive the call and the sequence can be captured.
@@ -1057,12 +1202,20 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
     }
     for (int t = 0; t < max_iters; ++t) {
       if (events) HIP_TRY(prof_mark(s, true));
+#define PMRF_LAUNCH_ITER(LM)                                                                                   \
+  do {                                                                                                         \
+    if (persist)                                                                                               \
+      hipLaunchKernelGGL((k_iter<LM, true>), dim3(grid_iter), dim3(threads), lds, s, gd, B, blocks_iter, t);  \
+    else                                                                                                       \
+      hipLaunchKernelGGL((k_iter<LM, false>), dim3(grid_iter), dim3(threads), lds, s, gd, B, blocks_iter, t); \
+  } while (0)
       switch (lm) {
-        case 2: hipLaunchKernelGGL(k_iter<2>, dim3(blocks_iter), dim3(threads), lds, s, gd, B, t); break;
-        case 4: hipLaunchKernelGGL(k_iter<4>, dim3(blocks_iter), dim3(threads), lds, s, gd, B, t); break;
-        case 8: hipLaunchKernelGGL(k_iter<8>, dim3(blocks_iter), dim3(threads), lds, s, gd, B, t); break;
-        default: hipLaunchKernelGGL(k_iter<16>, dim3(blocks_iter), dim3(threads), lds, s, gd, B, t); break;
+        case 2: PMRF_LAUNCH_ITER(2); break;
+        case 4: PMRF_LAUNCH_ITER(4); break;
+        case 8: PMRF_LAUNCH_ITER(8); break;
+        default: PMRF_LAUNCH_ITER(16); break;
       }
+#undef PMRF_LAUNCH_ITER
       HIP_TRY(hipGetLastError());
       if (events) HIP_TRY(prof_mark(s, false));
       switch (lm) {
@@ -1088,6 +1241,7 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
   put(&max_iters, sizeof max_iters);
   put(&lm, sizeof lm);
   put(&blocks_iter, sizeof blocks_iter);
+  put(&grid_iter, sizeof grid_iter);
   put(&blocks_vert, sizeof blocks_vert);
   put(&threads, sizeof threads);
   put(&lds, sizeof lds);

@@ -303,13 +303,16 @@ class Problem:
         self.mu.copy_(torch.as_tensor(np.asarray(mu, dtype=np.float64)))
         self.sigma.copy_(torch.as_tensor(np.asarray(sigma, dtype=np.float64)))
 
-    def prepare(self, params: EmParams):
+    def prepare(self, params: EmParams, workspace: bool = True):
+        """Size the trace/statistics outputs (and, unless batched, the workspace)."""
         import torch
 
         T = max(1, params.max_iters)
         if self.trace is None or self.trace.numel() < T:
             self.trace = torch.zeros(T, dtype=torch.float64, device=self.device)
             self.iter_stats = torch.zeros(2 * T, dtype=torch.int64, device=self.device)
+        if not workspace:
+            return
         need = pmrf_em_workspace_bytes(self.hoods, params)
         if self.ws is None or self.ws.numel() < need:
             self.ws = torch.empty(need, dtype=torch.uint8, device=self.device)
@@ -320,7 +323,8 @@ class Problem:
                     self.trace, self.iter_stats, self.counters, self.ws, params, stream)
 
     def item(self, params: EmParams) -> EmItem:
-        self.prepare(params)
+        """Argument set of this problem for pmrf_em_batch (the batch brings its own workspace)."""
+        self.prepare(params, workspace=False)
         return EmItem(self.hoods.handle.value, self.hoodbuf.data_ptr(), self.y.data_ptr(), self.labels.data_ptr(),
                       self.mu.data_ptr(), self.sigma.data_ptr(), self.hood_energy.data_ptr(), self.trace.data_ptr(),
                       self.iter_stats.data_ptr(), self.counters.data_ptr(), params)

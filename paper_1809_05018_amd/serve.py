@@ -1,0 +1,238 @@
+"""Continuous-batching request loop over pmrf_em_batch.
+
+Requests (one slice each: region graph, intensities, L, beta, iterations)
+arrive over time.  The loop keeps a set of active requests whose graph and
+label state stay resident on the device, and advances all of them together,
+``iters_per_step`` EM iterations per batched call.  Between steps it retires
+finished requests (freeing their memory) and admits arrived ones while the
+device footprint of the active set, including the batch workspace, stays
+within ``hbm_budget`` bytes.  Neighbourhoods of arriving requests are built on
+host worker threads while the device steps.
+
+Splitting a request's iterations over several batched calls gives the same
+labels, parameters, energy trace and neighbourhood sums as one call with all
+iterations (every step starts from the previous step's labels and parameters,
+and batching does not change any result).  The convergence bookkeeping
+(per-iteration non-converged counts, first converged iteration) restarts at
+each call and is reported per step.
+
+The executor does the device work; ``GpuExecutor`` drives the HIP library.  A
+test executor with the same methods can stand in for it.
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import dataclasses
+import time
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    n: int
+    row_ptr: np.ndarray
+    col_idx: np.ndarray
+    y: np.ndarray
+    L: int
+    beta: float
+    iters: int
+    arrival: float = 0.0  # seconds after the start of the run
+    x0: np.ndarray | None = None  # starting labels (default: threshold labelling)
+    # filled in by the server
+    admitted: float | None = None
+    finished: float | None = None
+    build_s: float = 0.0
+    done_iters: int = 0
+    result: dict | None = None
+
+
+def threshold_start(y, L):
+    return np.minimum(L - 1, np.floor(np.asarray(y) * L / 256.0)).astype(np.int32)
+
+
+class GpuExecutor:
+    """Device side of the server: one pmrf.Problem per active request."""
+
+    def __init__(self, device="cuda"):
+        import torch
+
+        from . import pmrf
+
+        self.torch, self.pmrf = torch, pmrf
+        self.device = torch.device(device)
+        self.ws = None
+
+    def build(self, req: Request):
+        """Host work (thread safe): neighbourhood construction."""
+        return self.pmrf.pmrf_build_neighborhoods(req.n, req.row_ptr, req.col_idx)
+
+    def open(self, req: Request, hoods):
+        pm = self.pmrf
+        prob = pm.Problem(req.n, req.row_ptr, req.col_idx, req.y, req.L, self.device, hoods=hoods)
+        x0 = req.x0 if req.x0 is not None else threshold_start(req.y, req.L)
+        prob.set_state(x0, np.zeros(req.L), np.ones(req.L))
+        full = pm.pmrf_em_params(L=req.L, beta=req.beta, max_iters=req.iters)
+        prob.prepare(full, workspace=False)  # trace and statistics buffers for the whole request
+        prob.trace.zero_()
+        prob.iter_stats.zero_()
+        return {"prob": prob, "first": True}
+
+    def footprint(self, req: Request, hoods) -> int:
+        """Exact device bytes one request holds while active (its share of the
+        batch workspace included)."""
+        pm = self.pmrf
+        n1, H1, T = max(1, req.n), max(1, hoods.H), max(1, req.iters)
+        params = pm.pmrf_em_params(L=req.L, beta=req.beta, max_iters=req.iters)
+
+        def t(nbytes):  # torch allocations are rounded to 512 bytes
+            return (nbytes + 511) // 512 * 512
+
+        own = (t(max(256, hoods.device_bytes)) + t(8 * n1) + t(4 * n1) + 2 * t(8 * req.L) + t(8 * H1)
+               + t(8 * pm.NCOUNTERS) + t(8 * T) + t(16 * T))
+        return own + pm.pmrf_em_workspace_bytes(hoods, params)  # plus its share of the batch workspace
+
+    def step(self, active: list, k: int):
+        """Advance every active request by min(k, remaining) iterations in one
+        batched call; returns the iterations done per request."""
+        pm, torch = self.pmrf, self.torch
+        items, steps = [], []
+        for req, slot in active:
+            prob = slot["prob"]
+            todo = min(k, req.iters - req.done_iters)
+            params = pm.pmrf_em_params(L=req.L, beta=req.beta, max_iters=todo, init_from_labels=slot["first"])
+            it = prob.item(params)
+            it.d_trace = prob.trace.data_ptr() + 8 * req.done_iters
+            it.d_iter_stats = prob.iter_stats.data_ptr() + 16 * req.done_iters
+            items.append(it)
+            steps.append(todo)
+            slot["first"] = False
+        need = pm.pmrf_em_batch_workspace_bytes(items)
+        if self.ws is None or self.ws.numel() < need:
+            self.ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        pm.pmrf_em_batch(items, self.ws)
+        torch.cuda.synchronize(self.device)
+        out = []
+        for (req, slot), todo in zip(active, steps):
+            c = slot["prob"].counters.cpu().numpy()
+            if c[pm.CTR_STATUS] != 0:
+                raise pm.PmrfError(int(c[pm.CTR_STATUS]), f"request {req.rid}: device-reported error")
+            out.append(int(c[pm.CTR_ITERS]))
+        return out
+
+    def close(self, req: Request, slot) -> dict:
+        prob = slot["prob"]
+        self.torch.cuda.synchronize(self.device)
+        it = req.done_iters
+        res = {"x": prob.labels[: req.n].cpu().numpy(), "mu": prob.mu.cpu().numpy(),
+               "sigma": prob.sigma.cpu().numpy(), "S": prob.hood_energy[: prob.hoods.H].cpu().numpy(),
+               "trace": prob.trace[:it].cpu().numpy(), "evals": prob.hoods.M * req.L * it}
+        slot["prob"] = None
+        return res
+
+    def workspace_bytes(self) -> int:
+        return 0 if self.ws is None else self.ws.numel()
+
+
+@dataclasses.dataclass
+class ServeStats:
+    requests: int
+    wall_s: float
+    p50_s: float
+    p99_s: float
+    mean_s: float
+    throughput_rps: float
+    evals_per_s: float
+    max_active: int
+    max_footprint: int
+    steps: int
+    build_s_mean: float
+
+
+class Server:
+    def __init__(self, executor, hbm_budget: int, iters_per_step: int = 10, max_active: int = 256,
+                 build_workers: int = 4, clock=time.perf_counter, sleep=time.sleep):
+        self.ex = executor
+        self.budget = int(hbm_budget)
+        self.k = int(iters_per_step)
+        self.max_active = int(max_active)
+        self.pool = cf.ThreadPoolExecutor(max_workers=build_workers)
+        self.clock, self.sleep = clock, sleep
+        self.footprint_log: list[int] = []
+
+    def run(self, requests: list[Request]) -> ServeStats:
+        pending = sorted(requests, key=lambda r: r.arrival)
+        t0 = self.clock()
+        now = lambda: self.clock() - t0
+        builds: dict[int, cf.Future] = {}
+        queue: list[Request] = []  # arrived, waiting for admission
+        active: list[tuple[Request, dict, int]] = []  # (request, slot, footprint)
+        done: list[Request] = []
+        evals = 0
+        steps = 0
+        max_active = 0
+        i = 0
+
+        def build(req):
+            b0 = time.perf_counter()
+            h = self.ex.build(req)
+            return h, time.perf_counter() - b0
+
+        while len(done) < len(pending):
+            t = now()
+            while i < len(pending) and pending[i].arrival <= t:
+                req = pending[i]
+                builds[req.rid] = self.pool.submit(build, req)
+                queue.append(req)
+                i += 1
+            # admission, in arrival order, while the footprint fits
+            used = sum(fp for _, _, fp in active)
+            still = []
+            for req in queue:
+                fut = builds[req.rid]
+                if not fut.done() or len(active) >= self.max_active:
+                    still.append(req)
+                    continue
+                hoods, req.build_s = fut.result()
+                fp = self.ex.footprint(req, hoods)
+                if fp > self.budget:
+                    raise ValueError(f"request {req.rid} needs {fp} bytes, above the budget {self.budget}")
+                if used + fp > self.budget:
+                    still.append(req)
+                    continue
+                slot = self.ex.open(req, hoods)
+                req.admitted = now()
+                active.append((req, slot, fp))
+                used += fp
+                del builds[req.rid]
+            queue = still
+            self.footprint_log.append(used)
+            max_active = max(max_active, len(active))
+            if not active:
+                # idle: wait for the next arrival or build
+                if queue:
+                    next(iter(cf.as_completed([builds[r.rid] for r in queue])))
+                elif i < len(pending):
+                    self.sleep(max(0.0, pending[i].arrival - now()))
+                continue
+            did = self.ex.step([(r, s) for r, s, _ in active], self.k)
+            steps += 1
+            keep = []
+            for (req, slot, fp), d in zip(active, did):
+                req.done_iters += d
+                if req.done_iters >= req.iters or d < min(self.k, req.iters - (req.done_iters - d)):
+                    req.result = self.ex.close(req, slot)
+                    req.finished = now()
+                    evals += req.result["evals"]
+                    done.append(req)
+                else:
+                    keep.append((req, slot, fp))
+            active = keep
+        wall = now()
+        lat = np.array([r.finished - r.arrival for r in done])
+        return ServeStats(requests=len(done), wall_s=wall, p50_s=float(np.percentile(lat, 50)),
+                          p99_s=float(np.percentile(lat, 99)), mean_s=float(lat.mean()),
+                          throughput_rps=len(done) / wall, evals_per_s=evals / wall, max_active=max_active,
+                          max_footprint=max(self.footprint_log) if self.footprint_log else 0, steps=steps,
+                          build_s_mean=float(np.mean([r.build_s for r in done])))

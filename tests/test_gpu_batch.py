@@ -1,0 +1,92 @@
+"""Batched runs (pmrf_em_batch): every graph's result equals its solo run bitwise,
+and matches the oracle (needs the GPU)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1809_05018_amd import pmrf, synth
+from tests.gpu_helpers import compare_runs, init_state
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("x", "mu", "sigma", "S", "trace", "near_ties", "nonconv", "iters", "map_conv_iter", "em_conv_iter",
+        "total_near_ties", "evals", "status")
+
+
+def make_cases():
+    cases = []
+    for i, (side, regions) in enumerate([(256, 1000), (700, 15000), (180, 400), (1024, 30000), (96, 120)]):
+        cases.append((synth.image_graph(600 + i, side, regions, 2), 2, 0.5, 12 + i, False))
+    cases.append((synth.image_graph(610, 400, 4000, 3), 3, 0.5, 9, False))
+    cases.append((synth.powerlaw_graph(611, 8000, phases=4, dmax=70, exponent=2.0), 4, 0.8, 7, False))
+    cases.append((synth.image_graph(612, 256, 1200, 2), 2, 0.0, 20, True))  # early exit inside the batch
+    return cases
+
+
+def setup(case):
+    g, L, beta, iters, early = case
+    x0, mu0, s0 = init_state(g, L)
+    prob = pmrf.Problem(g.n, g.row_ptr, g.col_idx, g.y, L)
+    params = pmrf.pmrf_em_params(L=L, beta=beta, max_iters=iters, early_exit=early)
+    prob.set_state(x0, mu0, s0)
+    return prob, params, (x0, mu0, s0)
+
+
+def test_batch_equals_solo_and_oracle():
+    cases = make_cases()
+    solos, probs = [], []
+    for case in cases:
+        prob, params, start = setup(case)
+        prob.run(params)
+        solos.append(prob.results(params))
+        prob.set_state(*start)
+        probs.append((prob, params))
+    items = [p.item(params) for p, params in probs]
+    ws = torch.empty(pmrf.pmrf_em_batch_workspace_bytes(items), dtype=torch.uint8, device="cuda")
+    pmrf.pmrf_em_batch(items, ws)
+    torch.cuda.synchronize()
+    for (prob, params), solo, case in zip(probs, solos, cases):
+        out = prob.results(params)
+        for k in KEYS:
+            assert np.array_equal(np.asarray(out[k]), np.asarray(solo[k])), (case[0].name, k)
+    # one multi-label graph and one early-exit graph against the oracle
+    for idx in (6, 7):
+        g, L, beta, iters, early = cases[idx]
+        x0, mu0, s0 = init_state(g, L)
+        ref = oracle.OracleGraph(g.n, g.row_ptr, g.col_idx).em_run(g.y, L, beta, x0, mu0, s0, iters,
+                                                                    early_exit=early)
+        compare_runs(probs[idx][0].results(probs[idx][1]), ref, g.name, check_labels=ref["total_near_ties"] == 0)
+
+
+def test_batch_shapes_and_graph_modes_agree():
+    cases = make_cases()[:4]
+    outs = []
+    old = pmrf.pmrf_get_launch()
+    try:
+        for shape in [(1, 0, 0, 0), (3, 2, 0, 0), (1, 16, 0, 0), (2, 8, 0, 1)]:
+            pmrf.pmrf_set_launch(*shape)
+            probs = [setup(c) for c in cases]
+            items = [p.item(params) for p, params, _ in probs]
+            ws = torch.empty(pmrf.pmrf_em_batch_workspace_bytes(items), dtype=torch.uint8, device="cuda")
+            pmrf.pmrf_em_batch(items, ws)
+            outs.append([p.results(params) for p, params, _ in probs])
+    finally:
+        pmrf.pmrf_set_launch(**old)
+    for other in outs[1:]:
+        for a, b in zip(outs[0], other):
+            for k in KEYS:
+                assert np.array_equal(np.asarray(a[k]), np.asarray(b[k])), k
+
+
+def test_batch_rejects_small_workspace_without_writing():
+    prob, params, _ = setup(make_cases()[0])
+    items = [prob.item(params)]
+    need = pmrf.pmrf_em_batch_workspace_bytes(items)
+    ws = torch.empty(need - 256, dtype=torch.uint8, device="cuda")
+    before = prob.labels.clone()
+    with pytest.raises(pmrf.PmrfError) as e:
+        pmrf.pmrf_em_batch(items, ws)
+    assert e.value.code == pmrf.PMRF_ENOMEM
+    torch.cuda.synchronize()
+    assert torch.equal(prob.labels, before)

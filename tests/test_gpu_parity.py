@@ -124,7 +124,8 @@ def test_determinism_and_launch_shape_invariance():
     old = pmrf.pmrf_get_launch()
     outs = []
     try:
-        for shape in [(3, 0, 0, 0), (1, 0, 0, 0), (1, 1, 1, 0), (3, 16, 2, 0), (1, 8, 64, 0), (3, 2, 5, 0)]:
+        for shape in [(3, 0, 0, 0), (1, 0, 0, 0), (1, 1, 0, 0), (3, 16, 0, 0), (2, 8, 0, 1), (2, 4, 0, 3),
+                      (3, 2, 0, 0)]:
             pmrf.pmrf_set_launch(*shape)
             outs.append(gpu_run(prob, x0, mu0, s0, beta=0.5, max_iters=12))
     finally:

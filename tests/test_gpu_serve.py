@@ -1,0 +1,34 @@
+"""Serving on the GPU: requests arriving while others run are batched together;
+each result equals the same request run alone (needs the GPU)."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1809_05018_amd import pmrf, serve, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def test_serving_mix_equals_solo():
+    rng = np.random.default_rng(17)
+    count = 16
+    arrivals = np.cumsum(rng.exponential(0.003, size=count))
+    reqs = []
+    for j in range(count):
+        regions = int(np.exp(rng.uniform(np.log(300), np.log(20000))))
+        side = int(round(np.sqrt(26.2 * regions)))
+        g = synth.image_graph(800 + j, side, regions, 2)
+        reqs.append(serve.Request(rid=j, n=g.n, row_ptr=g.row_ptr, col_idx=g.col_idx, y=g.y,
+                                  L=int(rng.integers(2, 5)), beta=0.5, iters=30, arrival=float(arrivals[j])))
+    ex = serve.GpuExecutor("cuda")
+    sizes = [ex.footprint(r, ex.build(r)) for r in reqs]
+    srv = serve.Server(ex, hbm_budget=int(sum(sizes) * 0.5), iters_per_step=10)
+    stats = srv.run(reqs)
+    assert stats.requests == count and max(srv.footprint_log) <= srv.budget
+    assert stats.max_active > 1  # work really overlapped
+    for r in reqs:
+        solo = pmrf.solve(r.n, r.row_ptr, r.col_idx, r.y, serve.threshold_start(r.y, r.L), np.zeros(r.L),
+                          np.ones(r.L), pmrf.pmrf_em_params(L=r.L, beta=r.beta, max_iters=r.iters,
+                                                            init_from_labels=True))
+        for k in ("x", "mu", "sigma", "S", "trace"):
+            assert np.array_equal(np.asarray(r.result[k]), np.asarray(solo[k])), (r.rid, k)

@@ -1,0 +1,98 @@
+"""The serving loop's scheduling on the CPU, with an executor that runs the
+oracle instead of the GPU and a virtual clock: admission by footprint,
+retirement, latency bookkeeping, and results equal to one uninterrupted run."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1809_05018_amd import serve, synth
+
+
+class VirtualClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+    def sleep(self, dt):
+        self.t += max(dt, 1e-6)
+
+
+class OracleExecutor:
+    """Same methods as serve.GpuExecutor; each step costs 1 ms of virtual time."""
+
+    def __init__(self, clock):
+        self.clock = clock
+
+    def build(self, req):
+        return oracle.OracleGraph(req.n, req.row_ptr, req.col_idx)
+
+    def footprint(self, req, og):
+        return 1000 + 40 * og.M + 16 * req.n
+
+    def open(self, req, og):
+        x0 = serve.threshold_start(req.y, req.L)
+        return {"og": og, "x": x0, "mu": np.zeros(req.L), "sigma": np.ones(req.L), "first": True, "trace": []}
+
+    def step(self, active, k):
+        self.clock.t += 1e-3
+        out = []
+        for req, slot in active:
+            todo = min(k, req.iters - req.done_iters)
+            r = slot["og"].em_run(req.y, req.L, req.beta, slot["x"], slot["mu"], slot["sigma"], todo,
+                                  init_from_labels=slot["first"])
+            slot.update(x=r["x"], mu=r["mu"], sigma=r["sigma"], first=False, S=r["S"])
+            slot["trace"].extend(r["trace"].tolist())
+            out.append(r["iters"])
+        return out
+
+    def close(self, req, slot):
+        return {"x": slot["x"], "mu": slot["mu"], "sigma": slot["sigma"], "S": slot["S"],
+                "trace": np.array(slot["trace"]), "evals": slot["og"].M * req.L * req.done_iters}
+
+
+def make_requests(count=12, seed=9):
+    rng = np.random.default_rng(seed)
+    arrivals = np.cumsum(rng.exponential(0.002, size=count))
+    reqs = []
+    for j in range(count):
+        side = int(rng.integers(48, 160))
+        g = synth.image_graph(700 + j, side, max(20, side * side // 30), 2)
+        L = int(rng.integers(2, 5))
+        reqs.append(serve.Request(rid=j, n=g.n, row_ptr=g.row_ptr, col_idx=g.col_idx, y=g.y, L=L, beta=0.5,
+                                  iters=int(rng.integers(5, 16)), arrival=float(arrivals[j])))
+    return reqs
+
+
+@pytest.mark.parametrize("budget_scale,k", [(100.0, 4), (1.2, 3), (3.0, 7)])
+def test_server_results_and_admission(budget_scale, k):
+    clock = VirtualClock()
+    ex = OracleExecutor(clock)
+    reqs = make_requests()
+    biggest = max(ex.footprint(r, ex.build(r)) for r in reqs)
+    srv = serve.Server(ex, hbm_budget=int(biggest * budget_scale), iters_per_step=k, clock=clock, sleep=clock.sleep)
+    stats = srv.run(reqs)
+    assert stats.requests == len(reqs)
+    assert max(srv.footprint_log) <= srv.budget
+    if budget_scale < 2:
+        assert stats.max_active < len(reqs)  # admission held requests back
+        assert any(r.admitted > r.arrival for r in reqs)
+    for r in reqs:
+        og = oracle.OracleGraph(r.n, r.row_ptr, r.col_idx)
+        x0 = serve.threshold_start(r.y, r.L)
+        ref = og.em_run(r.y, r.L, r.beta, x0, np.zeros(r.L), np.ones(r.L), r.iters, init_from_labels=True)
+        assert np.array_equal(r.result["x"], ref["x"])
+        assert np.array_equal(r.result["mu"], ref["mu"]) and np.array_equal(r.result["sigma"], ref["sigma"])
+        assert np.array_equal(r.result["trace"], ref["trace"]) and np.array_equal(r.result["S"], ref["S"])
+        assert r.finished >= r.admitted >= r.arrival
+    assert stats.p99_s >= stats.p50_s > 0
+
+
+def test_request_above_budget_is_refused():
+    clock = VirtualClock()
+    ex = OracleExecutor(clock)
+    reqs = make_requests(count=2)
+    srv = serve.Server(ex, hbm_budget=100, clock=clock, sleep=clock.sleep)
+    with pytest.raises(ValueError):
+        srv.run(reqs)
