@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "vertex-label energy evals/sec + HBM GB/s % peak; batched vs plain at bit-exact labels"
 HBM_PEAK_GBS = 8000.0
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_iter_slice2048_100k_counters.json")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_iter_slice2048_100k_traffic.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_1809_05018_amd", "csrc", "em.hip")
 
 
@@ -51,30 +51,58 @@ def kernel_sha() -> str:
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def measured_traffic(per_launch_units: str):
-    """HBM bytes per launch from the committed counter summary, if it was taken
-    on the current kernel source; else None."""
+def measured_traffic():
+    """HBM bytes per launch (read + written) from the committed counter summary,
+    if it was taken on the current kernel source; else None.  The summary holds
+    one line ``traffic: {json}`` with ``kernel_sha`` and ``bytes_per_launch``."""
     try:
-        d = json.load(open(COUNTERS_FILE))
-    except (OSError, ValueError):
+        lines = open(COUNTERS_FILE).read().splitlines()
+    except OSError:
         return None
-    if d.get("kernel_sha") != kernel_sha():
-        return None
-    return d.get("bytes_per_launch")
+    for line in lines:
+        if line.startswith("traffic: "):
+            try:
+                d = json.loads(line[len("traffic: "):])
+            except ValueError:
+                return None
+            if d.get("kernel_sha") != kernel_sha():
+                return None
+            return d.get("bytes_per_launch")
+    return None
 
 
-def cpu_baseline(g, L, beta, iters, x0, M):
+def copy_calibration(dev, mib=256, reps=3):
+    """A plain device copy of known size, for scaling the FETCH_SIZE and
+    WRITE_SIZE counters: each copy reads and writes ``mib`` MiB."""
+    import torch
+
+    a = torch.ones(mib << 17, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": mib << 20, "copies": reps}), flush=True)
+
+
+def cpu_baseline(g, L, beta, iters, x0, M, min_seconds=10.0, max_reps=12):
+    """The oracle's EM loop on the same problem, repeated until about
+    ``min_seconds`` of CPU work; the rate is the mean over the repetitions."""
     import numpy as np
 
     import oracle
 
     og = oracle.OracleGraph(g.n, g.row_ptr, g.col_idx)
-    t0 = time.perf_counter()
-    ref = og.em_run(g.y, L, beta, x0, np.zeros(L), np.ones(L), iters, init_from_labels=True)
-    dt = time.perf_counter() - t0
+    reps, total, ref = 0, 0.0, None
+    while reps < max_reps and (reps == 0 or total < min_seconds):
+        t0 = time.perf_counter()
+        ref = og.em_run(g.y, L, beta, x0, np.zeros(L), np.ones(L), iters, init_from_labels=True)
+        total += time.perf_counter() - t0
+        reps += 1
+    dt = total / reps
     return ref, {"value": M * L * iters / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
-                 "sample": f"full workload, {iters} EM iterations, serial C oracle (-O2), EM loop only, {dt:.2f} s",
-                 "seconds": round(dt, 3), "cpu": platform.processor() or platform.machine()}
+                 "sample": f"the full workload, {iters} EM iterations, run {reps} times ({total:.1f} s); "
+                           "serial C oracle (-O2), EM loop only",
+                 "seconds_per_run": round(dt, 3), "cpu": platform.processor() or platform.machine()}
 
 
 def main():
@@ -88,6 +116,8 @@ def main():
                     choices=["slice2048_100k", "batch64", "powerlaw16", "serving"],
                     help="default: the single 100k-region slice; the others print their own JSON line")
     ap.add_argument("--requests", type=int, default=128, help="serving: number of requests")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy (scale for the HBM byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -103,6 +133,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        return copy_calibration(dev)
     if args.workload in ("batch64", "powerlaw16"):
         return bench_batched(args, dev)
     if args.workload == "serving":
@@ -169,7 +201,7 @@ def main():
                    "neighbourhoods": info.H, "elements": info.M, "labels": L, "beta": beta, "em_iters": iters,
                    "mode": "HIP graph of two kernels per EM iteration"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("bytes"),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "k_iter<2>", "alg_bytes_per_launch": b_launch,
                      "avg_launch_us": avg_launch_s * 1e6, "launches_timed": launches,
                      "timing": "HIP events around each EM-iteration launch, second timed region of the same steps"},

@@ -607,6 +607,280 @@ __device__ __forceinline__ void hood_pass_pre(const Ctx &c, int h0, int h1, int 
 
 __device__ __forceinline__ int bcast(int v, int lane_src) { return __builtin_amdgcn_readlane(v, lane_src); }
 
+// ---------------------------------------------------------------- lean path
+// Per-wave LDS: 512 minima, 64 label-plane words (LARGE packets), and an owner
+// list of kOwnCap entries (y - mu_a as double, a as int).
+constexpr int kOwnCap = 128;
+constexpr int kWaveLds = kGroupTiles * 64 + 64 + kOwnCap + kOwnCap / 2;  // in doubles
+
+template <int LMAX>
+struct ChunkStats {
+  double s1[LMAX], s2[LMAX];  // per lane: sums of (y - mu_a), (y - mu_a)^2 of the owners it took
+  int cnt[LMAX];
+  double T;                   // per lane: sum of the neighbourhood totals it took
+  int ties, nonconv, err;     // uniform across the wave
+  __device__ void clear() {
+#pragma unroll
+    for (int l = 0; l < LMAX; ++l) {
+      s1[l] = 0.0;
+      s2[l] = 0.0;
+      cnt[l] = 0;
+    }
+    T = 0.0;
+    ties = nonconv = err = 0;
+  }
+  // owner entries k (in list order) go to lane k % 64, in order
+  __device__ void take_owners(const double *od, const int *oa, int count, int lane) {
+    for (int k0 = 0; k0 < count; k0 += 64) {
+      const int k = k0 + lane;
+      if (k < count) {
+        const double d = od[k];
+        const int a = oa[k];
+        const double d2 = d * d;
+#pragma unroll
+        for (int l = 0; l < LMAX; ++l)
+          if (a == l) {
+            cnt[l] += 1;
+            s1[l] = s1[l] + d;
+            s2[l] = s2[l] + d2;
+          }
+      }
+    }
+  }
+  // butterfly over the lanes; lane 0 writes the record row (LDS)
+  __device__ void store(long long *row, int L, int lane) {
+#pragma unroll
+    for (int l = 0; l < LMAX; ++l)
+      if (l < L) {
+        const double a = wave_sum(s1[l]);
+        const double b = wave_sum(s2[l]);
+        if (lane == 0) {
+          row[3 * l + 1] = __double_as_longlong(a);
+          row[3 * l + 2] = __double_as_longlong(b);
+        }
+      }
+#pragma unroll
+    for (int l0 = 0; l0 < LMAX; l0 += 4) {
+      long long packed = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (l0 + q < LMAX) packed |= (long long)cnt[l0 + q] << (16 * q);
+      packed = wave_sum(packed);  // per-chunk counts stay below 2^16
+      if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (l0 + q < L) row[3 * (l0 + q)] = (packed >> (16 * q)) & 0xffff;
+    }
+    const double t = wave_sum(T);
+    const long long e = (__ballot(err & 1) ? 1 : 0) | (__ballot(err & 2) ? 2 : 0);
+    if (lane == 0) {
+      row[3 * L] = __double_as_longlong(t);
+      row[3 * L + 1] = ties;
+      row[3 * L + 2] = nonconv;
+      row[3 * L + 3] = e;
+    }
+  }
+};
+
+// Element pass of one SMALL or MID packet on the lean path.
+template <int LMAX>
+__device__ __forceinline__ void lean_elem(const Ctx &c, const TileDesc &td, int v, uint32_t am_lo, int xv, double yv,
+                                          int gstart, const Theta<LMAX> &th, uint64_t below, ChunkStats<LMAX> &cs,
+                                          double *mb, double *od, int *oa, int &ocount, int lane) {
+  const bool valid = lane < td.nelem;
+  if (valid && (unsigned)xv >= (unsigned)c.L) cs.err |= 1;
+  uint64_t planes[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (k < c.P) planes[k] = __ballot(valid && ((xv >> k) & 1));
+  const int base = 63 - __clzll(td.start_mask & below);
+  const int j = lane - base;
+  int deg, cnt[LMAX];
+  bool owner;
+  if (td.words == 1) {
+    const uint32_t self = 1u << (j & 31);
+    owner = valid && (am_lo & self);
+    const uint32_t nbr = am_lo & ~self;
+    deg = __popc(nbr);
+#pragma unroll
+    for (int l = 0; l < LMAX; ++l) {
+      uint32_t eq = ~0u;
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (k < c.P) {
+          const uint32_t pk = (uint32_t)(planes[k] >> base);
+          eq &= ((l >> k) & 1) ? pk : ~pk;
+        }
+      cnt[l] = __popc(nbr & eq);
+    }
+  } else {
+    uint64_t am = am_lo;
+    if (valid) am |= (uint64_t)c.mask[td.mask_start + 2 * lane + 1] << 32;
+    const uint64_t self = 1ull << (j & 63);
+    owner = valid && (am & self);
+    const uint64_t nbr = am & ~self;
+    deg = __popcll(nbr);
+#pragma unroll
+    for (int l = 0; l < LMAX; ++l) {
+      uint64_t eq = ~0ull;
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (k < c.P) {
+          const uint64_t pk = planes[k] >> base;
+          eq &= ((l >> k) & 1) ? pk : ~pk;
+        }
+      cnt[l] = __popcll(nbr & eq);
+    }
+  }
+  double m, gap, dsel;
+  int a;
+  if constexpr (LMAX == 2) {
+    const double d0 = yv - th.mu[0], d1 = yv - th.mu[1];
+    double e0 = (d0 * d0) * th.w[0] + th.lg[0];
+    double e1 = (d1 * d1) * th.w[1] + th.lg[1];
+    e0 = e0 + c.beta * (double)(deg - cnt[0]);
+    e1 = e1 + c.beta * (double)(deg - cnt[1]);
+    const bool one = e1 < e0;
+    a = one ? 1 : 0;
+    m = one ? e1 : e0;
+    gap = one ? e0 - e1 : e1 - e0;
+    dsel = one ? d1 : d0;
+  } else {
+    element_energy<LMAX>(th, c.L, c.beta, yv, deg, cnt, m, a, gap, dsel);
+  }
+  const uint64_t ob = __ballot(owner);
+  if (ob) {
+    const int idx = ocount + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(ob >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)ob, 0u));
+    if (owner) {
+      c.xw[v] = a;
+      od[idx] = dsel;
+      oa[idx] = a;
+    }
+    ocount += __popcll(ob);
+    cs.ties += __popcll(__ballot(owner && gap < c.tie_eps));
+  }
+  if (valid) mb[td.elem_start - gstart + lane] = m;
+}
+
+// Neighbourhood pass of the lean path: lane per neighbourhood, offsets and
+// window values of the first 64 already loaded.
+template <int LMAX>
+__device__ __forceinline__ void lean_hoods(const Ctx &c, int h0, int h1, int gstart, const HoodPre &pre,
+                                           ChunkStats<LMAX> &cs, const double *mb, int lane) {
+  const int slots = c.W + 1;
+  const bool window = c.t >= c.W;
+  for (int hb = h0; hb < h1; hb += 64) {
+    const int h = hb + lane;
+    const bool act = h < h1;
+    int o = 0, s = 0;
+    double prev[kPreWindow];
+    if (hb == h0) {
+      o = pre.o - gstart;
+      s = act ? pre.s : 0;
+#pragma unroll
+      for (int w = 0; w < kPreWindow; ++w) prev[w] = pre.prev[w];
+    } else if (act) {
+      const int p0 = c.hood_ptr[h];
+      o = p0 - gstart;
+      s = c.hood_ptr[h + 1] - p0;
+      if (window)
+#pragma unroll
+        for (int w = 1; w <= kPreWindow; ++w)
+          if (w <= c.W) prev[w - 1] = c.ring[(size_t)((c.t - w) % slots) * c.H + h];
+    }
+    double S = 0.0;
+    for (int k = 0; __ballot(k < s); k += 4) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (k + i < s) S = S + mb[o + k + i];
+    }
+    bool conv = true;
+    if (act) {
+      c.ring[(size_t)(c.t % slots) * c.H + h] = S;
+      conv = window;
+      if (window)
+#pragma unroll
+        for (int w = 1; w <= kPreWindow; ++w)
+          if (w <= c.W && !(fabs(S - prev[w - 1]) < c.tol)) conv = false;
+      cs.T = cs.T + S;
+    }
+    cs.nonconv += __popcll(__ballot(act && !conv));
+  }
+}
+
+// Lean chunk (no LARGE packet, window <= 4): loads of the whole chunk first,
+// then the element passes, the owner list and the neighbourhood pass.
+template <int LMAX>
+__device__ void chunk_lean(const Ctx &c, int tb, int te, int hend, const Theta<LMAX> &th, long long *row,
+                           double *mb, double *od, int *oa, int lane) {
+  ChunkStats<LMAX> cs;
+  cs.clear();
+  const int nt = te - tb;
+  const uint64_t below = (2ull << lane) - 1ull;  // lanes 0..lane
+  const TileDesc t0 = load_tile(c.tiles + tb);
+  const int h0 = t0.hood_start, gstart = t0.elem_start;
+  int v[kChunkTiles];
+  uint32_t am[kChunkTiles];
+#pragma unroll
+  for (int i = 0; i < kChunkTiles; ++i) {
+    v[i] = 0;
+    am[i] = 0;
+    if (i < nt) {
+      const TileDesc t = load_tile(c.tiles + tb + i);
+      if (lane < t.nelem) {
+        v[i] = c.vid[t.elem_start + lane];
+        am[i] = c.mask[t.mask_start + t.words * lane];
+      }
+    }
+  }
+  HoodPre pre{0, 0, {}};
+  {
+    const int h = h0 + lane;
+    if (h < hend) {
+      pre.o = c.hood_ptr[h];
+      pre.s = c.hood_ptr[h + 1] - pre.o;
+      if (c.t >= c.W) {
+        const int slots = c.W + 1;
+#pragma unroll
+        for (int w = 1; w <= kPreWindow; ++w)
+          if (w <= c.W) pre.prev[w - 1] = c.ring[(size_t)((c.t - w) % slots) * c.H + h];
+      }
+    }
+  }
+  int xv[kChunkTiles];
+  double yv[kChunkTiles];
+#pragma unroll
+  for (int i = 0; i < kChunkTiles; ++i) {
+    xv[i] = 0;
+    yv[i] = 0.0;
+    if (i < nt && lane < load_tile(c.tiles + tb + i).nelem) {
+      xv[i] = c.xr[v[i]];
+      yv[i] = c.y[v[i]];
+    }
+  }
+  int ocount = 0;
+#pragma unroll
+  for (int i = 0; i < kChunkTiles; ++i)
+    if (i < nt) {
+      if (ocount > kOwnCap - 64) {
+        wave_lds_sync();
+        cs.take_owners(od, oa, ocount, lane);
+        ocount = 0;
+        wave_lds_sync();
+      }
+      lean_elem<LMAX>(c, load_tile(c.tiles + tb + i), v[i], am[i], xv[i], yv[i], gstart, th, below, cs, mb, od, oa,
+                      ocount, lane);
+    }
+  wave_lds_sync();
+  cs.take_owners(od, oa, ocount, lane);
+  lean_hoods<LMAX>(c, h0, hend, gstart, pre, cs, mb, lane);
+  wave_lds_sync();
+  cs.store(row, c.L, lane);
+}
+
+
+
 // One statistics chunk: packets [ck*8, min(ntiles, ck*8+8)).
 //
 // Fast path (no LARGE packet, window <= 4): the loads of the whole chunk are
@@ -615,10 +889,12 @@ __device__ __forceinline__ int bcast(int v, int lane_src) { return __builtin_amd
 // values of the chunk's first 64 neighbourhoods, then the label and intensity
 // gathers of all packets -- so a wave waits for memory a few times per chunk
 // instead of at every dependent load of every packet.  The other path goes
-// packet by packet.  Both compute the same values in the same order.
+// packet by packet.  Which path a chunk takes depends only on the graph and
+// the window length, never on the launch shape, so results stay independent of
+// it (the two paths add the owner statistics in different lane orders).
 template <int LMAX>
 __device__ void do_chunk(const Ctx &c, int ck, const Theta<LMAX> &th, long long *part, double *mb, uint64_t *pl,
-                         int lane) {
+                         double *od, int *oa, int lane) {
   LaneStats<LMAX> ls;
   ls.clear();
   const int tb = ck * kChunkTiles, te = min(c.ntiles, tb + kChunkTiles);
@@ -629,64 +905,8 @@ __device__ void do_chunk(const Ctx &c, int ck, const Theta<LMAX> &th, long long 
   const bool any_large = __ballot(lane < nt && mine.kind == kLarge) != 0;
   const int hend = te < c.ntiles ? bcast(mine.hood_start, nt) : c.H;
   if (!any_large && c.W <= kPreWindow) {
-    const int h0 = bcast(mine.hood_start, 0), gstart = bcast(mine.elem_start, 0);
-    int v[kChunkTiles];
-    uint32_t am[kChunkTiles];
-#pragma unroll
-    for (int i = 0; i < kChunkTiles; ++i) {
-      v[i] = 0;
-      am[i] = 0;
-      if (i < nt) {
-        const int ne = bcast((int)mine.nelem, i), es = bcast(mine.elem_start, i);
-        const int ms = bcast(mine.mask_start, i), wd = bcast((int)mine.words, i);
-        if (lane < ne) {
-          v[i] = c.vid[es + lane];
-          am[i] = c.mask[ms + wd * lane];
-        }
-      }
-    }
-    HoodPre pre{0, 0, {}};
-    {
-      const int h = h0 + lane;
-      if (h < hend) {
-        pre.o = c.hood_ptr[h];
-        pre.s = c.hood_ptr[h + 1] - pre.o;
-        if (c.t >= c.W) {
-          const int slots = c.W + 1;
-#pragma unroll
-          for (int w = 1; w <= kPreWindow; ++w)
-            if (w <= c.W) pre.prev[w - 1] = c.ring[(size_t)((c.t - w) % slots) * c.H + h];
-        }
-      }
-    }
-    int xv[kChunkTiles];
-    double yv[kChunkTiles];
-#pragma unroll
-    for (int i = 0; i < kChunkTiles; ++i) {
-      xv[i] = 0;
-      yv[i] = 0.0;
-      if (i < nt && lane < bcast((int)mine.nelem, i)) {
-        xv[i] = c.xr[v[i]];
-        yv[i] = c.y[v[i]];
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < kChunkTiles; ++i)
-      if (i < nt) {
-        TileDesc t;
-        t.start_mask = ((uint64_t)(uint32_t)bcast((int)(uint32_t)(mine.start_mask >> 32), i) << 32) |
-                       (uint64_t)(uint32_t)bcast((int)(uint32_t)mine.start_mask, i);
-        t.elem_start = bcast(mine.elem_start, i);
-        t.hood_start = bcast(mine.hood_start, i);
-        t.mask_start = bcast(mine.mask_start, i);
-        t.nelem = (int16_t)bcast((int)mine.nelem, i);
-        t.kind = (uint8_t)bcast((int)mine.kind, i);
-        t.words = (uint8_t)bcast((int)mine.words, i);
-        Stream sd{v[i], am[i]};
-        if (t.words == 2 && lane < t.nelem) sd.am |= (uint64_t)c.mask[t.mask_start + 2 * lane + 1] << 32;
-        elem_pass<LMAX>(c, t, sd, Gather{xv[i], yv[i]}, gstart, th, ls, mb, lane);
-      }
-    hood_pass_pre<LMAX>(c, h0, hend, gstart, pre, ls, mb, lane);
+    chunk_lean<LMAX>(c, tb, te, hend, th, part, mb, od, oa, lane);
+    return;
   } else {
     int g0 = tb;  // first packet of the pending neighbourhood group
     int gstart = 0, ghood = 0;
@@ -821,13 +1041,13 @@ __global__ __launch_bounds__(1024) void k_fin_init(const GraphDev *graphs, int B
 template <int LMAX>
 __device__ __forceinline__ void iter_superchunk(const GraphDev *__restrict__ graphs, int B, int sc, int t,
                                                 long long (*part)[rec_words(LMAX)], double *mb, uint64_t *pl,
-                                                int nw, int wave, int lane) {
+                                                double *od, int *oa, int nw, int wave, int lane) {
   {
     const int g = find_graph(graphs, B, sc, false);
     const GraphDev &G = graphs[g];
     if (t >= G.max_iters) return;
     gptr<const GraphState> st = gbl((const GraphState *)G.st);
-    if (st->done) return;
+    const int done = st->done;  // read with the parameters below (one wait)
     Ctx c;
     c.tiles = gbl(G.tiles);
     c.vid = gbl(G.vid);
@@ -854,10 +1074,11 @@ __device__ __forceinline__ void iter_superchunk(const GraphDev *__restrict__ gra
       th.w[l] = l < c.L ? st->w[l] : 0.0;
       th.lg[l] = l < c.L ? st->lg[l] : 0.0;
     }
+    if (done) return;
     const int b = sc - G.block0;
     const int c0 = b * kSuperChunks;
     const int c1 = min(G.nchunks, c0 + kSuperChunks);
-    for (int ck = c0 + wave; ck < c1; ck += nw) do_chunk<LMAX>(c, ck, th, part[ck - c0], mb, pl, lane);
+    for (int ck = c0 + wave; ck < c1; ck += nw) do_chunk<LMAX>(c, ck, th, part[ck - c0], mb, pl, od, oa, lane);
     __syncthreads();
     const int words = rec_words(c.L);
     if (threadIdx.x < words) {
@@ -886,57 +1107,82 @@ __global__ __launch_bounds__(1024) void k_iter(const GraphDev *__restrict__ grap
   extern __shared__ double smem[];
   __shared__ long long part[kSuperChunks][rec_words(LMAX)];
   const int nw = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  double *mb = smem + wave * (kGroupTiles * 64 + 64);
+  double *mb = smem + wave * kWaveLds;
   uint64_t *pl = reinterpret_cast<uint64_t *>(mb + kGroupTiles * 64);
+  double *od = mb + kGroupTiles * 64 + 64;
+  int *oa = reinterpret_cast<int *>(od + kOwnCap);
   if constexpr (!PERSIST) {
-    iter_superchunk<LMAX>(graphs, B, blockIdx.x, t, part, mb, pl, nw, wave, lane);
+    iter_superchunk<LMAX>(graphs, B, blockIdx.x, t, part, mb, pl, od, oa, nw, wave, lane);
   } else {
     for (int sc = blockIdx.x; sc < nsuper_total; sc += gridDim.x) {
-      iter_superchunk<LMAX>(graphs, B, sc, t, part, mb, pl, nw, wave, lane);
+      iter_superchunk<LMAX>(graphs, B, sc, t, part, mb, pl, od, oa, nw, wave, lane);
       __syncthreads();  // part[] is reused by the next superchunk
     }
   }
 }
 
 // Fold one graph's chunk records into the next parameters and the
-// per-iteration records (one block per graph).
+// per-iteration records (one block per graph).  The graph's state and its last
+// W totals are read into LDS together with the records, so the whole update
+// waits for memory once; wave 0 then writes the state back.
 template <int LMAX>
 __global__ __launch_bounds__(1024) void k_fin_iter(const GraphDev *graphs, int B, int t) {
+  constexpr int kStWords = sizeof(GraphState) / 8;
+  static_assert(sizeof(GraphState) % 8 == 0 && kStWords <= 128, "state copy layout");
   __shared__ long long tot[kRecMax];
   __shared__ long long part[kFinWaves][kRecMax];
+  __shared__ long long stw[kStWords];
+  __shared__ double hist[kMaxWindow];
+  __shared__ int write_back;
   const GraphDev &G = graphs[blockIdx.x];
   if (t >= G.max_iters) return;
-  GraphState *st = G.st;
-  if (st->done) return;
-  const int L = G.L;
-  sum_records<LMAX>(gbl((const long long *)G.rec), G.nsuper, L, tot, part);
-  if (threadIdx.x != 0) return;
-  long long errbits = tot[3 * L + 3];
-  if (errbits) {
-    st->status = (errbits & 1) ? PMRF_EBADLABEL : PMRF_ERANGE;
-    st->done = 1;
-    return;
+  const int L = G.L, W = G.W, tid = threadIdx.x;
+  gptr<long long> gst = gbl((long long *)G.st);
+  if (tid < kStWords) {
+    stw[tid] = gst[tid];
+  } else if (tid >= 128 && tid < 128 + W) {
+    const int w = tid - 127;  // 1 .. W
+    hist[w - 1] = t >= w ? gbl((const double *)G.thist)[t - w] : 0.0;
   }
-  double T = __longlong_as_double(tot[3 * L]);
-  long long ties = tot[3 * L + 1];
-  long long nonconv = tot[3 * L + 2];
-  G.thist[t] = T;
-  if (G.out_trace) G.out_trace[t] = T;
-  if (G.out_stats) {
-    G.out_stats[2 * t] = ties;
-    G.out_stats[2 * t + 1] = nonconv;
+  sum_records<LMAX>(gbl((const long long *)G.rec), G.nsuper, L, tot, part);  // ends with a block barrier
+  if (tid >= 64) return;
+  GraphState *st = reinterpret_cast<GraphState *>(stw);
+  if (tid == 0) {
+    write_back = 0;
+    const long long errbits = tot[3 * L + 3];
+    if (st->done) {
+      // nothing to do: an earlier iteration ended the run
+    } else if (errbits) {
+      st->status = (errbits & 1) ? PMRF_EBADLABEL : PMRF_ERANGE;
+      st->done = 1;
+      write_back = 1;
+    } else {
+      const double T = __longlong_as_double(tot[3 * L]);
+      const long long ties = tot[3 * L + 1];
+      const long long nonconv = tot[3 * L + 2];
+      G.thist[t] = T;
+      if (G.out_trace) G.out_trace[t] = T;
+      if (G.out_stats) {
+        G.out_stats[2 * t] = ties;
+        G.out_stats[2 * t + 1] = nonconv;
+      }
+      st->ties_total += ties;
+      if (nonconv == 0 && t >= W && st->map_conv < 0) st->map_conv = t;
+      if (t >= W && st->em_conv < 0) {
+        bool ok = true;
+        for (int w = 1; w <= W; ++w)
+          if (!(fabs(T - hist[w - 1]) < G.tol)) ok = false;
+        if (ok) st->em_conv = t;
+      }
+      update_theta(st, tot, L, G.sigma_min, false);
+      st->iters = t + 1;
+      if (G.early_exit && nonconv == 0 && t >= W) st->done = 1;
+      write_back = 1;
+    }
   }
-  st->ties_total += ties;
-  if (nonconv == 0 && t >= G.W && st->map_conv < 0) st->map_conv = t;
-  if (t >= G.W && st->em_conv < 0) {
-    bool ok = true;
-    for (int w = 1; w <= G.W; ++w)
-      if (!(fabs(T - G.thist[t - w]) < G.tol)) ok = false;
-    if (ok) st->em_conv = t;
-  }
-  update_theta(st, tot, L, G.sigma_min, false);
-  st->iters = t + 1;
-  if (G.early_exit && nonconv == 0 && t >= G.W) st->done = 1;
+  wave_lds_sync();
+  if (write_back)
+    for (int i = tid; i < kStWords; i += 64) gst[i] = stw[i];
 }
 
 // Copy results to the caller's buffers.
@@ -1160,7 +1406,7 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
   bool any_init = false;
   for (int i = 0; i < B; ++i) any_init |= desc[i].init_from_labels != 0;
   const int lm = lmax_for(Lmax);
-  const size_t lds = (size_t)((kGroupTiles + 1) * 64 * shape.waves_per_block) * 8;
+  const size_t lds = (size_t)(kWaveLds * shape.waves_per_block) * 8;
   const bool events = g_prof.on;
   // grid of the iteration kernel: one block per superchunk, or in persistent
   // mode a machine-sized grid whose blocks walk the superchunks
