@@ -20,13 +20,13 @@
 // After up to 8 packets, one lane per neighbourhood sums its members' minima in
 // member order (the paper's ReduceByKey<Add>), checks the neighbourhood's
 // convergence window and adds the sum to its lane's energy total.  At the end
-// of a chunk the wave reduces its lanes' statistics with a fixed butterfly and
-// stores one record for the chunk.  There is no cross-block communication and
-// no memory fence inside the launch.
+// of a chunk the wave reduces its lanes' statistics with a fixed butterfly into
+// LDS, and the block adds its 4 chunks in order into one record per superchunk.
+// There is no cross-block communication and no memory fence inside the launch.
 //
-// k_fin_iter (one block per graph) adds the chunk records in a fixed order and
-// turns them into the next parameters (mean, standard deviation) and the
-// per-iteration records.
+// k_fold (one block per graph) adds the superchunk records in a fixed order
+// and turns them into the next parameters (mean, standard deviation) and the
+// per-iteration results.
 //
 // Chunks and their order are fixed by the graph alone, so the results do not
 // depend on the launch shape or on how graphs are batched.
@@ -67,16 +67,24 @@ __device__ __forceinline__ gptr<T> gbl(T *p) {
 __host__ __device__ constexpr int rec_words(int L) { return 3 * L + 4; }
 constexpr int kRecMax = 3 * kMaxLabels + 4;
 constexpr int kChunkTiles = 8;     // packets per statistics chunk (fixed: part of the result's definition)
-constexpr int kSuperChunks = 8;    // chunks per block and record (fixed: part of the result's definition)
+constexpr int kSuperChunks = 4;    // chunks per block and record (fixed: part of the result's definition)
 constexpr int kGroupTiles = 8;     // packets per neighbourhood-sum group (LDS buffer of 512 minima)
 constexpr int kVertPerBlock = 1024;
 
+// Parameters of the labels, with the two values each energy uses
+// (w = 1 / (2 sigma^2), lg = ln sigma).
+template <int N>
+struct ThetaArr {
+  double mu[N], sigma[N], w[N], lg[N];
+};
+
 struct GraphState {
-  double mu[kMaxLabels], sigma[kMaxLabels], w[kMaxLabels], lg[kMaxLabels];
-  int32_t done;  // 1: no further iterations (early exit or error)
+  ThetaArr<kMaxLabels> th[2];  // parameters of iteration t in th[t & 1]
+  int32_t done;                // 1: no further iterations (early exit or error)
   int32_t status;
   int32_t iters;
   int32_t map_conv, em_conv;
+  int32_t pad;
   int64_t ties_total;
 };
 
@@ -96,6 +104,7 @@ struct GraphDev {
   double *out_mu, *out_sigma, *out_S, *out_trace;
   int64_t *out_stats, *out_ctr;
   int64_t M;
+  int64_t rec_stride;  // words of one record buffer (records of iteration t at rec + (t & 1) * rec_stride)
   int32_t n, H, ntiles, nchunks, nsuper, L, P, W, max_iters, early_exit, init_from_labels;
   double beta, tol, sigma_min, tie_eps;
   int32_t block0, nblocks;    // blocks of this graph in an iteration launch (one per superchunk)
@@ -181,98 +190,111 @@ struct LaneStats {
   }
 };
 
-// Sum of a graph's records in a fixed order by a block of 16 waves: thread i
-// adds records i, i + 1024, i + 2048, ... in that order (16 words at a time);
-// the lanes of a wave are
-// combined with the butterfly and the waves in wave order.  Thread 0 returns
-// the totals in out[0 .. rec_words(L)).
-constexpr int kFinWaves = 16;
-constexpr int kFinThreads = 64 * kFinWaves;
+// Totals of a graph's statistics records in a fixed order that does not
+// depend on the block size: 1024 virtual threads; virtual thread i adds
+// records i, i + 1024, i + 2048, ... in that order; each virtual wave of 64
+// combines its lanes with the butterfly, and thread 0 adds the 16 virtual
+// waves in order.
+// Wave w of the calling block plays virtual waves w, w + nw, ...  With
+// all_words false the energy total and near-tie words are skipped (left
+// unset).  Every thread of the block must call; on return tot[] is visible to
+// the whole block.
+constexpr int kFoldWaves = 16;
+constexpr int kFoldThreads = 64 * kFoldWaves;
 __device__ __forceinline__ bool word_is_double(int w, int L) { return (w < 3 * L && (w % 3) != 0) || w == 3 * L; }
 
 template <int LMAX>
-__device__ void sum_records(gptr<const long long> rec, int nrec, int L, long long *out,
-                            long long (*part)[kRecMax]) {
+__device__ __forceinline__ void fold_records(gptr<const long long> rec, int nrec, int L, bool all_words, long long *tot,
+                             long long (*part)[kRecMax], int nw, int wave, int lane) {
   constexpr int WG = rec_words(LMAX) < 16 ? rec_words(LMAX) : 16;  // words per pass
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int words = rec_words(L);
-  for (int w0 = 0; w0 < words; w0 += WG) {
-    long long acc[WG];
+  for (int vw = wave; vw < kFoldWaves; vw += nw) {
+    const int i = vw * 64 + lane;
+    for (int w0 = 0; w0 < words; w0 += WG) {
+      long long acc[WG];
 #pragma unroll
-    for (int j = 0; j < WG; ++j) acc[j] = 0;
-    for (int r = threadIdx.x; r < nrec; r += kFinThreads) {
+      for (int j = 0; j < WG; ++j) acc[j] = 0;
+#pragma unroll 2
+      for (int r = i; r < nrec; r += kFoldThreads) {
+#pragma unroll
+        for (int j = 0; j < WG; ++j) {
+          const int w = w0 + j;
+          if (w >= words || (!all_words && (w == 3 * L || w == 3 * L + 1))) continue;
+          const long long v = rec[(size_t)w * nrec + r];
+          if (word_is_double(w, L))
+            acc[j] = __double_as_longlong(__longlong_as_double(acc[j]) + __longlong_as_double(v));
+          else if (w == 3 * L + 3)
+            acc[j] |= v;
+          else
+            acc[j] += v;
+        }
+      }
 #pragma unroll
       for (int j = 0; j < WG; ++j) {
         const int w = w0 + j;
-        if (w >= words) continue;
-        const long long v = rec[(size_t)w * nrec + r];
+        if (w >= words || (!all_words && (w == 3 * L || w == 3 * L + 1))) continue;
+        long long r;
         if (word_is_double(w, L))
-          acc[j] = __double_as_longlong(__longlong_as_double(acc[j]) + __longlong_as_double(v));
+          r = __double_as_longlong(wave_sum(__longlong_as_double(acc[j])));
         else if (w == 3 * L + 3)
-          acc[j] |= v;
+          r = (long long)((__ballot(acc[j] & 1) ? 1ull : 0ull) | (__ballot(acc[j] & 2) ? 2ull : 0ull));
         else
-          acc[j] += v;
+          r = wave_sum(acc[j]);
+        if (lane == 0) part[vw][w] = r;
       }
-    }
-#pragma unroll
-    for (int j = 0; j < WG; ++j) {
-      const int w = w0 + j;
-      if (w >= words) continue;
-      long long r;
-      if (word_is_double(w, L))
-        r = __double_as_longlong(wave_sum(__longlong_as_double(acc[j])));
-      else if (w == 3 * L + 3)
-        r = (long long)((__ballot(acc[j] & 1) ? 1ull : 0ull) | (__ballot(acc[j] & 2) ? 2ull : 0ull));
-      else
-        r = wave_sum(acc[j]);
-      if (lane == 0) part[wave][w] = r;
     }
   }
   __syncthreads();
-  if (threadIdx.x != 0) return;
-  for (int w = 0; w < words; ++w) {
-    if (word_is_double(w, L)) {
-      double x = 0.0;
-      for (int k = 0; k < kFinWaves; ++k) x = x + __longlong_as_double(part[k][w]);
-      out[w] = __double_as_longlong(x);
-    } else if (w == 3 * L + 3) {
-      long long x = 0;
-      for (int k = 0; k < kFinWaves; ++k) x |= part[k][w];
-      out[w] = x;
-    } else {
-      long long x = 0;
-      for (int k = 0; k < kFinWaves; ++k) x += part[k][w];
-      out[w] = x;
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < words; ++w) {
+      if (!all_words && (w == 3 * L || w == 3 * L + 1)) continue;
+      if (word_is_double(w, L)) {
+        double x = 0.0;
+        for (int k = 0; k < kFoldWaves; ++k) x = x + __longlong_as_double(part[k][w]);
+        tot[w] = __double_as_longlong(x);
+      } else if (w == 3 * L + 3) {
+        long long x = 0;
+        for (int k = 0; k < kFoldWaves; ++k) x |= part[k][w];
+        tot[w] = x;
+      } else {
+        long long x = 0;
+        for (int k = 0; k < kFoldWaves; ++k) x += part[k][w];
+        tot[w] = x;
+      }
     }
   }
+  __syncthreads();
 }
 
-__device__ void set_label_theta(GraphState *st, int l, double mu, double sigma) {
-  st->mu[l] = mu;
-  st->sigma[l] = sigma;
-  st->w[l] = 1.0 / (2.0 * sigma * sigma);
-  st->lg[l] = log(sigma);
+template <typename S>
+__device__ __forceinline__ void set_label_theta(S *s, int l, double mu, double sigma) {
+  s->mu[l] = mu;
+  s->sigma[l] = sigma;
+  s->w[l] = 1.0 / (2.0 * sigma * sigma);
+  s->lg[l] = log(sigma);
 }
 
 // Parameters for the next iteration from the per-label sums ("Update
 // Parameters"): mu = c + D1, sigma^2 = D2 - D1^2 with D1 = sum(y - c)/n,
 // D2 = sum((y - c)^2)/n, c = the mean used this iteration (pass 0 of the
 // starting update uses c = 0 and keeps sigma).  A label with no vertex keeps
-// its parameters.
-__device__ void update_theta(GraphState *st, const long long *tot, int L, double sigma_min, bool mean_only) {
+// its parameters.  s holds the parameters used this iteration on entry and
+// the next ones on return.
+template <typename S>
+__device__ __forceinline__ void update_theta(S *s, const long long *tot, int L, double sigma_min, bool mean_only) {
   for (int l = 0; l < L; ++l) {
     long long cnt = tot[3 * l];
     if (cnt <= 0) continue;
     double nd = (double)cnt;
     double d1 = __longlong_as_double(tot[3 * l + 1]) / nd;
     if (mean_only) {
-      set_label_theta(st, l, d1, st->sigma[l]);
+      set_label_theta(s, l, d1, s->sigma[l]);
       continue;
     }
     double d2 = __longlong_as_double(tot[3 * l + 2]) / nd;
     double var = d2 - d1 * d1;
     double sg = sqrt(var > 0.0 ? var : 0.0);
-    set_label_theta(st, l, st->mu[l] + d1, sg < sigma_min ? sigma_min : sg);
+    set_label_theta(s, l, s->mu[l] + d1, sg < sigma_min ? sigma_min : sg);
   }
 }
 
@@ -953,15 +975,15 @@ __global__ void k_setup(const GraphDev *graphs, int B) {
   for (int l = 0; l < G.L; ++l) {
     double mu = G.in_mu[l], sigma = G.in_sigma[l];
     if (!(sigma > 0.0) || !isfinite(sigma) || !isfinite(mu)) ok = false;
-    st->mu[l] = mu;
-    st->sigma[l] = sigma;
+    st->th[0].mu[l] = mu;
+    st->th[0].sigma[l] = sigma;
   }
   if (!ok) {
     st->status = PMRF_EBADPARAM;
     st->done = 1;
     return;
   }
-  for (int l = 0; l < G.L; ++l) set_label_theta(st, l, st->mu[l], st->sigma[l]);
+  for (int l = 0; l < G.L; ++l) set_label_theta(&st->th[0], l, st->th[0].mu[l], st->th[0].sigma[l]);
 }
 
 // Parameter update from the starting labels (used when init_from_labels is
@@ -982,7 +1004,7 @@ __global__ __launch_bounds__(256) void k_mstep_init(const GraphDev *graphs, int 
   LaneStats<kMaxLabels> ls;
   ls.clear();
   double c[kMaxLabels];
-  for (int l = 0; l < kMaxLabels; ++l) c[l] = (pass == 0 || l >= L) ? 0.0 : st->mu[l];
+  for (int l = 0; l < kMaxLabels; ++l) c[l] = (pass == 0 || l >= L) ? 0.0 : st->th[0].mu[l];
   for (int v = v0 + threadIdx.x; v < v1; v += blockDim.x) {
     int xv = x[v];
     if ((unsigned)xv >= (unsigned)L) {
@@ -1016,13 +1038,14 @@ __global__ __launch_bounds__(256) void k_mstep_init(const GraphDev *graphs, int 
 }
 
 template <int LMAX>
-__global__ __launch_bounds__(1024) void k_fin_init(const GraphDev *graphs, int B, int pass) {
+__global__ __launch_bounds__(kFoldThreads) void k_fin_init(const GraphDev *graphs, int B, int pass) {
   __shared__ long long tot[kRecMax];
-  __shared__ long long part[kFinWaves][kRecMax];
+  __shared__ long long part[kFoldWaves][kRecMax];
   const GraphDev &G = graphs[blockIdx.x];
   GraphState *st = G.st;
   if (!G.init_from_labels || st->done) return;
-  sum_records<LMAX>(gbl((const long long *)G.rec), G.vnblocks, G.L, tot, part);
+  fold_records<LMAX>(gbl((const long long *)G.rec), G.vnblocks, G.L, true, tot, part, blockDim.x >> 6,
+                     threadIdx.x >> 6, threadIdx.x & 63);
   if (threadIdx.x != 0) return;
   long long errbits = tot[3 * G.L + 3];
   if (errbits) {
@@ -1030,24 +1053,99 @@ __global__ __launch_bounds__(1024) void k_fin_init(const GraphDev *graphs, int B
     st->done = 1;
     return;
   }
-  update_theta(st, tot, G.L, G.sigma_min, pass == 0);
+  update_theta(&st->th[0], tot, G.L, G.sigma_min, pass == 0);
+}
+
+// LDS of the parameter update.
+template <int LMAX>
+struct FoldLds {
+  long long tot[kRecMax];
+  long long part[kFoldWaves][kRecMax];
+  ThetaArr<LMAX> th;
+  double hist[kMaxWindow];
+};
+
+// Parameter update ("Update Parameters") of iteration tp = t - 1 of one graph,
+// by one block: fold the records of tp in the fixed order, derive the
+// parameters of iteration t, and store them with the per-iteration results of
+// tp (energy total, near ties, convergence, iteration count, early exit,
+// errors).  The graph's state, its last W energy totals and the parameters of
+// tp are read together with the records, so the block waits for memory once.
+template <int LMAX>
+__device__ __forceinline__ void fold_iteration(const GraphDev &G, int t, FoldLds<LMAX> &sh, int nw, int wave,
+                                               int lane) {
+  gptr<GraphState> st = gbl(G.st);
+  if (t < 1 || t - 1 >= G.max_iters) return;
+  const int L = G.L, W = G.W, tp = t - 1, tid = threadIdx.x;
+  const int done = st->done;
+  if (tid < L) {
+    sh.th.mu[tid] = st->th[tp & 1].mu[tid];
+    sh.th.sigma[tid] = st->th[tp & 1].sigma[tid];
+    sh.th.w[tid] = st->th[tp & 1].w[tid];
+    sh.th.lg[tid] = st->th[tp & 1].lg[tid];
+  } else if (tid >= kMaxLabels && tid < kMaxLabels + W) {
+    const int w = tid - kMaxLabels + 1;  // 1 .. W
+    sh.hist[w - 1] = tp >= w ? gbl(G.thist)[tp - w] : 0.0;
+  }
+  fold_records<LMAX>(gbl((const long long *)G.rec) + (size_t)(tp & 1) * G.rec_stride, G.nsuper, L, true, sh.tot,
+                     sh.part, nw, wave, lane);
+  if (tid != 0 || done) return;
+  const long long errbits = sh.tot[3 * L + 3];
+  if (errbits) {
+    st->status = (errbits & 1) ? PMRF_EBADLABEL : PMRF_ERANGE;
+    st->done = 1;
+    return;
+  }
+  const double T = __longlong_as_double(sh.tot[3 * L]);
+  const long long ties = sh.tot[3 * L + 1];
+  const long long nonconv = sh.tot[3 * L + 2];
+  gbl(G.thist)[tp] = T;
+  if (G.out_trace) gbl(G.out_trace)[tp] = T;
+  if (G.out_stats) {
+    gbl(G.out_stats)[2 * tp] = ties;
+    gbl(G.out_stats)[2 * tp + 1] = nonconv;
+  }
+  st->ties_total += ties;
+  if (nonconv == 0 && tp >= W && st->map_conv < 0) st->map_conv = tp;
+  if (tp >= W && st->em_conv < 0) {
+    bool ok = true;
+    for (int w = 1; w <= W; ++w)
+      if (!(fabs(T - sh.hist[w - 1]) < G.tol)) ok = false;
+    if (ok) st->em_conv = tp;
+  }
+  update_theta(&sh.th, sh.tot, L, G.sigma_min, false);
+  for (int l = 0; l < L; ++l) {
+    st->th[t & 1].mu[l] = sh.th.mu[l];
+    st->th[t & 1].sigma[l] = sh.th.sigma[l];
+    st->th[t & 1].w[l] = sh.th.w[l];
+    st->th[t & 1].lg[l] = sh.th.lg[l];
+  }
+  st->iters = t;
+  if (G.early_exit && nonconv == 0 && tp >= W) st->done = 1;
 }
 
 // One EM iteration over every graph of the launch.  Block b of a graph owns
-// superchunk b (chunks 8b .. 8b+7); its waves take the chunks in turn, leave
+// superchunk b (chunks 4b .. 4b+3); its waves take the chunks in turn, leave
 // each chunk's statistics in LDS, and the block adds them in chunk order into
-// the superchunk's record.  Dynamic LDS per wave: 512 minima and 64 label-plane
-// words.
+// the superchunk's record (buffer t & 1).
 template <int LMAX>
 __device__ __forceinline__ void iter_superchunk(const GraphDev *__restrict__ graphs, int B, int sc, int t,
                                                 long long (*part)[rec_words(LMAX)], double *mb, uint64_t *pl,
                                                 double *od, int *oa, int nw, int wave, int lane) {
+  const int g = find_graph(graphs, B, sc, false);
+  const GraphDev &G = graphs[g];
+  if (t >= G.max_iters) return;
+  gptr<const GraphState> st = gbl((const GraphState *)G.st);
+  const int done = st->done;  // read with the parameters below (one wait)
+  Theta<LMAX> th;
+#pragma unroll
+  for (int l = 0; l < LMAX; ++l) {
+    th.mu[l] = l < G.L ? st->th[t & 1].mu[l] : 0.0;
+    th.w[l] = l < G.L ? st->th[t & 1].w[l] : 0.0;
+    th.lg[l] = l < G.L ? st->th[t & 1].lg[l] : 0.0;
+  }
+  if (done) return;
   {
-    const int g = find_graph(graphs, B, sc, false);
-    const GraphDev &G = graphs[g];
-    if (t >= G.max_iters) return;
-    gptr<const GraphState> st = gbl((const GraphState *)G.st);
-    const int done = st->done;  // read with the parameters below (one wait)
     Ctx c;
     c.tiles = gbl(G.tiles);
     c.vid = gbl(G.vid);
@@ -1067,14 +1165,6 @@ __device__ __forceinline__ void iter_superchunk(const GraphDev *__restrict__ gra
     c.beta = G.beta;
     c.tol = G.tol;
     c.tie_eps = G.tie_eps;
-    Theta<LMAX> th;
-#pragma unroll
-    for (int l = 0; l < LMAX; ++l) {
-      th.mu[l] = l < c.L ? st->mu[l] : 0.0;
-      th.w[l] = l < c.L ? st->w[l] : 0.0;
-      th.lg[l] = l < c.L ? st->lg[l] : 0.0;
-    }
-    if (done) return;
     const int b = sc - G.block0;
     const int c0 = b * kSuperChunks;
     const int c1 = min(G.nchunks, c0 + kSuperChunks);
@@ -1095,7 +1185,7 @@ __device__ __forceinline__ void iter_superchunk(const GraphDev *__restrict__ gra
         out = 0;
         for (int k = 0; k < c1 - c0; ++k) out += part[k][w];
       }
-      gbl(G.rec)[(size_t)w * G.nsuper + b] = out;
+      gbl(G.rec)[(size_t)(t & 1) * G.rec_stride + (size_t)w * G.nsuper + b] = out;
     }
   }
 }
@@ -1103,7 +1193,8 @@ __device__ __forceinline__ void iter_superchunk(const GraphDev *__restrict__ gra
 // PERSIST = false: block b works on superchunk b.  PERSIST = true: a grid sized
 // to the machine whose blocks walk all superchunks.
 template <int LMAX, bool PERSIST>
-__global__ __launch_bounds__(1024) void k_iter(const GraphDev *__restrict__ graphs, int B, int nsuper_total, int t) {
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(LMAX <= 2 ? 5 : 1, 8))) void k_iter(
+    const GraphDev *__restrict__ graphs, int B, int nsuper_total, int t) {
   extern __shared__ double smem[];
   __shared__ long long part[kSuperChunks][rec_words(LMAX)];
   const int nw = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -1121,68 +1212,11 @@ __global__ __launch_bounds__(1024) void k_iter(const GraphDev *__restrict__ grap
   }
 }
 
-// Fold one graph's chunk records into the next parameters and the
-// per-iteration records (one block per graph).  The graph's state and its last
-// W totals are read into LDS together with the records, so the whole update
-// waits for memory once; wave 0 then writes the state back.
+// The parameter update of iteration t - 1 (one block per graph).
 template <int LMAX>
-__global__ __launch_bounds__(1024) void k_fin_iter(const GraphDev *graphs, int B, int t) {
-  constexpr int kStWords = sizeof(GraphState) / 8;
-  static_assert(sizeof(GraphState) % 8 == 0 && kStWords <= 128, "state copy layout");
-  __shared__ long long tot[kRecMax];
-  __shared__ long long part[kFinWaves][kRecMax];
-  __shared__ long long stw[kStWords];
-  __shared__ double hist[kMaxWindow];
-  __shared__ int write_back;
-  const GraphDev &G = graphs[blockIdx.x];
-  if (t >= G.max_iters) return;
-  const int L = G.L, W = G.W, tid = threadIdx.x;
-  gptr<long long> gst = gbl((long long *)G.st);
-  if (tid < kStWords) {
-    stw[tid] = gst[tid];
-  } else if (tid >= 128 && tid < 128 + W) {
-    const int w = tid - 127;  // 1 .. W
-    hist[w - 1] = t >= w ? gbl((const double *)G.thist)[t - w] : 0.0;
-  }
-  sum_records<LMAX>(gbl((const long long *)G.rec), G.nsuper, L, tot, part);  // ends with a block barrier
-  if (tid >= 64) return;
-  GraphState *st = reinterpret_cast<GraphState *>(stw);
-  if (tid == 0) {
-    write_back = 0;
-    const long long errbits = tot[3 * L + 3];
-    if (st->done) {
-      // nothing to do: an earlier iteration ended the run
-    } else if (errbits) {
-      st->status = (errbits & 1) ? PMRF_EBADLABEL : PMRF_ERANGE;
-      st->done = 1;
-      write_back = 1;
-    } else {
-      const double T = __longlong_as_double(tot[3 * L]);
-      const long long ties = tot[3 * L + 1];
-      const long long nonconv = tot[3 * L + 2];
-      G.thist[t] = T;
-      if (G.out_trace) G.out_trace[t] = T;
-      if (G.out_stats) {
-        G.out_stats[2 * t] = ties;
-        G.out_stats[2 * t + 1] = nonconv;
-      }
-      st->ties_total += ties;
-      if (nonconv == 0 && t >= W && st->map_conv < 0) st->map_conv = t;
-      if (t >= W && st->em_conv < 0) {
-        bool ok = true;
-        for (int w = 1; w <= W; ++w)
-          if (!(fabs(T - hist[w - 1]) < G.tol)) ok = false;
-        if (ok) st->em_conv = t;
-      }
-      update_theta(st, tot, L, G.sigma_min, false);
-      st->iters = t + 1;
-      if (G.early_exit && nonconv == 0 && t >= W) st->done = 1;
-      write_back = 1;
-    }
-  }
-  wave_lds_sync();
-  if (write_back)
-    for (int i = tid; i < kStWords; i += 64) gst[i] = stw[i];
+__global__ __launch_bounds__(kFoldThreads) void k_fold(const GraphDev *graphs, int B, int t) {
+  __shared__ FoldLds<LMAX> sh;
+  fold_iteration<LMAX>(graphs[blockIdx.x], t, sh, blockDim.x >> 6, threadIdx.x >> 6, threadIdx.x & 63);
 }
 
 // Copy results to the caller's buffers.
@@ -1201,8 +1235,8 @@ __global__ void k_final(const GraphDev *graphs, int B) {
   }
   if (b == 0 && threadIdx.x == 0) {
     for (int l = 0; l < G.L; ++l) {
-      G.out_mu[l] = st->mu[l];
-      G.out_sigma[l] = st->sigma[l];
+      G.out_mu[l] = st->th[iters & 1].mu[l];
+      G.out_sigma[l] = st->th[iters & 1].sigma[l];
     }
     int64_t *c = G.out_ctr;
     c[PMRF_CTR_STATUS] = st->status;
@@ -1251,9 +1285,9 @@ struct LaunchShape {
 LaunchShape resolve_shape() {
   std::lock_guard<std::mutex> lk(g_launch_mu);
   LaunchShape s{g_launch.mode > 0 ? g_launch.mode : kModeGraph,
-                g_launch.waves_per_block > 0 ? g_launch.waves_per_block : 8,
+                g_launch.waves_per_block > 0 ? g_launch.waves_per_block : 4,
                 g_launch.tiles_per_wave > 0 ? g_launch.tiles_per_wave : 1,
-                g_launch.blocks_per_cu > 0 ? g_launch.blocks_per_cu : 2};
+                g_launch.blocks_per_cu > 0 ? g_launch.blocks_per_cu : 5};
   return s;
 }
 
@@ -1329,7 +1363,7 @@ WsPlan plan_workspace(int B, const pmrf_em_item *items) {
     p.thist_off.push_back(off);
     off += align_up((int64_t)std::max(1, items[i].params.max_iters) * 8, 256);
     p.rec_off.push_back(off);
-    off += align_up(max_records(h) * rec_words(items[i].params.L) * 8, 256);
+    off += align_up(2 * max_records(h) * rec_words(items[i].params.L) * 8, 256);  // two record buffers
   }
   p.total = std::max<int64_t>(off, 256);
   return p;
@@ -1378,6 +1412,7 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
     G.out_stats = it.d_iter_stats;
     G.out_ctr = it.d_counters;
     G.M = h->M;
+    G.rec_stride = max_records(h) * rec_words(it.params.L);
     G.n = h->n;
     G.H = (int32_t)h->H;
     G.ntiles = (int32_t)h->tiles.size();
@@ -1438,10 +1473,10 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
         hipLaunchKernelGGL(k_mstep_init, dim3(blocks_vert), dim3(256), 0, s, gd, B, pass);
         HIP_TRY(hipGetLastError());
         switch (lm) {
-          case 2: hipLaunchKernelGGL(k_fin_init<2>, dim3(B), dim3(kFinThreads), 0, s, gd, B, pass); break;
-          case 4: hipLaunchKernelGGL(k_fin_init<4>, dim3(B), dim3(kFinThreads), 0, s, gd, B, pass); break;
-          case 8: hipLaunchKernelGGL(k_fin_init<8>, dim3(B), dim3(kFinThreads), 0, s, gd, B, pass); break;
-          default: hipLaunchKernelGGL(k_fin_init<16>, dim3(B), dim3(kFinThreads), 0, s, gd, B, pass); break;
+          case 2: hipLaunchKernelGGL(k_fin_init<2>, dim3(B), dim3(kFoldThreads), 0, s, gd, B, pass); break;
+          case 4: hipLaunchKernelGGL(k_fin_init<4>, dim3(B), dim3(kFoldThreads), 0, s, gd, B, pass); break;
+          case 8: hipLaunchKernelGGL(k_fin_init<8>, dim3(B), dim3(kFoldThreads), 0, s, gd, B, pass); break;
+          default: hipLaunchKernelGGL(k_fin_init<16>, dim3(B), dim3(kFoldThreads), 0, s, gd, B, pass); break;
         }
         HIP_TRY(hipGetLastError());
       }
@@ -1464,11 +1499,11 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
 #undef PMRF_LAUNCH_ITER
       HIP_TRY(hipGetLastError());
       if (events) HIP_TRY(prof_mark(s, false));
-      switch (lm) {
-        case 2: hipLaunchKernelGGL(k_fin_iter<2>, dim3(B), dim3(kFinThreads), 0, s, gd, B, t); break;
-        case 4: hipLaunchKernelGGL(k_fin_iter<4>, dim3(B), dim3(kFinThreads), 0, s, gd, B, t); break;
-        case 8: hipLaunchKernelGGL(k_fin_iter<8>, dim3(B), dim3(kFinThreads), 0, s, gd, B, t); break;
-        default: hipLaunchKernelGGL(k_fin_iter<16>, dim3(B), dim3(kFinThreads), 0, s, gd, B, t); break;
+      switch (lm) {  // the parameter update of iteration t
+        case 2: hipLaunchKernelGGL(k_fold<2>, dim3(B), dim3(kFoldThreads), 0, s, gd, B, t + 1); break;
+        case 4: hipLaunchKernelGGL(k_fold<4>, dim3(B), dim3(kFoldThreads), 0, s, gd, B, t + 1); break;
+        case 8: hipLaunchKernelGGL(k_fold<8>, dim3(B), dim3(kFoldThreads), 0, s, gd, B, t + 1); break;
+        default: hipLaunchKernelGGL(k_fold<16>, dim3(B), dim3(kFoldThreads), 0, s, gd, B, t + 1); break;
       }
       HIP_TRY(hipGetLastError());
     }
