@@ -45,7 +45,7 @@ typedef int32_t pmrf_status;
 /* device-reported codes, in counters[PMRF_CTR_STATUS] */
 #define PMRF_EBADLABEL (-10)   /* a starting label outside [0, L) */
 #define PMRF_EBADPARAM (-11)   /* a starting sigma <= 0 or a non-finite mu / sigma */
-#define PMRF_ERANGE (-12)      /* an intensity or energy too large for the exact accumulators (|value| >= 2^62) */
+#define PMRF_ERANGE (-12)      /* reserved: not returned by this version */
 #define PMRF_ETIMEOUT (-13)    /* the persistent kernel's grid barrier did not complete (not co-resident) */
 
 /* Thread-local text of the last error (never NULL; "" if none). */

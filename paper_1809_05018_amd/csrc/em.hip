@@ -58,12 +58,14 @@ __device__ __forceinline__ gptr<T> gbl(T *p) {
 }
 
 // ------------------------------------------------------------ device records
-// statistics record (8-byte words; counts as int64, sums as double bits), stored
-// word-major: word w of record r at rec[w * nrec + r]:
+// statistics record: 3L + 4 doubles, stored word-major (word w of record r at
+// rec[w * nrec + r]):
 //   per label l: [3l] count, [3l+1] sum of (y - c_l), [3l+2] sum of (y - c_l)^2
 //                (c_l = the mean used in this iteration)
 //   [3L] total energy, [3L+1] near ties, [3L+2] neighbourhoods not converged,
-//   [3L+3] error bits (1: label out of range, 2: non-finite value)
+//   [3L+3] labels out of range.
+// Counts are integers below 2^53, so their double sums are exact in any order;
+// every word of every record is combined with the same double addition.
 __host__ __device__ constexpr int rec_words(int L) { return 3 * L + 4; }
 constexpr int kRecMax = 3 * kMaxLabels + 4;
 constexpr int kChunkTiles = 8;     // packets per statistics chunk (fixed: part of the result's definition)
@@ -99,7 +101,7 @@ struct GraphDev {
   double *ring;  // (W+1) x H neighbourhood sums
   double *thist;
   GraphState *st;
-  long long *rec;  // statistics records (chunks, or vertex blocks)
+  double *rec;  // statistics records (chunks, or vertex blocks)
   const double *in_mu, *in_sigma;
   double *out_mu, *out_sigma, *out_S, *out_trace;
   int64_t *out_stats, *out_ctr;
@@ -172,20 +174,19 @@ struct LaneStats {
         double a = wave_sum(s1[l]);
         double b = wave_sum(s2[l]);
         if (lane == 0) {
-          rec[(3 * l) * stride] = c;
-          rec[(3 * l + 1) * stride] = __double_as_longlong(a);
-          rec[(3 * l + 2) * stride] = __double_as_longlong(b);
+          rec[(3 * l) * stride] = (double)c;
+          rec[(3 * l + 1) * stride] = a;
+          rec[(3 * l + 2) * stride] = b;
         }
       }
     double t = wave_sum(T);
     long long ti = wave_sum((long long)ties), nc = wave_sum((long long)nonconv);
-    unsigned long long e = __ballot(err & 1) ? 1ull : 0ull;
-    e |= __ballot(err & 2) ? 2ull : 0ull;
+    const int e = __popcll(__ballot(err != 0));
     if (lane == 0) {
-      rec[(3 * L) * stride] = __double_as_longlong(t);
-      rec[(3 * L + 1) * stride] = ti;
-      rec[(3 * L + 2) * stride] = nc;
-      rec[(3 * L + 3) * stride] = (long long)e;
+      rec[(3 * L) * stride] = t;
+      rec[(3 * L + 1) * stride] = (double)ti;
+      rec[(3 * L + 2) * stride] = (double)nc;
+      rec[(3 * L + 3) * stride] = (double)e;
     }
   }
 };
@@ -195,72 +196,49 @@ struct LaneStats {
 // records i, i + 1024, i + 2048, ... in that order; each virtual wave of 64
 // combines its lanes with the butterfly, and thread 0 adds the 16 virtual
 // waves in order.
-// Wave w of the calling block plays virtual waves w, w + nw, ...  With
-// all_words false the energy total and near-tie words are skipped (left
-// unset).  Every thread of the block must call; on return tot[] is visible to
-// the whole block.
+// Wave w of the calling block plays virtual waves w, w + nw, ...  Every thread
+// of the block must call; on return tot[] is visible to the whole block.
 constexpr int kFoldWaves = 16;
 constexpr int kFoldThreads = 64 * kFoldWaves;
-__device__ __forceinline__ bool word_is_double(int w, int L) { return (w < 3 * L && (w % 3) != 0) || w == 3 * L; }
 
 template <int LMAX>
-__device__ __forceinline__ void fold_records(gptr<const long long> rec, int nrec, int L, bool all_words, long long *tot,
-                             long long (*part)[kRecMax], int nw, int wave, int lane) {
+__device__ __forceinline__ void fold_records(gptr<const double> rec, int nrec, int L, double *tot,
+                                             double (*part)[kRecMax], int nw, int wave, int lane) {
   constexpr int WG = rec_words(LMAX) < 16 ? rec_words(LMAX) : 16;  // words per pass
   const int words = rec_words(L);
   for (int vw = wave; vw < kFoldWaves; vw += nw) {
     const int i = vw * 64 + lane;
     for (int w0 = 0; w0 < words; w0 += WG) {
-      long long acc[WG];
+      double acc[WG];
 #pragma unroll
-      for (int j = 0; j < WG; ++j) acc[j] = 0;
-#pragma unroll 2
-      for (int r = i; r < nrec; r += kFoldThreads) {
+      for (int j = 0; j < WG; ++j) acc[j] = 0.0;
+      // two records per pass, all loads issued before any is used (an absent
+      // record reads as 0)
+      for (int r = i; r < nrec; r += 2 * kFoldThreads) {
+        double v0[WG], v1[WG];
+        const bool has1 = r + kFoldThreads < nrec;
 #pragma unroll
         for (int j = 0; j < WG; ++j) {
-          const int w = w0 + j;
-          if (w >= words || (!all_words && (w == 3 * L || w == 3 * L + 1))) continue;
-          const long long v = rec[(size_t)w * nrec + r];
-          if (word_is_double(w, L))
-            acc[j] = __double_as_longlong(__longlong_as_double(acc[j]) + __longlong_as_double(v));
-          else if (w == 3 * L + 3)
-            acc[j] |= v;
-          else
-            acc[j] += v;
+          const bool wok = w0 + j < words;
+          v0[j] = wok ? rec[(size_t)(w0 + j) * nrec + r] : 0.0;
+          v1[j] = (wok && has1) ? rec[(size_t)(w0 + j) * nrec + r + kFoldThreads] : 0.0;
         }
+#pragma unroll
+        for (int j = 0; j < WG; ++j) acc[j] = (acc[j] + v0[j]) + v1[j];
       }
 #pragma unroll
       for (int j = 0; j < WG; ++j) {
-        const int w = w0 + j;
-        if (w >= words || (!all_words && (w == 3 * L || w == 3 * L + 1))) continue;
-        long long r;
-        if (word_is_double(w, L))
-          r = __double_as_longlong(wave_sum(__longlong_as_double(acc[j])));
-        else if (w == 3 * L + 3)
-          r = (long long)((__ballot(acc[j] & 1) ? 1ull : 0ull) | (__ballot(acc[j] & 2) ? 2ull : 0ull));
-        else
-          r = wave_sum(acc[j]);
-        if (lane == 0) part[vw][w] = r;
+        const double r = wave_sum(acc[j]);
+        if (lane == 0 && w0 + j < words) part[vw][w0 + j] = r;
       }
     }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int w = 0; w < words; ++w) {
-      if (!all_words && (w == 3 * L || w == 3 * L + 1)) continue;
-      if (word_is_double(w, L)) {
-        double x = 0.0;
-        for (int k = 0; k < kFoldWaves; ++k) x = x + __longlong_as_double(part[k][w]);
-        tot[w] = __double_as_longlong(x);
-      } else if (w == 3 * L + 3) {
-        long long x = 0;
-        for (int k = 0; k < kFoldWaves; ++k) x |= part[k][w];
-        tot[w] = x;
-      } else {
-        long long x = 0;
-        for (int k = 0; k < kFoldWaves; ++k) x += part[k][w];
-        tot[w] = x;
-      }
+      double x = 0.0;
+      for (int k = 0; k < kFoldWaves; ++k) x = x + part[k][w];
+      tot[w] = x;
     }
   }
   __syncthreads();
@@ -278,23 +256,40 @@ __device__ __forceinline__ void set_label_theta(S *s, int l, double mu, double s
 // Parameters"): mu = c + D1, sigma^2 = D2 - D1^2 with D1 = sum(y - c)/n,
 // D2 = sum((y - c)^2)/n, c = the mean used this iteration (pass 0 of the
 // starting update uses c = 0 and keeps sigma).  A label with no vertex keeps
-// its parameters.  s holds the parameters used this iteration on entry and
-// the next ones on return.
+// its parameters.  One label: (mu, sigma, w, lg) hold its parameters of this
+// iteration on entry and the next ones on return.
+__device__ __forceinline__ void next_label_theta(double nd, double s1, double s2, double sigma_min, bool mean_only,
+                                                 double &mu, double &sigma, double &w, double &lg) {
+  if (!(nd > 0.0)) return;
+  const double d1 = s1 / nd;
+  double m, sg;
+  if (mean_only) {
+    m = d1;
+    sg = sigma;
+  } else {
+    const double d2 = s2 / nd;
+    const double var = d2 - d1 * d1;
+    const double r = sqrt(var > 0.0 ? var : 0.0);
+    m = mu + d1;
+    sg = r < sigma_min ? sigma_min : r;
+  }
+  mu = m;
+  sigma = sg;
+  w = 1.0 / (2.0 * sg * sg);
+  lg = log(sg);
+}
+
+// All labels, by one thread (s: parameters of this iteration on entry, the
+// next ones on return).
 template <typename S>
-__device__ __forceinline__ void update_theta(S *s, const long long *tot, int L, double sigma_min, bool mean_only) {
+__device__ __forceinline__ void update_theta(S *s, const double *tot, int L, double sigma_min, bool mean_only) {
   for (int l = 0; l < L; ++l) {
-    long long cnt = tot[3 * l];
-    if (cnt <= 0) continue;
-    double nd = (double)cnt;
-    double d1 = __longlong_as_double(tot[3 * l + 1]) / nd;
-    if (mean_only) {
-      set_label_theta(s, l, d1, s->sigma[l]);
-      continue;
-    }
-    double d2 = __longlong_as_double(tot[3 * l + 2]) / nd;
-    double var = d2 - d1 * d1;
-    double sg = sqrt(var > 0.0 ? var : 0.0);
-    set_label_theta(s, l, s->mu[l] + d1, sg < sigma_min ? sigma_min : sg);
+    double mu = s->mu[l], sg = s->sigma[l], w = s->w[l], lg = s->lg[l];
+    next_label_theta(tot[3 * l], tot[3 * l + 1], tot[3 * l + 2], sigma_min, mean_only, mu, sg, w, lg);
+    s->mu[l] = mu;
+    s->sigma[l] = sg;
+    s->w[l] = w;
+    s->lg[l] = lg;
   }
 }
 
@@ -670,15 +665,15 @@ struct ChunkStats {
     }
   }
   // butterfly over the lanes; lane 0 writes the record row (LDS)
-  __device__ void store(long long *row, int L, int lane) {
+  __device__ void store(double *row, int L, int lane) {
 #pragma unroll
     for (int l = 0; l < LMAX; ++l)
       if (l < L) {
         const double a = wave_sum(s1[l]);
         const double b = wave_sum(s2[l]);
         if (lane == 0) {
-          row[3 * l + 1] = __double_as_longlong(a);
-          row[3 * l + 2] = __double_as_longlong(b);
+          row[3 * l + 1] = a;
+          row[3 * l + 2] = b;
         }
       }
 #pragma unroll
@@ -691,15 +686,15 @@ struct ChunkStats {
       if (lane == 0)
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-          if (l0 + q < L) row[3 * (l0 + q)] = (packed >> (16 * q)) & 0xffff;
+          if (l0 + q < L) row[3 * (l0 + q)] = (double)((packed >> (16 * q)) & 0xffff);
     }
     const double t = wave_sum(T);
-    const long long e = (__ballot(err & 1) ? 1 : 0) | (__ballot(err & 2) ? 2 : 0);
+    const int e = __popcll(__ballot(err != 0));
     if (lane == 0) {
-      row[3 * L] = __double_as_longlong(t);
-      row[3 * L + 1] = ties;
-      row[3 * L + 2] = nonconv;
-      row[3 * L + 3] = e;
+      row[3 * L] = t;
+      row[3 * L + 1] = (double)ties;
+      row[3 * L + 2] = (double)nonconv;
+      row[3 * L + 3] = (double)e;
     }
   }
 };
@@ -834,7 +829,7 @@ __device__ __forceinline__ void lean_hoods(const Ctx &c, int h0, int h1, int gst
 // Lean chunk (no LARGE packet, window <= 4): loads of the whole chunk first,
 // then the element passes, the owner list and the neighbourhood pass.
 template <int LMAX>
-__device__ void chunk_lean(const Ctx &c, int tb, int te, int hend, const Theta<LMAX> &th, long long *row,
+__device__ void chunk_lean(const Ctx &c, int tb, int te, int hend, const Theta<LMAX> &th, double *row,
                            double *mb, double *od, int *oa, int lane) {
   ChunkStats<LMAX> cs;
   cs.clear();
@@ -915,7 +910,7 @@ __device__ void chunk_lean(const Ctx &c, int tb, int te, int hend, const Theta<L
 // the window length, never on the launch shape, so results stay independent of
 // it (the two paths add the owner statistics in different lane orders).
 template <int LMAX>
-__device__ void do_chunk(const Ctx &c, int ck, const Theta<LMAX> &th, long long *part, double *mb, uint64_t *pl,
+__device__ void do_chunk(const Ctx &c, int ck, const Theta<LMAX> &th, double *part, double *mb, uint64_t *pl,
                          double *od, int *oa, int lane) {
   LaneStats<LMAX> ls;
   ls.clear();
@@ -991,7 +986,7 @@ __global__ void k_setup(const GraphDev *graphs, int B) {
 // Block b covers vertices [b*1024, b*1024 + 1024), thread t the vertices
 // t, t+256, ... of that range; one record per block.
 __global__ __launch_bounds__(256) void k_mstep_init(const GraphDev *graphs, int B, int pass) {
-  __shared__ long long part[4][kRecMax];
+  __shared__ double part[4][kRecMax];
   const int g = find_graph(graphs, B, blockIdx.x, true);
   const GraphDev &G = graphs[g];
   gptr<const GraphState> st = gbl((const GraphState *)G.st);
@@ -1022,34 +1017,25 @@ __global__ __launch_bounds__(256) void k_mstep_init(const GraphDev *graphs, int 
   if (threadIdx.x >= 64) return;
   // the four waves in order
   if (lane < words) {
-    long long out;
     const int w = lane;
-    if (word_is_double(w, L)) {
-      double acc = 0.0;
-      for (int k = 0; k < 4; ++k) acc = acc + __longlong_as_double(part[k][w]);
-      out = __double_as_longlong(acc);
-    } else if (w == 3 * L + 3) {
-      out = part[0][w] | part[1][w] | part[2][w] | part[3][w];
-    } else {
-      out = part[0][w] + part[1][w] + part[2][w] + part[3][w];
-    }
-    gbl(G.rec)[(size_t)w * G.vnblocks + b] = out;
+    double acc = 0.0;
+    for (int k = 0; k < 4; ++k) acc = acc + part[k][w];
+    gbl(G.rec)[(size_t)w * G.vnblocks + b] = acc;
   }
 }
 
 template <int LMAX>
 __global__ __launch_bounds__(kFoldThreads) void k_fin_init(const GraphDev *graphs, int B, int pass) {
-  __shared__ long long tot[kRecMax];
-  __shared__ long long part[kFoldWaves][kRecMax];
+  __shared__ double tot[kRecMax];
+  __shared__ double part[kFoldWaves][kRecMax];
   const GraphDev &G = graphs[blockIdx.x];
   GraphState *st = G.st;
   if (!G.init_from_labels || st->done) return;
-  fold_records<LMAX>(gbl((const long long *)G.rec), G.vnblocks, G.L, true, tot, part, blockDim.x >> 6,
-                     threadIdx.x >> 6, threadIdx.x & 63);
+  fold_records<LMAX>(gbl((const double *)G.rec), G.vnblocks, G.L, tot, part, blockDim.x >> 6, threadIdx.x >> 6,
+                     threadIdx.x & 63);
   if (threadIdx.x != 0) return;
-  long long errbits = tot[3 * G.L + 3];
-  if (errbits) {
-    st->status = (errbits & 1) ? PMRF_EBADLABEL : PMRF_ERANGE;
+  if (tot[3 * G.L + 3] != 0.0) {
+    st->status = PMRF_EBADLABEL;
     st->done = 1;
     return;
   }
@@ -1059,69 +1045,78 @@ __global__ __launch_bounds__(kFoldThreads) void k_fin_init(const GraphDev *graph
 // LDS of the parameter update.
 template <int LMAX>
 struct FoldLds {
-  long long tot[kRecMax];
-  long long part[kFoldWaves][kRecMax];
-  ThetaArr<LMAX> th;
-  double hist[kMaxWindow];
+  double tot[kRecMax];
+  double part[kFoldWaves][kRecMax];
 };
 
-// Parameter update ("Update Parameters") of iteration tp = t - 1 of one graph,
-// by one block: fold the records of tp in the fixed order, derive the
+// Parameter update ("Update Parameters") of iteration tp = t - 1 >= 0 of one
+// graph, by one block: fold the records of tp in the fixed order, derive the
 // parameters of iteration t, and store them with the per-iteration results of
 // tp (energy total, near ties, convergence, iteration count, early exit,
-// errors).  The graph's state, its last W energy totals and the parameters of
-// tp are read together with the records, so the block waits for memory once.
+// errors).  Every value the update reads is requested before any of it is
+// used: the state (uniform, scalar loads), and in wave 0 lane l's label
+// parameters and the energy total of iteration tp - l - 1 travel with the
+// record loads.  Wave 0 then updates label l in lane l.
 template <int LMAX>
 __device__ __forceinline__ void fold_iteration(const GraphDev &G, int t, FoldLds<LMAX> &sh, int nw, int wave,
                                                int lane) {
+  const int max_iters = G.max_iters, L = G.L, W = G.W;
   gptr<GraphState> st = gbl(G.st);
-  if (t < 1 || t - 1 >= G.max_iters) return;
-  const int L = G.L, W = G.W, tp = t - 1, tid = threadIdx.x;
+  gptr<const double> thist = gbl((const double *)G.thist);
+  const int tp = t - 1;
   const int done = st->done;
-  if (tid < L) {
-    sh.th.mu[tid] = st->th[tp & 1].mu[tid];
-    sh.th.sigma[tid] = st->th[tp & 1].sigma[tid];
-    sh.th.w[tid] = st->th[tp & 1].w[tid];
-    sh.th.lg[tid] = st->th[tp & 1].lg[tid];
-  } else if (tid >= kMaxLabels && tid < kMaxLabels + W) {
-    const int w = tid - kMaxLabels + 1;  // 1 .. W
-    sh.hist[w - 1] = tp >= w ? gbl(G.thist)[tp - w] : 0.0;
-  }
-  fold_records<LMAX>(gbl((const long long *)G.rec) + (size_t)(tp & 1) * G.rec_stride, G.nsuper, L, true, sh.tot,
-                     sh.part, nw, wave, lane);
-  if (tid != 0 || done) return;
-  const long long errbits = sh.tot[3 * L + 3];
-  if (errbits) {
-    st->status = (errbits & 1) ? PMRF_EBADLABEL : PMRF_ERANGE;
-    st->done = 1;
+  const long long ties_total = st->ties_total;
+  const int map_conv = st->map_conv, em_conv = st->em_conv;
+  const int ll = lane < kMaxLabels ? lane : 0;
+  double mu = st->th[tp & 1].mu[ll], sg = st->th[tp & 1].sigma[ll];
+  double wl = st->th[tp & 1].w[ll], lg = st->th[tp & 1].lg[ll];
+  // thist holds max(1, max_iters) entries; used only where tp >= lane + 1
+  const double hist = thist[min(max(0, tp - lane - 1), max(0, max_iters - 1))];
+  if (tp >= max_iters) return;
+  fold_records<LMAX>(gbl((const double *)G.rec) + (size_t)(tp & 1) * G.rec_stride, G.nsuper, L, sh.tot, sh.part,
+                     nw, wave, lane);
+  if (wave != 0 || done) return;
+  if (sh.tot[3 * L + 3] != 0.0) {
+    if (lane == 0) {
+      st->status = PMRF_EBADLABEL;
+      st->done = 1;
+    }
     return;
   }
-  const double T = __longlong_as_double(sh.tot[3 * L]);
-  const long long ties = sh.tot[3 * L + 1];
-  const long long nonconv = sh.tot[3 * L + 2];
-  gbl(G.thist)[tp] = T;
-  if (G.out_trace) gbl(G.out_trace)[tp] = T;
-  if (G.out_stats) {
-    gbl(G.out_stats)[2 * tp] = ties;
-    gbl(G.out_stats)[2 * tp + 1] = nonconv;
+  const double T = sh.tot[3 * L];
+  const long long ties = (long long)sh.tot[3 * L + 1];
+  const long long nonconv = (long long)sh.tot[3 * L + 2];
+  // the energy total has converged if it moved less than tol against each of
+  // the previous W totals
+  const bool em_ok = __ballot(lane < W && !(fabs(T - hist) < G.tol)) == 0;
+  if (lane < L) {
+    next_label_theta(sh.tot[3 * lane], sh.tot[3 * lane + 1], sh.tot[3 * lane + 2], G.sigma_min, false, mu, sg, wl,
+                     lg);
+    st->th[t & 1].mu[lane] = mu;
+    st->th[t & 1].sigma[lane] = sg;
+    st->th[t & 1].w[lane] = wl;
+    st->th[t & 1].lg[lane] = lg;
   }
-  st->ties_total += ties;
-  if (nonconv == 0 && tp >= W && st->map_conv < 0) st->map_conv = tp;
-  if (tp >= W && st->em_conv < 0) {
-    bool ok = true;
-    for (int w = 1; w <= W; ++w)
-      if (!(fabs(T - sh.hist[w - 1]) < G.tol)) ok = false;
-    if (ok) st->em_conv = tp;
+  if (lane == 0) {
+    gbl(G.thist)[tp] = T;
+    if (G.out_trace) gbl(G.out_trace)[tp] = T;
+    if (G.out_stats) {
+      gbl(G.out_stats)[2 * tp] = ties;
+      gbl(G.out_stats)[2 * tp + 1] = nonconv;
+    }
+    st->ties_total = ties_total + ties;
+    if (nonconv == 0 && tp >= W && map_conv < 0) st->map_conv = tp;
+    if (tp >= W && em_conv < 0 && em_ok) st->em_conv = tp;
+    st->iters = t;
+    if (G.early_exit && nonconv == 0 && tp >= W) st->done = 1;
   }
-  update_theta(&sh.th, sh.tot, L, G.sigma_min, false);
-  for (int l = 0; l < L; ++l) {
-    st->th[t & 1].mu[l] = sh.th.mu[l];
-    st->th[t & 1].sigma[l] = sh.th.sigma[l];
-    st->th[t & 1].w[l] = sh.th.w[l];
-    st->th[t & 1].lg[l] = sh.th.lg[l];
-  }
-  st->iters = t;
-  if (G.early_exit && nonconv == 0 && tp >= W) st->done = 1;
+}
+
+// The parameter update of iteration t - 1 (one block per graph).
+template <int LMAX>
+__global__ __launch_bounds__(kFoldThreads) void k_fold(const GraphDev *graphs, int B, int t) {
+  __shared__ FoldLds<LMAX> sh;
+  fold_iteration<LMAX>(graphs[blockIdx.x], t, sh, blockDim.x >> 6, threadIdx.x >> 6, threadIdx.x & 63);
 }
 
 // One EM iteration over every graph of the launch.  Block b of a graph owns
@@ -1130,7 +1125,7 @@ __device__ __forceinline__ void fold_iteration(const GraphDev &G, int t, FoldLds
 // the superchunk's record (buffer t & 1).
 template <int LMAX>
 __device__ __forceinline__ void iter_superchunk(const GraphDev *__restrict__ graphs, int B, int sc, int t,
-                                                long long (*part)[rec_words(LMAX)], double *mb, uint64_t *pl,
+                                                double (*part)[rec_words(LMAX)], double *mb, uint64_t *pl,
                                                 double *od, int *oa, int nw, int wave, int lane) {
   const int g = find_graph(graphs, B, sc, false);
   const GraphDev &G = graphs[g];
@@ -1173,18 +1168,8 @@ __device__ __forceinline__ void iter_superchunk(const GraphDev *__restrict__ gra
     const int words = rec_words(c.L);
     if (threadIdx.x < words) {
       const int w = threadIdx.x;
-      long long out;
-      if (word_is_double(w, c.L)) {
-        double acc = 0.0;
-        for (int k = 0; k < c1 - c0; ++k) acc = acc + __longlong_as_double(part[k][w]);
-        out = __double_as_longlong(acc);
-      } else if (w == 3 * c.L + 3) {
-        out = 0;
-        for (int k = 0; k < c1 - c0; ++k) out |= part[k][w];
-      } else {
-        out = 0;
-        for (int k = 0; k < c1 - c0; ++k) out += part[k][w];
-      }
+      double out = 0.0;
+      for (int k = 0; k < c1 - c0; ++k) out = out + part[k][w];
       gbl(G.rec)[(size_t)(t & 1) * G.rec_stride + (size_t)w * G.nsuper + b] = out;
     }
   }
@@ -1196,7 +1181,7 @@ template <int LMAX, bool PERSIST>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(LMAX <= 2 ? 5 : 1, 8))) void k_iter(
     const GraphDev *__restrict__ graphs, int B, int nsuper_total, int t) {
   extern __shared__ double smem[];
-  __shared__ long long part[kSuperChunks][rec_words(LMAX)];
+  __shared__ double part[kSuperChunks][rec_words(LMAX)];
   const int nw = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   double *mb = smem + wave * kWaveLds;
   uint64_t *pl = reinterpret_cast<uint64_t *>(mb + kGroupTiles * 64);
@@ -1212,12 +1197,6 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(LMAX <= 2 
   }
 }
 
-// The parameter update of iteration t - 1 (one block per graph).
-template <int LMAX>
-__global__ __launch_bounds__(kFoldThreads) void k_fold(const GraphDev *graphs, int B, int t) {
-  __shared__ FoldLds<LMAX> sh;
-  fold_iteration<LMAX>(graphs[blockIdx.x], t, sh, blockDim.x >> 6, threadIdx.x >> 6, threadIdx.x & 63);
-}
 
 // Copy results to the caller's buffers.
 __global__ void k_final(const GraphDev *graphs, int B) {
@@ -1402,7 +1381,7 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
     G.ring = reinterpret_cast<double *>(ws + plan.ring_off[i]);
     G.thist = reinterpret_cast<double *>(ws + plan.thist_off[i]);
     G.st = reinterpret_cast<GraphState *>(ws + plan.state_off[i]);
-    G.rec = reinterpret_cast<long long *>(ws + plan.rec_off[i]);
+    G.rec = reinterpret_cast<double *>(ws + plan.rec_off[i]);
     G.in_mu = it.d_mu;
     G.in_sigma = it.d_sigma;
     G.out_mu = it.d_mu;
