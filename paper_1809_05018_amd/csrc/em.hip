@@ -68,7 +68,7 @@ __device__ __forceinline__ gptr<T> gbl(T *p) {
 // every word of every record is combined with the same double addition.
 __host__ __device__ constexpr int rec_words(int L) { return 3 * L + 4; }
 constexpr int kRecMax = 3 * kMaxLabels + 4;
-constexpr int kChunkTiles = 8;     // packets per statistics chunk (fixed: part of the result's definition)
+
 constexpr int kSuperChunks = 4;    // chunks per block and record (fixed: part of the result's definition)
 constexpr int kGroupTiles = 8;     // packets per neighbourhood-sum group (LDS buffer of 512 minima)
 constexpr int kVertPerBlock = 1024;
@@ -94,6 +94,9 @@ struct GraphDev {
   const TileDesc *tiles;
   const int32_t *vid;
   const uint32_t *mask;
+  const ChunkHdr *chdr;  // slot layout
+  const int32_t *svid;
+  const uint32_t *smask, *smask_hi;
   const int32_t *hood_ptr;  // element offset of each neighbourhood, H+1 entries
   const double *y;
   int32_t *x0;   // caller labels (even iterations read here)
@@ -315,11 +318,15 @@ struct Ctx {
   gptr<const TileDesc> tiles;
   gptr<const int32_t> vid;
   gptr<const uint32_t> mask;
+  gptr<const ChunkHdr> chdr;
+  gptr<const int32_t> svid;
+  gptr<const uint32_t> smask, smask_hi;
   gptr<const int32_t> hood_ptr;
   gptr<const double> y;
   gptr<const int32_t> xr;
   gptr<int32_t> xw;
   gptr<double> ring;
+  gptr<const GraphState> st;
   int H, W, L, P, t, ntiles, nchunks;
   double beta, tol, tie_eps;
 };
@@ -699,25 +706,29 @@ struct ChunkStats {
   }
 };
 
-// Element pass of one SMALL or MID packet on the lean path.
+// Element pass of one SMALL or MID packet on the slot layout.  v < 0 marks an
+// unused slot; smask is the packet's neighbourhood-start mask, eoff its first
+// element relative to the chunk, am the element's first adjacency word; the
+// second word of a MID packet is read here from slot (ti, lane).
 template <int LMAX>
-__device__ __forceinline__ void lean_elem(const Ctx &c, const TileDesc &td, int v, uint32_t am_lo, int xv, double yv,
-                                          int gstart, const Theta<LMAX> &th, uint64_t below, ChunkStats<LMAX> &cs,
-                                          double *mb, double *od, int *oa, int &ocount, int lane) {
-  const bool valid = lane < td.nelem;
+__device__ __forceinline__ void slot_elem(const Ctx &c, uint64_t smask, int eoff, bool mid, int ti, int v,
+                                          uint32_t am, int xv, double yv, const Theta<LMAX> &th, uint64_t below,
+                                          ChunkStats<LMAX> &cs, double *mb, double *od, int *oa, int &ocount,
+                                          int lane) {
+  const bool valid = v >= 0;
   if (valid && (unsigned)xv >= (unsigned)c.L) cs.err |= 1;
   uint64_t planes[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k)
     if (k < c.P) planes[k] = __ballot(valid && ((xv >> k) & 1));
-  const int base = 63 - __clzll(td.start_mask & below);
+  const int base = 63 - __clzll(smask & below);
   const int j = lane - base;
   int deg, cnt[LMAX];
   bool owner;
-  if (td.words == 1) {
+  if (!mid) {
     const uint32_t self = 1u << (j & 31);
-    owner = valid && (am_lo & self);
-    const uint32_t nbr = am_lo & ~self;
+    owner = valid && (am & self);
+    const uint32_t nbr = am & ~self;
     deg = __popc(nbr);
 #pragma unroll
     for (int l = 0; l < LMAX; ++l) {
@@ -731,11 +742,10 @@ __device__ __forceinline__ void lean_elem(const Ctx &c, const TileDesc &td, int 
       cnt[l] = __popc(nbr & eq);
     }
   } else {
-    uint64_t am = am_lo;
-    if (valid) am |= (uint64_t)c.mask[td.mask_start + 2 * lane + 1] << 32;
+    const uint64_t a64 = (uint64_t)am | ((uint64_t)c.smask_hi[(size_t)ti * kWave + lane] << 32);
     const uint64_t self = 1ull << (j & 63);
-    owner = valid && (am & self);
-    const uint64_t nbr = am & ~self;
+    owner = valid && (a64 & self);
+    const uint64_t nbr = a64 & ~self;
     deg = __popcll(nbr);
 #pragma unroll
     for (int l = 0; l < LMAX; ++l) {
@@ -777,7 +787,7 @@ __device__ __forceinline__ void lean_elem(const Ctx &c, const TileDesc &td, int 
     ocount += __popcll(ob);
     cs.ties += __popcll(__ballot(owner && gap < c.tie_eps));
   }
-  if (valid) mb[td.elem_start - gstart + lane] = m;
+  if (valid) mb[eoff + lane] = m;
 }
 
 // Neighbourhood pass of the lean path: lane per neighbourhood, offsets and
@@ -826,29 +836,58 @@ __device__ __forceinline__ void lean_hoods(const Ctx &c, int h0, int h1, int gst
   }
 }
 
-// Lean chunk (no LARGE packet, window <= 4): loads of the whole chunk first,
-// then the element passes, the owner list and the neighbourhood pass.
+// Run state and parameters of iteration c.t (uniform scalar loads); every slot
+// holds kMaxLabels >= LMAX entries.
 template <int LMAX>
-__device__ void chunk_lean(const Ctx &c, int tb, int te, int hend, const Theta<LMAX> &th, double *row,
-                           double *mb, double *od, int *oa, int lane) {
-  ChunkStats<LMAX> cs;
-  cs.clear();
-  const int nt = te - tb;
-  const uint64_t below = (2ull << lane) - 1ull;  // lanes 0..lane
-  const TileDesc t0 = load_tile(c.tiles + tb);
-  const int h0 = t0.hood_start, gstart = t0.elem_start;
+__device__ __forceinline__ int load_theta(const Ctx &c, Theta<LMAX> &th) {
+#pragma unroll
+  for (int l = 0; l < LMAX; ++l) {
+    th.mu[l] = c.st->th[c.t & 1].mu[l];
+    th.w[l] = c.st->th[c.t & 1].w[l];
+    th.lg[l] = c.st->th[c.t & 1].lg[l];
+  }
+  return c.st->done;
+}
+
+// Chunk on the slot layout.  The chunk's member ids and adjacency words are
+// requested from the chunk index alone, together with its header; then the
+// label and intensity gathers and the offsets and window values of the chunk's
+// first 64 neighbourhoods; then the
+// element passes, the owner list and the neighbourhood pass.  Returns false,
+// having written nothing, when the chunk has a LARGE packet or the window is
+// longer than kPreWindow (the packet-by-packet path takes those), and true
+// without writing when the run is already done.  done and th arrive with the
+// chunk's loads (they are requested before the kernel's first store).
+template <int LMAX>
+__device__ bool chunk_slots(const Ctx &c, int ck, bool done, const Theta<LMAX> &th, double *row, double *mb,
+                            double *od, int *oa, int lane) {
+  const int tb = ck * kChunkTiles;
+  const int nt = min(kChunkTiles, c.ntiles - tb);
   int v[kChunkTiles];
   uint32_t am[kChunkTiles];
 #pragma unroll
   for (int i = 0; i < kChunkTiles; ++i) {
-    v[i] = 0;
+    v[i] = -1;
     am[i] = 0;
     if (i < nt) {
-      const TileDesc t = load_tile(c.tiles + tb + i);
-      if (lane < t.nelem) {
-        v[i] = c.vid[t.elem_start + lane];
-        am[i] = c.mask[t.mask_start + t.words * lane];
-      }
+      v[i] = c.svid[(size_t)(tb + i) * kWave + lane];
+      am[i] = c.smask[(size_t)(tb + i) * kWave + lane];
+    }
+  }
+  const gptr<const ChunkHdr> hp = c.chdr + ck;
+  const int flags = hp->flags;
+  if ((flags & kHdrLarge) || c.W > kPreWindow) return false;
+  if (done) return true;
+  const int gstart = hp->elem_start, h0 = hp->hood_start, hend = hp->hood_end;
+  int xv[kChunkTiles];
+  double yv[kChunkTiles];
+#pragma unroll
+  for (int i = 0; i < kChunkTiles; ++i) {
+    xv[i] = 0;
+    yv[i] = 0.0;
+    if (i < nt && v[i] >= 0) {
+      xv[i] = c.xr[v[i]];
+      yv[i] = c.y[v[i]];
     }
   }
   HoodPre pre{0, 0, {}};
@@ -865,17 +904,9 @@ __device__ void chunk_lean(const Ctx &c, int tb, int te, int hend, const Theta<L
       }
     }
   }
-  int xv[kChunkTiles];
-  double yv[kChunkTiles];
-#pragma unroll
-  for (int i = 0; i < kChunkTiles; ++i) {
-    xv[i] = 0;
-    yv[i] = 0.0;
-    if (i < nt && lane < load_tile(c.tiles + tb + i).nelem) {
-      xv[i] = c.xr[v[i]];
-      yv[i] = c.y[v[i]];
-    }
-  }
+  ChunkStats<LMAX> cs;
+  cs.clear();
+  const uint64_t below = (2ull << lane) - 1ull;  // lanes 0..lane
   int ocount = 0;
 #pragma unroll
   for (int i = 0; i < kChunkTiles; ++i)
@@ -886,32 +917,29 @@ __device__ void chunk_lean(const Ctx &c, int tb, int te, int hend, const Theta<L
         ocount = 0;
         wave_lds_sync();
       }
-      lean_elem<LMAX>(c, load_tile(c.tiles + tb + i), v[i], am[i], xv[i], yv[i], gstart, th, below, cs, mb, od, oa,
-                      ocount, lane);
+      slot_elem<LMAX>(c, hp->start_mask[i], hp->elem_off[i], (flags >> (kHdrMidShift + i)) & 1, tb + i, v[i], am[i],
+                      xv[i], yv[i], th, below, cs, mb, od, oa, ocount, lane);
     }
   wave_lds_sync();
   cs.take_owners(od, oa, ocount, lane);
   lean_hoods<LMAX>(c, h0, hend, gstart, pre, cs, mb, lane);
   wave_lds_sync();
   cs.store(row, c.L, lane);
+  return true;
 }
-
-
 
 // One statistics chunk: packets [ck*8, min(ntiles, ck*8+8)).
 //
-// Fast path (no LARGE packet, window <= 4): the loads of the whole chunk are
-// issued before any computation -- packet descriptors (one per lane), then the
-// id and mask streams of all packets together with the offsets and window
-// values of the chunk's first 64 neighbourhoods, then the label and intensity
-// gathers of all packets -- so a wave waits for memory a few times per chunk
-// instead of at every dependent load of every packet.  The other path goes
-// packet by packet.  Which path a chunk takes depends only on the graph and
-// the window length, never on the launch shape, so results stay independent of
-// it (the two paths add the owner statistics in different lane orders).
+// Chunks without a LARGE packet (window <= 4) take the slot layout, where the
+// wave waits for memory twice per chunk (chunk_slots).  The others go packet by
+// packet over the element arrays.  Which path a chunk takes depends only on the
+// graph and the window length, never on the launch shape, so results stay
+// independent of it (the two paths add the owner statistics in different lane
+// orders).
 template <int LMAX>
-__device__ void do_chunk(const Ctx &c, int ck, const Theta<LMAX> &th, double *part, double *mb, uint64_t *pl,
-                         double *od, int *oa, int lane) {
+__device__ void do_chunk(const Ctx &c, int ck, bool done, const Theta<LMAX> &th, double *part, double *mb,
+                         uint64_t *pl, double *od, int *oa, int lane) {
+  if (chunk_slots<LMAX>(c, ck, done, th, part, mb, od, oa, lane) || done) return;
   LaneStats<LMAX> ls;
   ls.clear();
   const int tb = ck * kChunkTiles, te = min(c.ntiles, tb + kChunkTiles);
@@ -921,10 +949,8 @@ __device__ void do_chunk(const Ctx &c, int ck, const Theta<LMAX> &th, double *pa
   if (lane <= nt && tb + lane < c.ntiles) mine = load_tile(c.tiles + tb + lane);
   const bool any_large = __ballot(lane < nt && mine.kind == kLarge) != 0;
   const int hend = te < c.ntiles ? bcast(mine.hood_start, nt) : c.H;
-  if (!any_large && c.W <= kPreWindow) {
-    chunk_lean<LMAX>(c, tb, te, hend, th, part, mb, od, oa, lane);
-    return;
-  } else {
+  (void)any_large;
+  {
     int g0 = tb;  // first packet of the pending neighbourhood group
     int gstart = 0, ghood = 0;
     for (int i = 0; i < nt; ++i) {
@@ -1124,27 +1150,20 @@ __global__ __launch_bounds__(kFoldThreads) void k_fold(const GraphDev *graphs, i
 // each chunk's statistics in LDS, and the block adds them in chunk order into
 // the superchunk's record (buffer t & 1).
 template <int LMAX>
-__device__ __forceinline__ void iter_superchunk(const GraphDev *__restrict__ graphs, int B, int sc, int t,
-                                                double (*part)[rec_words(LMAX)], double *mb, uint64_t *pl,
-                                                double *od, int *oa, int nw, int wave, int lane) {
-  const int g = find_graph(graphs, B, sc, false);
-  const GraphDev &G = graphs[g];
+__device__ __forceinline__ void iter_superchunk(const GraphDev &G, int sc, int t, double (*part)[rec_words(LMAX)],
+                                                double *mb, uint64_t *pl, double *od, int *oa, int nw, int wave,
+                                                int lane) {
   if (t >= G.max_iters) return;
-  gptr<const GraphState> st = gbl((const GraphState *)G.st);
-  const int done = st->done;  // read with the parameters below (one wait)
-  Theta<LMAX> th;
-#pragma unroll
-  for (int l = 0; l < LMAX; ++l) {
-    th.mu[l] = l < G.L ? st->th[t & 1].mu[l] : 0.0;
-    th.w[l] = l < G.L ? st->th[t & 1].w[l] : 0.0;
-    th.lg[l] = l < G.L ? st->th[t & 1].lg[l] : 0.0;
-  }
-  if (done) return;
   {
     Ctx c;
     c.tiles = gbl(G.tiles);
     c.vid = gbl(G.vid);
     c.mask = gbl(G.mask);
+    c.chdr = gbl(G.chdr);
+    c.svid = gbl(G.svid);
+    c.smask = gbl(G.smask);
+    c.smask_hi = gbl(G.smask_hi);
+    c.st = gbl((const GraphState *)G.st);
     c.hood_ptr = gbl(G.hood_ptr);
     c.y = gbl(G.y);
     c.xr = gbl((const int32_t *)((t & 1) ? G.x1 : G.x0));
@@ -1163,10 +1182,13 @@ __device__ __forceinline__ void iter_superchunk(const GraphDev *__restrict__ gra
     const int b = sc - G.block0;
     const int c0 = b * kSuperChunks;
     const int c1 = min(G.nchunks, c0 + kSuperChunks);
-    for (int ck = c0 + wave; ck < c1; ck += nw) do_chunk<LMAX>(c, ck, th, part[ck - c0], mb, pl, od, oa, lane);
+    Theta<LMAX> th;
+    const bool done = load_theta<LMAX>(c, th);  // uniform scalar loads, waited for with the chunk's loads
+    for (int ck = c0 + wave; ck < c1; ck += nw)
+      do_chunk<LMAX>(c, ck, done, th, part[ck - c0], mb, pl, od, oa, lane);
     __syncthreads();
     const int words = rec_words(c.L);
-    if (threadIdx.x < words) {
+    if (!done && threadIdx.x < words) {
       const int w = threadIdx.x;
       double out = 0.0;
       for (int k = 0; k < c1 - c0; ++k) out = out + part[k][w];
@@ -1176,10 +1198,13 @@ __device__ __forceinline__ void iter_superchunk(const GraphDev *__restrict__ gra
 }
 
 // PERSIST = false: block b works on superchunk b.  PERSIST = true: a grid sized
-// to the machine whose blocks walk all superchunks.
-template <int LMAX, bool PERSIST>
+// to the machine whose blocks walk all superchunks.  SINGLE: one graph, whose
+// descriptor g1 travels in the kernel arguments (its fields are then at hand
+// without a dependent load); otherwise each block looks its graph up in
+// graphs[0 .. B).
+template <int LMAX, bool PERSIST, bool SINGLE>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(LMAX <= 2 ? 5 : 1, 8))) void k_iter(
-    const GraphDev *__restrict__ graphs, int B, int nsuper_total, int t) {
+    const GraphDev *__restrict__ graphs, const GraphDev g1, int B, int nsuper_total, int t) {
   extern __shared__ double smem[];
   __shared__ double part[kSuperChunks][rec_words(LMAX)];
   const int nw = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -1188,10 +1213,17 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(LMAX <= 2 
   double *od = mb + kGroupTiles * 64 + 64;
   int *oa = reinterpret_cast<int *>(od + kOwnCap);
   if constexpr (!PERSIST) {
-    iter_superchunk<LMAX>(graphs, B, blockIdx.x, t, part, mb, pl, od, oa, nw, wave, lane);
+    if constexpr (SINGLE)
+      iter_superchunk<LMAX>(g1, blockIdx.x, t, part, mb, pl, od, oa, nw, wave, lane);
+    else
+      iter_superchunk<LMAX>(graphs[find_graph(graphs, B, blockIdx.x, false)], blockIdx.x, t, part, mb, pl, od, oa,
+                            nw, wave, lane);
   } else {
     for (int sc = blockIdx.x; sc < nsuper_total; sc += gridDim.x) {
-      iter_superchunk<LMAX>(graphs, B, sc, t, part, mb, pl, od, oa, nw, wave, lane);
+      if constexpr (SINGLE)
+        iter_superchunk<LMAX>(g1, sc, t, part, mb, pl, od, oa, nw, wave, lane);
+      else
+        iter_superchunk<LMAX>(graphs[find_graph(graphs, B, sc, false)], sc, t, part, mb, pl, od, oa, nw, wave, lane);
       __syncthreads();  // part[] is reused by the next superchunk
     }
   }
@@ -1374,6 +1406,10 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
     G.tiles = reinterpret_cast<const TileDesc *>(hb + h->layout.tiles_off);
     G.vid = reinterpret_cast<const int32_t *>(hb + h->layout.vid_off);
     G.mask = reinterpret_cast<const uint32_t *>(hb + h->layout.mask_off);
+    G.chdr = reinterpret_cast<const ChunkHdr *>(hb + h->layout.chdr_off);
+    G.svid = reinterpret_cast<const int32_t *>(hb + h->layout.svid_off);
+    G.smask = reinterpret_cast<const uint32_t *>(hb + h->layout.smask_off);
+    G.smask_hi = reinterpret_cast<const uint32_t *>(hb + h->layout.smaskhi_off);
     G.hood_ptr = reinterpret_cast<const int32_t *>(hb + h->layout.hptr_off);
     G.y = it.d_y;
     G.x0 = it.d_labels;
@@ -1462,12 +1498,20 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
     }
     for (int t = 0; t < max_iters; ++t) {
       if (events) HIP_TRY(prof_mark(s, true));
-#define PMRF_LAUNCH_ITER(LM)                                                                                   \
-  do {                                                                                                         \
-    if (persist)                                                                                               \
-      hipLaunchKernelGGL((k_iter<LM, true>), dim3(grid_iter), dim3(threads), lds, s, gd, B, blocks_iter, t);  \
-    else                                                                                                       \
-      hipLaunchKernelGGL((k_iter<LM, false>), dim3(grid_iter), dim3(threads), lds, s, gd, B, blocks_iter, t); \
+#define PMRF_LAUNCH_ITER(LM)                                                                                  \
+  do {                                                                                                        \
+    if (persist && B == 1)                                                                                    \
+      hipLaunchKernelGGL((k_iter<LM, true, true>), dim3(grid_iter), dim3(threads), lds, s, gd, desc[0], B,     \
+                         blocks_iter, t);                                                                     \
+    else if (persist)                                                                                         \
+      hipLaunchKernelGGL((k_iter<LM, true, false>), dim3(grid_iter), dim3(threads), lds, s, gd, desc[0], B,    \
+                         blocks_iter, t);                                                                     \
+    else if (B == 1)                                                                                          \
+      hipLaunchKernelGGL((k_iter<LM, false, true>), dim3(grid_iter), dim3(threads), lds, s, gd, desc[0], B,    \
+                         blocks_iter, t);                                                                     \
+    else                                                                                                      \
+      hipLaunchKernelGGL((k_iter<LM, false, false>), dim3(grid_iter), dim3(threads), lds, s, gd, desc[0], B,   \
+                         blocks_iter, t);                                                                     \
   } while (0)
       switch (lm) {
         case 2: PMRF_LAUNCH_ITER(2); break;

@@ -259,13 +259,51 @@ extern "C" pmrf_status pmrf_build_neighborhoods(int32_t n, const int32_t *row_pt
       }
       for (int32_t j = 0; j < s; ++j) loc[hd->hood_vid[o + j]] = -1;
     }
+    // slot layout and chunk headers: packet t's elements in slots [64 t, 64 t + 64)
+    const int64_t ntiles = (int64_t)hd->tiles.size();
+    const int64_t nchunks = (ntiles + kChunkTiles - 1) / kChunkTiles;
+    bool any_mid = false;
+    for (const TileDesc &t : hd->tiles) any_mid |= t.kind == kMid;
+    hd->svid.assign((size_t)ntiles * kWave, -1);
+    hd->smask.assign((size_t)ntiles * kWave, 0u);
+    hd->smask_hi.assign(any_mid ? (size_t)ntiles * kWave : 0, 0u);
+    hd->chdr.assign((size_t)nchunks, ChunkHdr{});
+    for (int64_t ti = 0; ti < ntiles; ++ti) {
+      const TileDesc &t = hd->tiles[ti];
+      if (t.kind == kLarge) continue;
+      for (int k = 0; k < t.nelem; ++k) {
+        hd->svid[ti * kWave + k] = hd->hood_vid[t.elem_start + k];
+        hd->smask[ti * kWave + k] = hd->mask[t.mask_start + (size_t)k * t.words];
+        if (t.kind == kMid) hd->smask_hi[ti * kWave + k] = hd->mask[t.mask_start + (size_t)k * t.words + 1];
+      }
+    }
+    for (int64_t ck = 0; ck < nchunks; ++ck) {
+      ChunkHdr &c = hd->chdr[ck];
+      const int64_t tb = ck * kChunkTiles, te = std::min(ntiles, tb + kChunkTiles);
+      c.elem_start = hd->tiles[tb].elem_start;
+      c.hood_start = hd->tiles[tb].hood_start;
+      c.hood_end = te < ntiles ? hd->tiles[te].hood_start : (int32_t)hd->H;
+      for (int64_t ti = tb; ti < te; ++ti) {
+        const TileDesc &t = hd->tiles[ti];
+        const int i = (int)(ti - tb);
+        c.start_mask[i] = t.start_mask;
+        if (t.kind == kLarge) c.flags |= kHdrLarge;
+        if (t.kind == kMid) c.flags |= 1 << (kHdrMidShift + i);
+        // offsets of a chunk without LARGE packets stay below 8 * 64
+        c.elem_off[i] = (uint16_t)std::min<int64_t>(t.elem_start - c.elem_start, 0xffff);
+      }
+    }
     DeviceLayout &L = hd->layout;
     L.tiles_off = 0;
-    L.hptr_off = align_up((int64_t)hd->tiles.size() * (int64_t)sizeof(TileDesc), 256);
+    L.hptr_off = align_up(ntiles * (int64_t)sizeof(TileDesc), 256);
     L.vid_off = L.hptr_off + align_up((hd->H + 1) * 4, 256);
     hd->hood_ptr32.assign(hd->hood_ptr.begin(), hd->hood_ptr.end());
     L.mask_off = L.vid_off + align_up(hd->M * 4, 256);
-    L.total = L.mask_off + align_up((int64_t)hd->mask.size() * 4, 256);
+    L.chdr_off = L.mask_off + align_up((int64_t)hd->mask.size() * 4, 256);
+    L.svid_off = L.chdr_off + align_up(nchunks * (int64_t)sizeof(ChunkHdr), 256);
+    L.smask_off = L.svid_off + align_up((int64_t)hd->svid.size() * 4, 256);
+    L.smaskhi_off = L.smask_off + align_up((int64_t)hd->smask.size() * 4, 256);
+    L.total = L.smaskhi_off + align_up((int64_t)hd->smask_hi.size() * 4, 256);
     if (L.total == 0) L.total = 256;
   } catch (const std::bad_alloc &) {
     delete hd;
@@ -319,6 +357,16 @@ extern "C" pmrf_status pmrf_hoods_upload(const pmrf_hoods *h, void *d_buf, int64
     e = hipMemcpyAsync(base + h->layout.vid_off, h->hood_vid.data(), (size_t)h->M * 4, hipMemcpyHostToDevice, s);
   if (e == hipSuccess && !h->mask.empty())
     e = hipMemcpyAsync(base + h->layout.mask_off, h->mask.data(), h->mask.size() * 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && !h->chdr.empty())
+    e = hipMemcpyAsync(base + h->layout.chdr_off, h->chdr.data(), h->chdr.size() * sizeof(ChunkHdr),
+                       hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && !h->svid.empty())
+    e = hipMemcpyAsync(base + h->layout.svid_off, h->svid.data(), h->svid.size() * 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && !h->smask.empty())
+    e = hipMemcpyAsync(base + h->layout.smask_off, h->smask.data(), h->smask.size() * 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && !h->smask_hi.empty())
+    e = hipMemcpyAsync(base + h->layout.smaskhi_off, h->smask_hi.data(), h->smask_hi.size() * 4,
+                       hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return fail(PMRF_EDEVICE, std::string("hipMemcpyAsync: ") + hipGetErrorString(e));
   return PMRF_OK;
 }

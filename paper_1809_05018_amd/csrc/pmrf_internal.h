@@ -35,9 +35,30 @@ struct TileDesc {
 };
 static_assert(sizeof(TileDesc) == 24, "TileDesc layout");
 
+constexpr int kChunkTiles = 8;  // packets per statistics chunk (part of the result's definition)
+
+// Header of one chunk of kChunkTiles consecutive packets, for the slot layout:
+// packet t owns slots [64 t, 64 t + 64) of the slot arrays (member id, low and
+// high adjacency word; unused slots hold id -1), so a wave can request a
+// chunk's element data knowing only the chunk index.  Chunks with a LARGE
+// packet are processed from the element arrays instead.
+struct ChunkHdr {
+  uint64_t start_mask[kChunkTiles];  // per packet: bit i set if lane i starts a neighbourhood
+  int32_t elem_start;                // first element of the chunk (element arrays)
+  int32_t hood_start, hood_end;      // the chunk holds neighbourhoods [hood_start, hood_end)
+  int32_t flags;                     // bit 0: a LARGE packet; bit 8 + i: packet i is MID (two words)
+  uint16_t elem_off[kChunkTiles];    // first element of packet i, relative to elem_start
+  int32_t pad[8];
+};
+static_assert(sizeof(ChunkHdr) == 128, "ChunkHdr layout");
+constexpr int kHdrLarge = 1;
+constexpr int kHdrMidShift = 8;
+
 // Offsets (bytes) of the arrays inside the uploaded device buffer.
 struct DeviceLayout {
-  int64_t tiles_off, hptr_off, vid_off, mask_off, total;
+  int64_t tiles_off, hptr_off, vid_off, mask_off;
+  int64_t chdr_off, svid_off, smask_off, smaskhi_off;  // slot layout
+  int64_t total;
 };
 
 inline int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
@@ -58,6 +79,9 @@ struct pmrf_hoods {
   // device layout, built once
   std::vector<pmrf::TileDesc> tiles;
   std::vector<uint32_t> mask;  // adjacency words (bit j' = in-hood neighbour j'; own bit = owner flag)
+  std::vector<pmrf::ChunkHdr> chdr;               // one per chunk of packets
+  std::vector<int32_t> svid;                      // slot layout: member id (-1: unused slot)
+  std::vector<uint32_t> smask, smask_hi;          // slot layout: adjacency words 0 and 1 (the latter only if MID packets exist)
   pmrf::DeviceLayout layout{};
 };
 
