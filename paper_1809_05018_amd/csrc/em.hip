@@ -33,6 +33,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <cmath>
 #include <cstring>
 #include <list>
@@ -70,7 +71,10 @@ __host__ __device__ constexpr int rec_words(int L) { return 3 * L + 4; }
 constexpr int kRecMax = 3 * kMaxLabels + 4;
 
 constexpr int kSuperChunks = 4;    // chunks per block and record (fixed: part of the result's definition)
-constexpr int kGroupTiles = 8;     // packets per neighbourhood-sum group (LDS buffer of 512 minima)
+constexpr int kGroupTiles = kChunkTiles;  // packets per neighbourhood-sum group (LDS buffer of 64 minima each)
+#ifndef PMRF_ITER_WAVES_PER_EU
+#define PMRF_ITER_WAVES_PER_EU 5
+#endif
 constexpr int kVertPerBlock = 1024;
 
 // Parameters of the labels, with the two values each energy uses
@@ -715,12 +719,12 @@ __device__ __forceinline__ void slot_elem(const Ctx &c, uint64_t smask, int eoff
                                           uint32_t am, int xv, double yv, const Theta<LMAX> &th, uint64_t below,
                                           ChunkStats<LMAX> &cs, double *mb, double *od, int *oa, int &ocount,
                                           int lane) {
+  constexpr int PMAX = LMAX <= 2 ? 1 : LMAX <= 4 ? 2 : LMAX <= 8 ? 3 : 4;  // label bit planes
   const bool valid = v >= 0;
   if (valid && (unsigned)xv >= (unsigned)c.L) cs.err |= 1;
-  uint64_t planes[4];
+  uint64_t planes[PMAX];
 #pragma unroll
-  for (int k = 0; k < 4; ++k)
-    if (k < c.P) planes[k] = __ballot(valid && ((xv >> k) & 1));
+  for (int k = 0; k < PMAX; ++k) planes[k] = (k < c.P) ? __ballot(valid && ((xv >> k) & 1)) : 0ull;
   const int base = 63 - __clzll(smask & below);
   const int j = lane - base;
   int deg, cnt[LMAX];
@@ -730,16 +734,21 @@ __device__ __forceinline__ void slot_elem(const Ctx &c, uint64_t smask, int eoff
     owner = valid && (am & self);
     const uint32_t nbr = am & ~self;
     deg = __popc(nbr);
+    if constexpr (LMAX == 2) {  // neighbours with label 1; the rest have label 0
+      cnt[1] = __popc(nbr & (uint32_t)(planes[0] >> base));
+      cnt[0] = deg - cnt[1];
+    } else {
 #pragma unroll
-    for (int l = 0; l < LMAX; ++l) {
-      uint32_t eq = ~0u;
+      for (int l = 0; l < LMAX; ++l) {
+        uint32_t eq = ~0u;
 #pragma unroll
-      for (int k = 0; k < 4; ++k)
-        if (k < c.P) {
-          const uint32_t pk = (uint32_t)(planes[k] >> base);
-          eq &= ((l >> k) & 1) ? pk : ~pk;
-        }
-      cnt[l] = __popc(nbr & eq);
+        for (int k = 0; k < PMAX; ++k)
+          if (k < c.P) {
+            const uint32_t pk = (uint32_t)(planes[k] >> base);
+            eq &= ((l >> k) & 1) ? pk : ~pk;
+          }
+        cnt[l] = __popc(nbr & eq);
+      }
     }
   } else {
     const uint64_t a64 = (uint64_t)am | ((uint64_t)c.smask_hi[(size_t)ti * kWave + lane] << 32);
@@ -747,16 +756,21 @@ __device__ __forceinline__ void slot_elem(const Ctx &c, uint64_t smask, int eoff
     owner = valid && (a64 & self);
     const uint64_t nbr = a64 & ~self;
     deg = __popcll(nbr);
+    if constexpr (LMAX == 2) {
+      cnt[1] = __popcll(nbr & (planes[0] >> base));
+      cnt[0] = deg - cnt[1];
+    } else {
 #pragma unroll
-    for (int l = 0; l < LMAX; ++l) {
-      uint64_t eq = ~0ull;
+      for (int l = 0; l < LMAX; ++l) {
+        uint64_t eq = ~0ull;
 #pragma unroll
-      for (int k = 0; k < 4; ++k)
-        if (k < c.P) {
-          const uint64_t pk = planes[k] >> base;
-          eq &= ((l >> k) & 1) ? pk : ~pk;
-        }
-      cnt[l] = __popcll(nbr & eq);
+        for (int k = 0; k < PMAX; ++k)
+          if (k < c.P) {
+            const uint64_t pk = planes[k] >> base;
+            eq &= ((l >> k) & 1) ? pk : ~pk;
+          }
+        cnt[l] = __popcll(nbr & eq);
+      }
     }
   }
   double m, gap, dsel;
@@ -874,11 +888,18 @@ __device__ bool chunk_slots(const Ctx &c, int ck, bool done, const Theta<LMAX> &
       am[i] = c.smask[(size_t)(tb + i) * kWave + lane];
     }
   }
-  const gptr<const ChunkHdr> hp = c.chdr + ck;
-  const int flags = hp->flags;
+  // the header: dword k in lane k (one load), fields read out with readlane
+  // once it has arrived
+  constexpr int kHdrDw = sizeof(ChunkHdr) / 4;
+  const uint32_t hw = lane < kHdrDw ? gptr<const uint32_t>(c.chdr + ck)[lane] : 0u;
+  auto hdr = [&](int k) { return (uint32_t)__builtin_amdgcn_readlane((int)hw, k); };
+  constexpr int kDwElem = offsetof(ChunkHdr, elem_start) / 4, kDwHood = offsetof(ChunkHdr, hood_start) / 4,
+                kDwHend = offsetof(ChunkHdr, hood_end) / 4, kDwFlags = offsetof(ChunkHdr, flags) / 4,
+                kDwOff = offsetof(ChunkHdr, elem_off) / 4;
+  const int flags = (int)hdr(kDwFlags);
   if ((flags & kHdrLarge) || c.W > kPreWindow) return false;
   if (done) return true;
-  const int gstart = hp->elem_start, h0 = hp->hood_start, hend = hp->hood_end;
+  const int gstart = (int)hdr(kDwElem), h0 = (int)hdr(kDwHood), hend = (int)hdr(kDwHend);
   int xv[kChunkTiles];
   double yv[kChunkTiles];
 #pragma unroll
@@ -917,8 +938,10 @@ __device__ bool chunk_slots(const Ctx &c, int ck, bool done, const Theta<LMAX> &
         ocount = 0;
         wave_lds_sync();
       }
-      slot_elem<LMAX>(c, hp->start_mask[i], hp->elem_off[i], (flags >> (kHdrMidShift + i)) & 1, tb + i, v[i], am[i],
-                      xv[i], yv[i], th, below, cs, mb, od, oa, ocount, lane);
+      const uint64_t smask = (uint64_t)hdr(2 * i) | ((uint64_t)hdr(2 * i + 1) << 32);
+      const int eoff = (int)((hdr(kDwOff + i / 2) >> (16 * (i & 1))) & 0xffffu);
+      slot_elem<LMAX>(c, smask, eoff, (flags >> (kHdrMidShift + i)) & 1, tb + i, v[i], am[i], xv[i], yv[i], th, below,
+                      cs, mb, od, oa, ocount, lane);
     }
   wave_lds_sync();
   cs.take_owners(od, oa, ocount, lane);
@@ -1203,7 +1226,7 @@ __device__ __forceinline__ void iter_superchunk(const GraphDev &G, int sc, int t
 // without a dependent load); otherwise each block looks its graph up in
 // graphs[0 .. B).
 template <int LMAX, bool PERSIST, bool SINGLE>
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(LMAX <= 2 ? 5 : 1, 8))) void k_iter(
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(LMAX <= 2 ? PMRF_ITER_WAVES_PER_EU : 1, 8))) void k_iter(
     const GraphDev *__restrict__ graphs, const GraphDev g1, int B, int nsuper_total, int t) {
   extern __shared__ double smem[];
   __shared__ double part[kSuperChunks][rec_words(LMAX)];

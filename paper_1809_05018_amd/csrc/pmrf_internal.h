@@ -35,7 +35,11 @@ struct TileDesc {
 };
 static_assert(sizeof(TileDesc) == 24, "TileDesc layout");
 
-constexpr int kChunkTiles = 8;  // packets per statistics chunk (part of the result's definition)
+#ifndef PMRF_CHUNK_TILES
+#define PMRF_CHUNK_TILES 8
+#endif
+constexpr int kChunkTiles = PMRF_CHUNK_TILES;  // packets per statistics chunk (part of the result's definition)
+static_assert(kChunkTiles >= 1 && kChunkTiles <= 23, "chunk header layout");
 
 // Header of one chunk of kChunkTiles consecutive packets, for the slot layout:
 // packet t owns slots [64 t, 64 t + 64) of the slot arrays (member id, low and
@@ -48,9 +52,8 @@ struct ChunkHdr {
   int32_t hood_start, hood_end;      // the chunk holds neighbourhoods [hood_start, hood_end)
   int32_t flags;                     // bit 0: a LARGE packet; bit 8 + i: packet i is MID (two words)
   uint16_t elem_off[kChunkTiles];    // first element of packet i, relative to elem_start
-  int32_t pad[8];
 };
-static_assert(sizeof(ChunkHdr) == 128, "ChunkHdr layout");
+static_assert(sizeof(ChunkHdr) % 4 == 0 && sizeof(ChunkHdr) <= 64 * 4, "ChunkHdr: one dword per lane");
 constexpr int kHdrLarge = 1;
 constexpr int kHdrMidShift = 8;
 
