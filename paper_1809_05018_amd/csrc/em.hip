@@ -77,15 +77,14 @@ constexpr int kGroupTiles = kChunkTiles;  // packets per neighbourhood-sum group
 #endif
 constexpr int kVertPerBlock = 1024;
 
-// Parameters of the labels, with the two values each energy uses
+// Parameters of one label, with the two values each energy uses
 // (w = 1 / (2 sigma^2), lg = ln sigma).
-template <int N>
-struct ThetaArr {
-  double mu[N], sigma[N], w[N], lg[N];
+struct LabelTheta {
+  double mu, sigma, w, lg;
 };
 
 struct GraphState {
-  ThetaArr<kMaxLabels> th[2];  // parameters of iteration t in th[t & 1]
+  LabelTheta th[2][kMaxLabels];  // parameters of iteration t in th[t & 1]
   int32_t done;                // 1: no further iterations (early exit or error)
   int32_t status;
   int32_t iters;
@@ -251,12 +250,11 @@ __device__ __forceinline__ void fold_records(gptr<const double> rec, int nrec, i
   __syncthreads();
 }
 
-template <typename S>
-__device__ __forceinline__ void set_label_theta(S *s, int l, double mu, double sigma) {
-  s->mu[l] = mu;
-  s->sigma[l] = sigma;
-  s->w[l] = 1.0 / (2.0 * sigma * sigma);
-  s->lg[l] = log(sigma);
+__device__ __forceinline__ void set_label_theta(LabelTheta *s, int l, double mu, double sigma) {
+  s[l].mu = mu;
+  s[l].sigma = sigma;
+  s[l].w = 1.0 / (2.0 * sigma * sigma);
+  s[l].lg = log(sigma);
 }
 
 // Parameters for the next iteration from the per-label sums ("Update
@@ -288,15 +286,15 @@ __device__ __forceinline__ void next_label_theta(double nd, double s1, double s2
 
 // All labels, by one thread (s: parameters of this iteration on entry, the
 // next ones on return).
-template <typename S>
-__device__ __forceinline__ void update_theta(S *s, const double *tot, int L, double sigma_min, bool mean_only) {
+__device__ __forceinline__ void update_theta(LabelTheta *s, const double *tot, int L, double sigma_min,
+                                             bool mean_only) {
   for (int l = 0; l < L; ++l) {
-    double mu = s->mu[l], sg = s->sigma[l], w = s->w[l], lg = s->lg[l];
+    double mu = s[l].mu, sg = s[l].sigma, w = s[l].w, lg = s[l].lg;
     next_label_theta(tot[3 * l], tot[3 * l + 1], tot[3 * l + 2], sigma_min, mean_only, mu, sg, w, lg);
-    s->mu[l] = mu;
-    s->sigma[l] = sg;
-    s->w[l] = w;
-    s->lg[l] = lg;
+    s[l].mu = mu;
+    s[l].sigma = sg;
+    s[l].w = w;
+    s[l].lg = lg;
   }
 }
 
@@ -856,9 +854,9 @@ template <int LMAX>
 __device__ __forceinline__ int load_theta(const Ctx &c, Theta<LMAX> &th) {
 #pragma unroll
   for (int l = 0; l < LMAX; ++l) {
-    th.mu[l] = c.st->th[c.t & 1].mu[l];
-    th.w[l] = c.st->th[c.t & 1].w[l];
-    th.lg[l] = c.st->th[c.t & 1].lg[l];
+    th.mu[l] = c.st->th[c.t & 1][l].mu;
+    th.w[l] = c.st->th[c.t & 1][l].w;
+    th.lg[l] = c.st->th[c.t & 1][l].lg;
   }
   return c.st->done;
 }
@@ -1019,15 +1017,15 @@ __global__ void k_setup(const GraphDev *graphs, int B) {
   for (int l = 0; l < G.L; ++l) {
     double mu = G.in_mu[l], sigma = G.in_sigma[l];
     if (!(sigma > 0.0) || !isfinite(sigma) || !isfinite(mu)) ok = false;
-    st->th[0].mu[l] = mu;
-    st->th[0].sigma[l] = sigma;
+    st->th[0][l].mu = mu;
+    st->th[0][l].sigma = sigma;
   }
   if (!ok) {
     st->status = PMRF_EBADPARAM;
     st->done = 1;
     return;
   }
-  for (int l = 0; l < G.L; ++l) set_label_theta(&st->th[0], l, st->th[0].mu[l], st->th[0].sigma[l]);
+  for (int l = 0; l < G.L; ++l) set_label_theta(st->th[0], l, st->th[0][l].mu, st->th[0][l].sigma);
 }
 
 // Parameter update from the starting labels (used when init_from_labels is
@@ -1048,7 +1046,7 @@ __global__ __launch_bounds__(256) void k_mstep_init(const GraphDev *graphs, int 
   LaneStats<kMaxLabels> ls;
   ls.clear();
   double c[kMaxLabels];
-  for (int l = 0; l < kMaxLabels; ++l) c[l] = (pass == 0 || l >= L) ? 0.0 : st->th[0].mu[l];
+  for (int l = 0; l < kMaxLabels; ++l) c[l] = (pass == 0 || l >= L) ? 0.0 : st->th[0][l].mu;
   for (int v = v0 + threadIdx.x; v < v1; v += blockDim.x) {
     int xv = x[v];
     if ((unsigned)xv >= (unsigned)L) {
@@ -1088,7 +1086,7 @@ __global__ __launch_bounds__(kFoldThreads) void k_fin_init(const GraphDev *graph
     st->done = 1;
     return;
   }
-  update_theta(&st->th[0], tot, G.L, G.sigma_min, pass == 0);
+  update_theta(st->th[0], tot, G.L, G.sigma_min, pass == 0);
 }
 
 // LDS of the parameter update.
@@ -1116,15 +1114,19 @@ __device__ __forceinline__ void fold_iteration(const GraphDev &G, int t, FoldLds
   const int done = st->done;
   const long long ties_total = st->ties_total;
   const int map_conv = st->map_conv, em_conv = st->em_conv;
-  const int ll = lane < kMaxLabels ? lane : 0;
-  double mu = st->th[tp & 1].mu[ll], sg = st->th[tp & 1].sigma[ll];
-  double wl = st->th[tp & 1].w[ll], lg = st->th[tp & 1].lg[ll];
-  // thist holds max(1, max_iters) entries; used only where tp >= lane + 1
-  const double hist = thist[min(max(0, tp - lane - 1), max(0, max_iters - 1))];
   if (tp >= max_iters) return;
   fold_records<LMAX>(gbl((const double *)G.rec) + (size_t)(tp & 1) * G.rec_stride, G.nsuper, L, sh.tot, sh.part,
                      nw, wave, lane);
   if (wave != 0 || done) return;
+  // wave 0: label `lane`'s parameters of tp and the energy total of iteration
+  // tp - lane - 1 (thist holds max(1, max_iters) entries; used where tp >= lane + 1)
+  const int ll = lane < kMaxLabels ? lane : 0;
+  double mu = st->th[tp & 1][ll].mu, sg = st->th[tp & 1][ll].sigma;
+  double wl = st->th[tp & 1][ll].w, lg = st->th[tp & 1][ll].lg;
+  const double hist = thist[min(max(0, tp - lane - 1), max(0, max_iters - 1))];
+  // both requests are in flight before either is waited for (no branch may
+  // separate them)
+  asm volatile("" ::"v"(mu), "v"(sg), "v"(wl), "v"(lg), "v"(hist));
   if (sh.tot[3 * L + 3] != 0.0) {
     if (lane == 0) {
       st->status = PMRF_EBADLABEL;
@@ -1141,10 +1143,10 @@ __device__ __forceinline__ void fold_iteration(const GraphDev &G, int t, FoldLds
   if (lane < L) {
     next_label_theta(sh.tot[3 * lane], sh.tot[3 * lane + 1], sh.tot[3 * lane + 2], G.sigma_min, false, mu, sg, wl,
                      lg);
-    st->th[t & 1].mu[lane] = mu;
-    st->th[t & 1].sigma[lane] = sg;
-    st->th[t & 1].w[lane] = wl;
-    st->th[t & 1].lg[lane] = lg;
+    st->th[t & 1][lane].mu = mu;
+    st->th[t & 1][lane].sigma = sg;
+    st->th[t & 1][lane].w = wl;
+    st->th[t & 1][lane].lg = lg;
   }
   if (lane == 0) {
     gbl(G.thist)[tp] = T;
@@ -1161,11 +1163,15 @@ __device__ __forceinline__ void fold_iteration(const GraphDev &G, int t, FoldLds
   }
 }
 
-// The parameter update of iteration t - 1 (one block per graph).
-template <int LMAX>
-__global__ __launch_bounds__(kFoldThreads) void k_fold(const GraphDev *graphs, int B, int t) {
+// The parameter update of iteration t - 1 (one block per graph; SINGLE: the
+// one graph's descriptor g1 travels in the kernel arguments).
+template <int LMAX, bool SINGLE>
+__global__ __launch_bounds__(kFoldThreads) void k_fold(const GraphDev *graphs, const GraphDev g1, int B, int t) {
   __shared__ FoldLds<LMAX> sh;
-  fold_iteration<LMAX>(graphs[blockIdx.x], t, sh, blockDim.x >> 6, threadIdx.x >> 6, threadIdx.x & 63);
+  if constexpr (SINGLE)
+    fold_iteration<LMAX>(g1, t, sh, blockDim.x >> 6, threadIdx.x >> 6, threadIdx.x & 63);
+  else
+    fold_iteration<LMAX>(graphs[blockIdx.x], t, sh, blockDim.x >> 6, threadIdx.x >> 6, threadIdx.x & 63);
 }
 
 // One EM iteration over every graph of the launch.  Block b of a graph owns
@@ -1269,8 +1275,8 @@ __global__ void k_final(const GraphDev *graphs, int B) {
   }
   if (b == 0 && threadIdx.x == 0) {
     for (int l = 0; l < G.L; ++l) {
-      G.out_mu[l] = st->th[iters & 1].mu[l];
-      G.out_sigma[l] = st->th[iters & 1].sigma[l];
+      G.out_mu[l] = st->th[iters & 1][l].mu;
+      G.out_sigma[l] = st->th[iters & 1][l].sigma;
     }
     int64_t *c = G.out_ctr;
     c[PMRF_CTR_STATUS] = st->status;
@@ -1545,12 +1551,20 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
 #undef PMRF_LAUNCH_ITER
       HIP_TRY(hipGetLastError());
       if (events) HIP_TRY(prof_mark(s, false));
+#define PMRF_LAUNCH_FOLD(LM)                                                                                \
+  do {                                                                                                      \
+    if (B == 1)                                                                                             \
+      hipLaunchKernelGGL((k_fold<LM, true>), dim3(B), dim3(kFoldThreads), 0, s, gd, desc[0], B, t + 1);      \
+    else                                                                                                    \
+      hipLaunchKernelGGL((k_fold<LM, false>), dim3(B), dim3(kFoldThreads), 0, s, gd, desc[0], B, t + 1);     \
+  } while (0)
       switch (lm) {  // the parameter update of iteration t
-        case 2: hipLaunchKernelGGL(k_fold<2>, dim3(B), dim3(kFoldThreads), 0, s, gd, B, t + 1); break;
-        case 4: hipLaunchKernelGGL(k_fold<4>, dim3(B), dim3(kFoldThreads), 0, s, gd, B, t + 1); break;
-        case 8: hipLaunchKernelGGL(k_fold<8>, dim3(B), dim3(kFoldThreads), 0, s, gd, B, t + 1); break;
-        default: hipLaunchKernelGGL(k_fold<16>, dim3(B), dim3(kFoldThreads), 0, s, gd, B, t + 1); break;
+        case 2: PMRF_LAUNCH_FOLD(2); break;
+        case 4: PMRF_LAUNCH_FOLD(4); break;
+        case 8: PMRF_LAUNCH_FOLD(8); break;
+        default: PMRF_LAUNCH_FOLD(16); break;
       }
+#undef PMRF_LAUNCH_FOLD
       HIP_TRY(hipGetLastError());
     }
     hipLaunchKernelGGL(k_final, dim3(blocks_vert), dim3(256), 0, s, gd, B);
