@@ -129,17 +129,53 @@ struct DescPack {
 // its LDS instructions in order; this also stops the compiler moving them).
 __device__ __forceinline__ void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 
-// Butterfly sums across the 64 lanes: every lane ends with the same value and
-// the order of additions is fixed.
+// Sums across the 64 lanes in one fixed order, with DPP lane moves (no trip
+// through the LDS crossbar): pairs, quads, half rows and rows combine inside
+// each row of 16 (every lane of a row ends with the row's sum; a + b and b + a
+// round alike), then row 0 joins row 1 and row 2 joins row 3 (row_bcast15),
+// then rows 0+1 join rows 2+3 (row_bcast31).  Lane 63 holds
+// ((r3 + r2) + (r1 + r0)), which readlane hands to every lane.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ long long dpp_i64(long long x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(x & 0xffffffff), CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(x >> 32), CTRL, ROWS, 0xf, false);
+  return ((long long)hi << 32) | (unsigned)lo;
+}
+constexpr int kDppSwap1 = 0xb1;           // quad_perm [1,0,3,2]
+constexpr int kDppSwap2 = 0x4e;           // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141;     // row_half_mirror
+constexpr int kDppMirror = 0x140;         // row_mirror
+constexpr int kDppBcast15 = 0x142;        // row_bcast:15
+constexpr int kDppBcast31 = 0x143;        // row_bcast:31
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v = v + __shfl_xor(v, m);
-  return v;
+  v = v + dpp_f64<kDppSwap1, 0xf>(v);
+  v = v + dpp_f64<kDppSwap2, 0xf>(v);
+  v = v + dpp_f64<kDppHalfMirror, 0xf>(v);
+  v = v + dpp_f64<kDppMirror, 0xf>(v);
+  v = v + dpp_f64<kDppBcast15, 0xa>(v);  // rows 1 and 3 (others add 0)
+  v = v + dpp_f64<kDppBcast31, 0xc>(v);  // rows 2 and 3
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 __device__ __forceinline__ long long wave_sum(long long v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v = v + __shfl_xor(v, m);
-  return v;
+  v = v + dpp_i64<kDppSwap1, 0xf>(v);
+  v = v + dpp_i64<kDppSwap2, 0xf>(v);
+  v = v + dpp_i64<kDppHalfMirror, 0xf>(v);
+  v = v + dpp_i64<kDppMirror, 0xf>(v);
+  v = v + dpp_i64<kDppBcast15, 0xa>(v);
+  v = v + dpp_i64<kDppBcast31, 0xc>(v);
+  const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffff), 63);
+  const int hi = __builtin_amdgcn_readlane((int)(v >> 32), 63);
+  return ((long long)hi << 32) | (unsigned)lo;
 }
 
 template <int LMAX>
@@ -240,12 +276,11 @@ __device__ __forceinline__ void fold_records(gptr<const double> rec, int nrec, i
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int w = 0; w < words; ++w) {
-      double x = 0.0;
-      for (int k = 0; k < kFoldWaves; ++k) x = x + part[k][w];
-      tot[w] = x;
-    }
+  for (int w = threadIdx.x; w < words; w += blockDim.x) {  // thread w: word w over the virtual waves in order
+    double x = 0.0;
+#pragma unroll
+    for (int k = 0; k < kFoldWaves; ++k) x = x + part[k][w];
+    tot[w] = x;
   }
   __syncthreads();
 }
