@@ -115,8 +115,10 @@ struct GraphDev {
   int64_t rec_stride;  // words of one record buffer (records of iteration t at rec + (t & 1) * rec_stride)
   int32_t n, H, ntiles, nchunks, nsuper, L, P, W, max_iters, early_exit, init_from_labels;
   double beta, tol, sigma_min, tie_eps;
-  int32_t block0, nblocks;    // blocks of this graph in an iteration launch (one per superchunk)
+  int32_t block0, nblocks;    // slot-kernel blocks of this graph: superchunks [0, nblocks)
+  int32_t pblock0, pnblocks;  // packet-kernel blocks: superchunks [nblocks, nsuper)
   int32_t vblock0, vnblocks;  // blocks of this graph in a vertex-parallel launch
+  const int32_t *perm;        // processing index -> canonical neighbourhood
 };
 
 constexpr int kDescPerPack = 12;
@@ -334,11 +336,12 @@ __device__ __forceinline__ void update_theta(LabelTheta *s, const double *tot, i
 }
 
 // Graph owning a block: the last graph whose first block is <= block.
-__device__ __forceinline__ int find_graph(const GraphDev *graphs, int B, int block, bool vertex_launch) {
+enum GridKind { kGridSlot = 0, kGridVertex = 1, kGridPacket = 2 };
+__device__ __forceinline__ int find_graph(const GraphDev *graphs, int B, int block, int grid) {
   int lo = 0, hi = B - 1;
   while (lo < hi) {
     int mid = (lo + hi + 1) >> 1;
-    int first = vertex_launch ? graphs[mid].vblock0 : graphs[mid].block0;
+    int first = grid == kGridVertex ? graphs[mid].vblock0 : grid == kGridPacket ? graphs[mid].pblock0 : graphs[mid].block0;
     if (first <= block) lo = mid; else hi = mid - 1;
   }
   return lo;
@@ -993,9 +996,8 @@ __device__ bool chunk_slots(const Ctx &c, int ck, bool done, const Theta<LMAX> &
 // independent of it (the two paths add the owner statistics in different lane
 // orders).
 template <int LMAX>
-__device__ void do_chunk(const Ctx &c, int ck, bool done, const Theta<LMAX> &th, double *part, double *mb,
-                         uint64_t *pl, double *od, int *oa, int lane) {
-  if (chunk_slots<LMAX>(c, ck, done, th, part, mb, od, oa, lane) || done) return;
+__device__ void chunk_packets(const Ctx &c, int ck, const Theta<LMAX> &th, double *part, double *mb, uint64_t *pl,
+                              int lane) {
   LaneStats<LMAX> ls;
   ls.clear();
   const int tb = ck * kChunkTiles, te = min(c.ntiles, tb + kChunkTiles);
@@ -1069,7 +1071,7 @@ __global__ void k_setup(const GraphDev *graphs, int B) {
 // t, t+256, ... of that range; one record per block.
 __global__ __launch_bounds__(256) void k_mstep_init(const GraphDev *graphs, int B, int pass) {
   __shared__ double part[4][kRecMax];
-  const int g = find_graph(graphs, B, blockIdx.x, true);
+  const int g = find_graph(graphs, B, blockIdx.x, kGridVertex);
   const GraphDev &G = graphs[g];
   gptr<const GraphState> st = gbl((const GraphState *)G.st);
   if (!G.init_from_labels || st->done) return;
@@ -1209,12 +1211,14 @@ __global__ __launch_bounds__(kFoldThreads) void k_fold(const GraphDev *graphs, c
     fold_iteration<LMAX>(graphs[blockIdx.x], t, sh, blockDim.x >> 6, threadIdx.x >> 6, threadIdx.x & 63);
 }
 
-// One EM iteration over every graph of the launch.  Block b of a graph owns
-// superchunk b (chunks 4b .. 4b+3); its waves take the chunks in turn, leave
-// each chunk's statistics in LDS, and the block adds them in chunk order into
-// the superchunk's record (buffer t & 1).
-template <int LMAX>
-__device__ __forceinline__ void iter_superchunk(const GraphDev &G, int sc, int t, double (*part)[rec_words(LMAX)],
+// One EM iteration over every graph of the launch.  Superchunk b of a graph
+// (chunks 4b .. 4b+3) belongs to one block; its waves take the chunks in turn,
+// leave each chunk's statistics in LDS, and the block adds them in chunk order
+// into record b (buffer t & 1).  PACKET: the superchunk holds a LARGE packet
+// (or the window is longer than kPreWindow) and goes packet by packet over the
+// element arrays; otherwise every chunk takes the slot layout.
+template <int LMAX, bool PACKET>
+__device__ __forceinline__ void iter_superchunk(const GraphDev &G, int b, int t, double (*part)[rec_words(LMAX)],
                                                 double *mb, uint64_t *pl, double *od, int *oa, int nw, int wave,
                                                 int lane) {
   if (t >= G.max_iters) return;
@@ -1243,13 +1247,17 @@ __device__ __forceinline__ void iter_superchunk(const GraphDev &G, int sc, int t
     c.beta = G.beta;
     c.tol = G.tol;
     c.tie_eps = G.tie_eps;
-    const int b = sc - G.block0;
     const int c0 = b * kSuperChunks;
     const int c1 = min(G.nchunks, c0 + kSuperChunks);
     Theta<LMAX> th;
     const bool done = load_theta<LMAX>(c, th);  // uniform scalar loads, waited for with the chunk's loads
-    for (int ck = c0 + wave; ck < c1; ck += nw)
-      do_chunk<LMAX>(c, ck, done, th, part[ck - c0], mb, pl, od, oa, lane);
+    for (int ck = c0 + wave; ck < c1; ck += nw) {
+      if constexpr (PACKET) {
+        if (!done) chunk_packets<LMAX>(c, ck, th, part[ck - c0], mb, pl, lane);
+      } else {
+        chunk_slots<LMAX>(c, ck, done, th, part[ck - c0], mb, od, oa, lane);
+      }
+    }
     __syncthreads();
     const int words = rec_words(c.L);
     if (!done && threadIdx.x < words) {
@@ -1277,26 +1285,44 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(LMAX <= 2 
   double *od = mb + kGroupTiles * 64 + 64;
   int *oa = reinterpret_cast<int *>(od + kOwnCap);
   if constexpr (!PERSIST) {
-    if constexpr (SINGLE)
-      iter_superchunk<LMAX>(g1, blockIdx.x, t, part, mb, pl, od, oa, nw, wave, lane);
-    else
-      iter_superchunk<LMAX>(graphs[find_graph(graphs, B, blockIdx.x, false)], blockIdx.x, t, part, mb, pl, od, oa,
-                            nw, wave, lane);
+    if constexpr (SINGLE) {
+      iter_superchunk<LMAX, false>(g1, blockIdx.x, t, part, mb, pl, od, oa, nw, wave, lane);
+    } else {
+      const GraphDev &G = graphs[find_graph(graphs, B, blockIdx.x, kGridSlot)];
+      iter_superchunk<LMAX, false>(G, blockIdx.x - G.block0, t, part, mb, pl, od, oa, nw, wave, lane);
+    }
   } else {
     for (int sc = blockIdx.x; sc < nsuper_total; sc += gridDim.x) {
-      if constexpr (SINGLE)
-        iter_superchunk<LMAX>(g1, sc, t, part, mb, pl, od, oa, nw, wave, lane);
-      else
-        iter_superchunk<LMAX>(graphs[find_graph(graphs, B, sc, false)], sc, t, part, mb, pl, od, oa, nw, wave, lane);
+      if constexpr (SINGLE) {
+        iter_superchunk<LMAX, false>(g1, sc, t, part, mb, pl, od, oa, nw, wave, lane);
+      } else {
+        const GraphDev &G = graphs[find_graph(graphs, B, sc, kGridSlot)];
+        iter_superchunk<LMAX, false>(G, sc - G.block0, t, part, mb, pl, od, oa, nw, wave, lane);
+      }
       __syncthreads();  // part[] is reused by the next superchunk
     }
   }
 }
 
+// The superchunks that hold a LARGE packet: block i of a graph works on its
+// superchunk nblocks + i, packet by packet.
+template <int LMAX>
+__global__ __launch_bounds__(1024) void k_iter_packets(const GraphDev *__restrict__ graphs, int B, int t) {
+  extern __shared__ double smem[];
+  __shared__ double part[kSuperChunks][rec_words(LMAX)];
+  const int nw = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double *mb = smem + wave * kWaveLds;
+  uint64_t *pl = reinterpret_cast<uint64_t *>(mb + kGroupTiles * 64);
+  double *od = mb + kGroupTiles * 64 + 64;
+  int *oa = reinterpret_cast<int *>(od + kOwnCap);
+  const GraphDev &G = graphs[find_graph(graphs, B, blockIdx.x, kGridPacket)];
+  iter_superchunk<LMAX, true>(G, G.nblocks + (blockIdx.x - G.pblock0), t, part, mb, pl, od, oa, nw, wave, lane);
+}
+
 
 // Copy results to the caller's buffers.
 __global__ void k_final(const GraphDev *graphs, int B) {
-  const int g = find_graph(graphs, B, blockIdx.x, true);
+  const int g = find_graph(graphs, B, blockIdx.x, kGridVertex);
   const GraphDev &G = graphs[g];
   GraphState *st = G.st;
   const int b = blockIdx.x - G.vblock0;
@@ -1306,7 +1332,7 @@ __global__ void k_final(const GraphDev *graphs, int B) {
     for (int v = b * blockDim.x + threadIdx.x; v < G.n; v += stride) G.x0[v] = G.x1[v];
   if (G.out_S && iters > 0) {
     const double *src = G.ring + (size_t)((iters - 1) % (G.W + 1)) * G.H;
-    for (int h = b * blockDim.x + threadIdx.x; h < G.H; h += stride) G.out_S[h] = src[h];
+    for (int h = b * blockDim.x + threadIdx.x; h < G.H; h += stride) G.out_S[G.perm[h]] = src[h];
   }
   if (b == 0 && threadIdx.x == 0) {
     for (int l = 0; l < G.L; ++l) {
@@ -1461,7 +1487,7 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
   const int threads = shape.waves_per_block * kWave;
   char *ws = static_cast<char *>(d_ws);
   std::vector<GraphDev> desc(B);
-  int blocks_iter = 0, blocks_vert = 0, max_iters = 0, Lmax = 2;
+  int blocks_iter = 0, blocks_pk = 0, blocks_vert = 0, max_iters = 0, Lmax = 2;
   for (int i = 0; i < B; ++i) {
     const pmrf_em_item &it = items[i];
     const pmrf_hoods *h = it.hoods;
@@ -1508,8 +1534,17 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
     G.block0 = blocks_iter;
     G.nchunks = (int32_t)n_chunks(h);
     G.nsuper = (int32_t)n_super(h);
-    G.nblocks = G.nsuper;
+    // superchunks before the first LARGE packet take the slot kernel, the rest
+    // the packet kernel (all of them when the window is longer than kPreWindow)
+    const int64_t per_super = (int64_t)kChunkTiles * kSuperChunks;
+    int32_t nslot = h->slot_tiles == (int64_t)h->tiles.size() ? G.nsuper : (int32_t)(h->slot_tiles / per_super);
+    if (it.params.conv_window > kPreWindow) nslot = 0;
+    G.nblocks = nslot;
     blocks_iter += G.nblocks;
+    G.pblock0 = blocks_pk;
+    G.pnblocks = G.nsuper - nslot;
+    blocks_pk += G.pnblocks;
+    G.perm = reinterpret_cast<const int32_t *>(hb + h->layout.perm_off);
     G.vblock0 = blocks_vert;
     G.vnblocks = (int32_t)vert_blocks(h);
     blocks_vert += G.vnblocks;
@@ -1577,11 +1612,22 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
       hipLaunchKernelGGL((k_iter<LM, false, false>), dim3(grid_iter), dim3(threads), lds, s, gd, desc[0], B,   \
                          blocks_iter, t);                                                                     \
   } while (0)
-      switch (lm) {
-        case 2: PMRF_LAUNCH_ITER(2); break;
-        case 4: PMRF_LAUNCH_ITER(4); break;
-        case 8: PMRF_LAUNCH_ITER(8); break;
-        default: PMRF_LAUNCH_ITER(16); break;
+      if (blocks_iter > 0) {
+        switch (lm) {
+          case 2: PMRF_LAUNCH_ITER(2); break;
+          case 4: PMRF_LAUNCH_ITER(4); break;
+          case 8: PMRF_LAUNCH_ITER(8); break;
+          default: PMRF_LAUNCH_ITER(16); break;
+        }
+        HIP_TRY(hipGetLastError());
+      }
+      if (blocks_pk > 0) {
+        switch (lm) {
+          case 2: hipLaunchKernelGGL(k_iter_packets<2>, dim3(blocks_pk), dim3(threads), lds, s, gd, B, t); break;
+          case 4: hipLaunchKernelGGL(k_iter_packets<4>, dim3(blocks_pk), dim3(threads), lds, s, gd, B, t); break;
+          case 8: hipLaunchKernelGGL(k_iter_packets<8>, dim3(blocks_pk), dim3(threads), lds, s, gd, B, t); break;
+          default: hipLaunchKernelGGL(k_iter_packets<16>, dim3(blocks_pk), dim3(threads), lds, s, gd, B, t); break;
+        }
       }
 #undef PMRF_LAUNCH_ITER
       HIP_TRY(hipGetLastError());
@@ -1617,6 +1663,7 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
   put(&max_iters, sizeof max_iters);
   put(&lm, sizeof lm);
   put(&blocks_iter, sizeof blocks_iter);
+  put(&blocks_pk, sizeof blocks_pk);
   put(&grid_iter, sizeof grid_iter);
   put(&blocks_vert, sizeof blocks_vert);
   put(&threads, sizeof threads);

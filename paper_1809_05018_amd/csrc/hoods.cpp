@@ -214,13 +214,30 @@ extern "C" pmrf_status pmrf_build_neighborhoods(int32_t n, const int32_t *row_pt
         auto b = hd->hood_vid.begin() + hd->hood_ptr[h], e = hd->hood_vid.begin() + hd->hood_ptr[h + 1];
         hd->owner[v] = hd->hood_ptr[h] + (std::lower_bound(b, e, v) - b);
       }
-    // work packets and adjacency words
+    // processing order: neighbourhoods of at most 64 members first, then the
+    // larger ones, each group in canonical order; the device arrays follow it
+    // (perm maps a processing index to the canonical one)
+    hd->perm.clear();
+    for (int64_t h = 0; h < H; ++h)
+      if (hd->hood_ptr[h + 1] - hd->hood_ptr[h] <= kWave) hd->perm.push_back((int32_t)h);
+    for (int64_t h = 0; h < H; ++h)
+      if (hd->hood_ptr[h + 1] - hd->hood_ptr[h] > kWave) hd->perm.push_back((int32_t)h);
+    hd->hood_ptr32.assign(1, 0);
+    hd->dev_vid.clear();
+    hd->dev_vid.reserve((size_t)hd->M);
+    for (int64_t hp = 0; hp < H; ++hp) {
+      const int64_t h = hd->perm[hp];
+      hd->dev_vid.insert(hd->dev_vid.end(), hd->hood_vid.begin() + hd->hood_ptr[h],
+                         hd->hood_vid.begin() + hd->hood_ptr[h + 1]);
+      hd->hood_ptr32.push_back((int32_t)hd->dev_vid.size());
+    }
+    // work packets and adjacency words, in processing order
     std::vector<int32_t> loc(n, -1);
-    auto open_tile = [&](uint8_t kind, uint8_t words, int64_t h) {
+    auto open_tile = [&](uint8_t kind, uint8_t words, int64_t hp) {
       TileDesc t{};
       t.start_mask = 0;
-      t.elem_start = (int32_t)hd->hood_ptr[h];
-      t.hood_start = (int32_t)h;
+      t.elem_start = hd->hood_ptr32[hp];
+      t.hood_start = (int32_t)hp;
       t.mask_start = (int32_t)hd->mask.size();
       t.nelem = 0;
       t.kind = kind;
@@ -228,20 +245,21 @@ extern "C" pmrf_status pmrf_build_neighborhoods(int32_t n, const int32_t *row_pt
       hd->tiles.push_back(t);
     };
     bool small_open = false;
-    for (int64_t h = 0; h < H; ++h) {
-      int64_t o = hd->hood_ptr[h];
+    for (int64_t hp = 0; hp < H; ++hp) {
+      const int64_t h = hd->perm[hp];
+      int64_t o = hd->hood_ptr[h];  // canonical element offset (owner indices are canonical)
       int32_t s = (int32_t)(hd->hood_ptr[h + 1] - o);
       uint8_t words;
       if (s <= 32) {
         words = 1;
-        if (!small_open || hd->tiles.back().nelem + s > kWave) { open_tile(kSmall, 1, h); small_open = true; }
+        if (!small_open || hd->tiles.back().nelem + s > kWave) { open_tile(kSmall, 1, hp); small_open = true; }
         TileDesc &t = hd->tiles.back();
         t.start_mask |= uint64_t(1) << t.nelem;
         t.nelem = (int16_t)(t.nelem + s);
       } else {
         small_open = false;
         words = (uint8_t)((s + 31) / 32);
-        open_tile(s <= 64 ? kMid : kLarge, words, h);
+        open_tile(s <= 64 ? kMid : kLarge, words, hp);
         hd->tiles.back().start_mask = 1;
         hd->tiles.back().nelem = (int16_t)s;
       }
@@ -259,6 +277,8 @@ extern "C" pmrf_status pmrf_build_neighborhoods(int32_t n, const int32_t *row_pt
       }
       for (int32_t j = 0; j < s; ++j) loc[hd->hood_vid[o + j]] = -1;
     }
+    hd->slot_tiles = 0;
+    while (hd->slot_tiles < (int64_t)hd->tiles.size() && hd->tiles[hd->slot_tiles].kind != kLarge) ++hd->slot_tiles;
     // slot layout and chunk headers: packet t's elements in slots [64 t, 64 t + 64)
     const int64_t ntiles = (int64_t)hd->tiles.size();
     const int64_t nchunks = (ntiles + kChunkTiles - 1) / kChunkTiles;
@@ -272,7 +292,7 @@ extern "C" pmrf_status pmrf_build_neighborhoods(int32_t n, const int32_t *row_pt
       const TileDesc &t = hd->tiles[ti];
       if (t.kind == kLarge) continue;
       for (int k = 0; k < t.nelem; ++k) {
-        hd->svid[ti * kWave + k] = hd->hood_vid[t.elem_start + k];
+        hd->svid[ti * kWave + k] = hd->dev_vid[t.elem_start + k];
         hd->smask[ti * kWave + k] = hd->mask[t.mask_start + (size_t)k * t.words];
         if (t.kind == kMid) hd->smask_hi[ti * kWave + k] = hd->mask[t.mask_start + (size_t)k * t.words + 1];
       }
@@ -297,13 +317,13 @@ extern "C" pmrf_status pmrf_build_neighborhoods(int32_t n, const int32_t *row_pt
     L.tiles_off = 0;
     L.hptr_off = align_up(ntiles * (int64_t)sizeof(TileDesc), 256);
     L.vid_off = L.hptr_off + align_up((hd->H + 1) * 4, 256);
-    hd->hood_ptr32.assign(hd->hood_ptr.begin(), hd->hood_ptr.end());
     L.mask_off = L.vid_off + align_up(hd->M * 4, 256);
     L.chdr_off = L.mask_off + align_up((int64_t)hd->mask.size() * 4, 256);
     L.svid_off = L.chdr_off + align_up(nchunks * (int64_t)sizeof(ChunkHdr), 256);
     L.smask_off = L.svid_off + align_up((int64_t)hd->svid.size() * 4, 256);
     L.smaskhi_off = L.smask_off + align_up((int64_t)hd->smask.size() * 4, 256);
-    L.total = L.smaskhi_off + align_up((int64_t)hd->smask_hi.size() * 4, 256);
+    L.perm_off = L.smaskhi_off + align_up((int64_t)hd->smask_hi.size() * 4, 256);
+    L.total = L.perm_off + align_up(hd->H * 4, 256);
     if (L.total == 0) L.total = 256;
   } catch (const std::bad_alloc &) {
     delete hd;
@@ -354,7 +374,7 @@ extern "C" pmrf_status pmrf_hoods_upload(const pmrf_hoods *h, void *d_buf, int64
     e = hipMemcpyAsync(base + h->layout.hptr_off, h->hood_ptr32.data(), h->hood_ptr32.size() * 4,
                        hipMemcpyHostToDevice, s);
   if (e == hipSuccess && h->M)
-    e = hipMemcpyAsync(base + h->layout.vid_off, h->hood_vid.data(), (size_t)h->M * 4, hipMemcpyHostToDevice, s);
+    e = hipMemcpyAsync(base + h->layout.vid_off, h->dev_vid.data(), (size_t)h->M * 4, hipMemcpyHostToDevice, s);
   if (e == hipSuccess && !h->mask.empty())
     e = hipMemcpyAsync(base + h->layout.mask_off, h->mask.data(), h->mask.size() * 4, hipMemcpyHostToDevice, s);
   if (e == hipSuccess && !h->chdr.empty())
@@ -364,6 +384,8 @@ extern "C" pmrf_status pmrf_hoods_upload(const pmrf_hoods *h, void *d_buf, int64
     e = hipMemcpyAsync(base + h->layout.svid_off, h->svid.data(), h->svid.size() * 4, hipMemcpyHostToDevice, s);
   if (e == hipSuccess && !h->smask.empty())
     e = hipMemcpyAsync(base + h->layout.smask_off, h->smask.data(), h->smask.size() * 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && !h->perm.empty())
+    e = hipMemcpyAsync(base + h->layout.perm_off, h->perm.data(), h->perm.size() * 4, hipMemcpyHostToDevice, s);
   if (e == hipSuccess && !h->smask_hi.empty())
     e = hipMemcpyAsync(base + h->layout.smaskhi_off, h->smask_hi.data(), h->smask_hi.size() * 4,
                        hipMemcpyHostToDevice, s);

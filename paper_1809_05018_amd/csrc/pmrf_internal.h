@@ -61,6 +61,7 @@ constexpr int kHdrMidShift = 8;
 struct DeviceLayout {
   int64_t tiles_off, hptr_off, vid_off, mask_off;
   int64_t chdr_off, svid_off, smask_off, smaskhi_off;  // slot layout
+  int64_t perm_off;                                     // processing index -> canonical neighbourhood
   int64_t total;
 };
 
@@ -77,10 +78,15 @@ struct pmrf_hoods {
   std::vector<int32_t> clique_vid;
   std::vector<int64_t> hood_ptr;
   std::vector<int32_t> hood_vid;
-  std::vector<int32_t> hood_ptr32;  // device copy of hood_ptr
+  // device arrays use the processing order: neighbourhoods of at most 64
+  // members first, then the larger ones, each group in canonical order
+  std::vector<int32_t> perm;        // processing index -> canonical index
+  std::vector<int32_t> hood_ptr32;  // element offsets in processing order
+  std::vector<int32_t> dev_vid;     // members in processing order
   std::vector<int64_t> owner;  // element owning each vertex
   // device layout, built once
   std::vector<pmrf::TileDesc> tiles;
+  int64_t slot_tiles = 0;  // leading packets without a LARGE one (all LARGE packets come last)
   std::vector<uint32_t> mask;  // adjacency words (bit j' = in-hood neighbour j'; own bit = owner flag)
   std::vector<pmrf::ChunkHdr> chdr;               // one per chunk of packets
   std::vector<int32_t> svid;                      // slot layout: member id (-1: unused slot)

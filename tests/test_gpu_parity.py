@@ -167,3 +167,16 @@ def test_graph_replays_match_direct_launches():
                 assert np.array_equal(out[k], eager[k]), (rep, k)
     finally:
         pmrf.pmrf_set_launch(**old)
+
+
+@pytest.mark.parametrize("W", [1, 6])
+def test_convergence_window_lengths(W):
+    # W = 6 exceeds the slot path's prefetched window, so every superchunk of
+    # the graph takes the packet kernel; W = 1 is the shortest window
+    g = synth.workload_small()
+    x0, mu0, s0 = init_state(g, 2)
+    og = oracle.OracleGraph(g.n, g.row_ptr, g.col_idx)
+    ref = og.em_run(g.y, 2, 0.5, x0, mu0, s0, 12, window=W)
+    prob = pmrf.Problem(g.n, g.row_ptr, g.col_idx, g.y, 2)
+    gpu = gpu_run(prob, x0, mu0, s0, beta=0.5, max_iters=12, conv_window=W)
+    compare_runs(gpu, ref, f"window{W}")
