@@ -746,13 +746,20 @@ struct ChunkStats {
   }
 };
 
+// Whether the slot path requests the second adjacency words of MID packets
+// with the gathers (more registers) or when the packet is computed (one more
+// wait per MID packet).  Two-label kernels keep their register budget.
+template <int LMAX>
+constexpr bool kPrefetchHi = LMAX >= 4;
+
 // Element pass of one SMALL or MID packet on the slot layout.  v < 0 marks an
 // unused slot; smask is the packet's neighbourhood-start mask, eoff its first
 // element relative to the chunk, am the element's first adjacency word; the
 // second word of a MID packet is read here from slot (ti, lane).
 template <int LMAX>
 __device__ __forceinline__ void slot_elem(const Ctx &c, uint64_t smask, int eoff, bool mid, int ti, int v,
-                                          uint32_t am, int xv, double yv, const Theta<LMAX> &th, uint64_t below,
+                                          uint32_t am, uint32_t ah, int xv, double yv, const Theta<LMAX> &th,
+                                          uint64_t below,
                                           ChunkStats<LMAX> &cs, double *mb, double *od, int *oa, int &ocount,
                                           int lane) {
   constexpr int PMAX = LMAX <= 2 ? 1 : LMAX <= 4 ? 2 : LMAX <= 8 ? 3 : 4;  // label bit planes
@@ -787,7 +794,9 @@ __device__ __forceinline__ void slot_elem(const Ctx &c, uint64_t smask, int eoff
       }
     }
   } else {
-    const uint64_t a64 = (uint64_t)am | ((uint64_t)c.smask_hi[(size_t)ti * kWave + lane] << 32);
+    // the second word: prefetched (ah) where registers allow, else read here
+    const uint32_t hi = kPrefetchHi<LMAX> ? ah : c.smask_hi[(size_t)ti * kWave + lane];
+    const uint64_t a64 = (uint64_t)am | ((uint64_t)hi << 32);
     const uint64_t self = 1ull << (j & 63);
     owner = valid && (a64 & self);
     const uint64_t nbr = a64 & ~self;
@@ -938,14 +947,18 @@ __device__ bool chunk_slots(const Ctx &c, int ck, bool done, const Theta<LMAX> &
   const int gstart = (int)hdr(kDwElem), h0 = (int)hdr(kDwHood), hend = (int)hdr(kDwHend);
   int xv[kChunkTiles];
   double yv[kChunkTiles];
+  uint32_t ah[kChunkTiles];
 #pragma unroll
   for (int i = 0; i < kChunkTiles; ++i) {
     xv[i] = 0;
     yv[i] = 0.0;
+    ah[i] = 0;
     if (i < nt && v[i] >= 0) {
       xv[i] = c.xr[v[i]];
       yv[i] = c.y[v[i]];
     }
+    if (kPrefetchHi<LMAX> && i < nt && ((flags >> (kHdrMidShift + i)) & 1))
+      ah[i] = c.smask_hi[(size_t)(tb + i) * kWave + lane];
   }
   HoodPre pre{0, 0, {}};
   {
@@ -976,8 +989,8 @@ __device__ bool chunk_slots(const Ctx &c, int ck, bool done, const Theta<LMAX> &
       }
       const uint64_t smask = (uint64_t)hdr(2 * i) | ((uint64_t)hdr(2 * i + 1) << 32);
       const int eoff = (int)((hdr(kDwOff + i / 2) >> (16 * (i & 1))) & 0xffffu);
-      slot_elem<LMAX>(c, smask, eoff, (flags >> (kHdrMidShift + i)) & 1, tb + i, v[i], am[i], xv[i], yv[i], th, below,
-                      cs, mb, od, oa, ocount, lane);
+      slot_elem<LMAX>(c, smask, eoff, (flags >> (kHdrMidShift + i)) & 1, tb + i, v[i], am[i], ah[i], xv[i], yv[i], th,
+                      below, cs, mb, od, oa, ocount, lane);
     }
   wave_lds_sync();
   cs.take_owners(od, oa, ocount, lane);
