@@ -41,7 +41,7 @@ typedef int32_t pmrf_status;
 #define PMRF_EINVAL (-1)       /* bad argument or malformed graph */
 #define PMRF_ENOMEM (-2)       /* a caller buffer is too small, or host allocation failed */
 #define PMRF_EDEVICE (-3)      /* a HIP runtime call failed */
-#define PMRF_EUNSUPPORTED (-4) /* valid request outside what this build supports (k != 1, L > 16, neighbourhood > 1024) */
+#define PMRF_EUNSUPPORTED (-4) /* valid request outside what this build supports (k != 1, L > 16, neighbourhood > 1024, n > 2^26 - 1) */
 /* device-reported codes, in counters[PMRF_CTR_STATUS] */
 #define PMRF_EBADLABEL (-10)   /* a starting label outside [0, L) */
 #define PMRF_EBADPARAM (-11)   /* a starting sigma <= 0 or a non-finite mu / sigma */
@@ -84,7 +84,8 @@ typedef struct {
  * directions.  k is the neighbourhood radius; only k = 1 is supported.
  * n = 0 is allowed (empty problem).  *out receives a new host object.
  * Errors: PMRF_EINVAL (malformed CSR, NULL pointers), PMRF_EUNSUPPORTED
- * (k != 1, a neighbourhood above 1024 members), PMRF_ENOMEM. */
+ * (k != 1, a neighbourhood above 1024 members, n above 2^26 - 1 = 67108863
+ * vertices), PMRF_ENOMEM. */
 pmrf_status pmrf_build_neighborhoods(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, int32_t k,
                                      pmrf_hoods **out);
 

@@ -752,29 +752,31 @@ struct ChunkStats {
 template <int LMAX>
 constexpr bool kPrefetchHi = LMAX >= 4;
 
-// Element pass of one SMALL or MID packet on the slot layout.  v < 0 marks an
-// unused slot; smask is the packet's neighbourhood-start mask, eoff its first
-// element relative to the chunk, am the element's first adjacency word; the
-// second word of a MID packet is read here from slot (ti, lane).
+// Element pass of one SMALL or MID packet on the slot layout.  sv is the slot
+// word (member vertex in bits 0..25, the member's index j inside its
+// neighbourhood in bits 26..31, all ones for an unused slot), so the lane of
+// the neighbourhood's first member is lane - j.  eoff: the packet's first
+// element relative to the chunk; am: the element's first adjacency word; the
+// second word of a MID packet is prefetched (ah) or read here.
 template <int LMAX>
-__device__ __forceinline__ void slot_elem(const Ctx &c, uint64_t smask, int eoff, bool mid, int ti, int v,
-                                          uint32_t am, uint32_t ah, int xv, double yv, const Theta<LMAX> &th,
-                                          uint64_t below,
+__device__ __forceinline__ void slot_elem(const Ctx &c, int eoff, bool mid, int ti, uint32_t sv, uint32_t am,
+                                          uint32_t ah, int xv, double yv, const Theta<LMAX> &th,
                                           ChunkStats<LMAX> &cs, double *mb, double *od, int *oa, int &ocount,
                                           int lane) {
   constexpr int PMAX = LMAX <= 2 ? 1 : LMAX <= 4 ? 2 : LMAX <= 8 ? 3 : 4;  // label bit planes
-  const bool valid = v >= 0;
+  const bool valid = sv != kSlotEmpty;
+  const int v = (int)(sv & kSlotVidMask);
+  const int j = (int)(sv >> kSlotJShift);
+  const int base = lane - j;
   if (valid && (unsigned)xv >= (unsigned)c.L) cs.err |= 1;
   uint64_t planes[PMAX];
 #pragma unroll
   for (int k = 0; k < PMAX; ++k) planes[k] = (k < c.P) ? __ballot(valid && ((xv >> k) & 1)) : 0ull;
-  const int base = 63 - __clzll(smask & below);
-  const int j = lane - base;
   int deg, cnt[LMAX];
-  bool owner;
+  uint32_t own;  // the element's own bit: set for the owner element of its vertex
   if (!mid) {
-    const uint32_t self = 1u << (j & 31);
-    owner = valid && (am & self);
+    const uint32_t self = 1u << j;
+    own = am & self;
     const uint32_t nbr = am & ~self;
     deg = __popc(nbr);
     if constexpr (LMAX == 2) {  // neighbours with label 1; the rest have label 0
@@ -794,11 +796,10 @@ __device__ __forceinline__ void slot_elem(const Ctx &c, uint64_t smask, int eoff
       }
     }
   } else {
-    // the second word: prefetched (ah) where registers allow, else read here
     const uint32_t hi = kPrefetchHi<LMAX> ? ah : c.smask_hi[(size_t)ti * kWave + lane];
     const uint64_t a64 = (uint64_t)am | ((uint64_t)hi << 32);
-    const uint64_t self = 1ull << (j & 63);
-    owner = valid && (a64 & self);
+    const uint64_t self = 1ull << j;
+    own = (a64 & self) != 0;
     const uint64_t nbr = a64 & ~self;
     deg = __popcll(nbr);
     if constexpr (LMAX == 2) {
@@ -818,6 +819,7 @@ __device__ __forceinline__ void slot_elem(const Ctx &c, uint64_t smask, int eoff
       }
     }
   }
+  const bool owner = valid && own != 0;
   double m, gap, dsel;
   int a;
   if constexpr (LMAX == 2) {
@@ -829,7 +831,7 @@ __device__ __forceinline__ void slot_elem(const Ctx &c, uint64_t smask, int eoff
     const bool one = e1 < e0;
     a = one ? 1 : 0;
     m = one ? e1 : e0;
-    gap = one ? e0 - e1 : e1 - e0;
+    gap = fabs(e1 - e0);  // the runner-up minus the minimum
     dsel = one ? d1 : d0;
   } else {
     element_energy<LMAX>(th, c.L, c.beta, yv, deg, cnt, m, a, gap, dsel);
@@ -953,9 +955,10 @@ __device__ bool chunk_slots(const Ctx &c, int ck, bool done, const Theta<LMAX> &
     xv[i] = 0;
     yv[i] = 0.0;
     ah[i] = 0;
-    if (i < nt && v[i] >= 0) {
-      xv[i] = c.xr[v[i]];
-      yv[i] = c.y[v[i]];
+    if (i < nt && (uint32_t)v[i] != kSlotEmpty) {
+      const int vv = (int)((uint32_t)v[i] & kSlotVidMask);
+      xv[i] = c.xr[vv];
+      yv[i] = c.y[vv];
     }
     if (kPrefetchHi<LMAX> && i < nt && ((flags >> (kHdrMidShift + i)) & 1))
       ah[i] = c.smask_hi[(size_t)(tb + i) * kWave + lane];
@@ -976,7 +979,6 @@ __device__ bool chunk_slots(const Ctx &c, int ck, bool done, const Theta<LMAX> &
   }
   ChunkStats<LMAX> cs;
   cs.clear();
-  const uint64_t below = (2ull << lane) - 1ull;  // lanes 0..lane
   int ocount = 0;
 #pragma unroll
   for (int i = 0; i < kChunkTiles; ++i)
@@ -987,10 +989,9 @@ __device__ bool chunk_slots(const Ctx &c, int ck, bool done, const Theta<LMAX> &
         ocount = 0;
         wave_lds_sync();
       }
-      const uint64_t smask = (uint64_t)hdr(2 * i) | ((uint64_t)hdr(2 * i + 1) << 32);
       const int eoff = (int)((hdr(kDwOff + i / 2) >> (16 * (i & 1))) & 0xffffu);
-      slot_elem<LMAX>(c, smask, eoff, (flags >> (kHdrMidShift + i)) & 1, tb + i, v[i], am[i], ah[i], xv[i], yv[i], th,
-                      below, cs, mb, od, oa, ocount, lane);
+      slot_elem<LMAX>(c, eoff, (flags >> (kHdrMidShift + i)) & 1, tb + i, (uint32_t)v[i], am[i], ah[i], xv[i], yv[i],
+                      th, cs, mb, od, oa, ocount, lane);
     }
   wave_lds_sync();
   cs.take_owners(od, oa, ocount, lane);

@@ -155,6 +155,8 @@ extern "C" pmrf_status pmrf_build_neighborhoods(int32_t n, const int32_t *row_pt
   if (k != 1) return fail(PMRF_EUNSUPPORTED, "only k = 1 neighbourhoods are supported");
   pmrf_status st = validate_csr(n, row_ptr, col_idx);
   if (st != PMRF_OK) return st;
+  if (n > kMaxSlotVertices)
+    return fail(PMRF_EUNSUPPORTED, "more than " + std::to_string(kMaxSlotVertices) + " vertices in one graph");
   pmrf_hoods *hd = nullptr;
   try {
     hd = new pmrf_hoods();
@@ -284,15 +286,18 @@ extern "C" pmrf_status pmrf_build_neighborhoods(int32_t n, const int32_t *row_pt
     const int64_t nchunks = (ntiles + kChunkTiles - 1) / kChunkTiles;
     bool any_mid = false;
     for (const TileDesc &t : hd->tiles) any_mid |= t.kind == kMid;
-    hd->svid.assign((size_t)ntiles * kWave, -1);
+    hd->svid.assign((size_t)ntiles * kWave, (int32_t)kSlotEmpty);
     hd->smask.assign((size_t)ntiles * kWave, 0u);
     hd->smask_hi.assign(any_mid ? (size_t)ntiles * kWave : 0, 0u);
     hd->chdr.assign((size_t)nchunks, ChunkHdr{});
     for (int64_t ti = 0; ti < ntiles; ++ti) {
       const TileDesc &t = hd->tiles[ti];
       if (t.kind == kLarge) continue;
+      int first = 0;  // lane of the current neighbourhood's first member
       for (int k = 0; k < t.nelem; ++k) {
-        hd->svid[ti * kWave + k] = hd->dev_vid[t.elem_start + k];
+        if ((t.start_mask >> k) & 1) first = k;
+        hd->svid[ti * kWave + k] = (int32_t)((uint32_t)hd->dev_vid[t.elem_start + k] |
+                                             ((uint32_t)(k - first) << kSlotJShift));
         hd->smask[ti * kWave + k] = hd->mask[t.mask_start + (size_t)k * t.words];
         if (t.kind == kMid) hd->smask_hi[ti * kWave + k] = hd->mask[t.mask_start + (size_t)k * t.words + 1];
       }
@@ -306,7 +311,6 @@ extern "C" pmrf_status pmrf_build_neighborhoods(int32_t n, const int32_t *row_pt
       for (int64_t ti = tb; ti < te; ++ti) {
         const TileDesc &t = hd->tiles[ti];
         const int i = (int)(ti - tb);
-        c.start_mask[i] = t.start_mask;
         if (t.kind == kLarge) c.flags |= kHdrLarge;
         if (t.kind == kMid) c.flags |= 1 << (kHdrMidShift + i);
         // offsets of a chunk without LARGE packets stay below 8 * 64

@@ -47,7 +47,6 @@ static_assert(kChunkTiles >= 1 && kChunkTiles <= 23, "chunk header layout");
 // chunk's element data knowing only the chunk index.  Chunks with a LARGE
 // packet are processed from the element arrays instead.
 struct ChunkHdr {
-  uint64_t start_mask[kChunkTiles];  // per packet: bit i set if lane i starts a neighbourhood
   int32_t elem_start;                // first element of the chunk (element arrays)
   int32_t hood_start, hood_end;      // the chunk holds neighbourhoods [hood_start, hood_end)
   int32_t flags;                     // bit 0: a LARGE packet; bit 8 + i: packet i is MID (two words)
@@ -55,6 +54,12 @@ struct ChunkHdr {
 };
 static_assert(sizeof(ChunkHdr) % 4 == 0 && sizeof(ChunkHdr) <= 64 * 4, "ChunkHdr: one dword per lane");
 constexpr int kHdrLarge = 1;
+// slot word: member vertex (bits 0..25) and the member's index inside its
+// neighbourhood (bits 26..31); an unused slot holds all ones
+constexpr uint32_t kSlotEmpty = 0xffffffffu;
+constexpr int kSlotJShift = 26;
+constexpr uint32_t kSlotVidMask = (1u << kSlotJShift) - 1u;
+constexpr int32_t kMaxSlotVertices = (1 << kSlotJShift) - 1;
 constexpr int kHdrMidShift = 8;
 
 // Offsets (bytes) of the arrays inside the uploaded device buffer.
