@@ -214,13 +214,13 @@ pmrf_status pmrf_em_batch(int32_t B, const pmrf_em_item *items, void *d_ws, int6
  *  mode: 0 = automatic (currently 1); 1 = the run's kernels are captured once
  *        per distinct argument set into a HIP graph (kept in a small cache) and
  *        the graph is replayed on the caller's stream; the iteration kernel has
- *        one block per superchunk (32 work packets) of every graph;
+ *        one block per superchunk (40 work packets) of every graph;
  *        2 = as 1, but the iteration kernel is a persistent grid of
  *        blocks_per_cu blocks per compute unit that walk all superchunks;
  *        3 = direct launches on the caller's stream (one block per superchunk).
  *        While kernel timing is on (pmrf_profile_begin), runs use direct
  *        launches with the grid of the selected mode.
- *  waves_per_block: 1..16 (0 = automatic: 4, one wave per chunk of 8 packets)
+ *  waves_per_block: 1..16 (0 = automatic: 4, one wave per chunk of 10 packets)
  *  tiles_per_wave: reserved (0)
  *  blocks_per_cu: blocks per compute unit in mode 2 (0 = automatic: 5)
  * ------------------------------------------------------------------------ */

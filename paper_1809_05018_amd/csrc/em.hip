@@ -3,7 +3,7 @@
 //
 // Each EM iteration is two launches.
 //
-// k_iter works through chunks of 8 consecutive work packets (a packet is up to
+// k_iter works through chunks of 10 consecutive work packets (a packet is up to
 // 64 elements of whole neighbourhoods).  For every packet, one lane per element
 // (neighbourhood h, member v) does, for every label l:
 //   - gather y_v and the current labels of the packet (label bit planes from
@@ -17,7 +17,7 @@
 //     paper's Scatter, without write conflicts) and adds y - mu to its lane's
 //     per-label statistics of the parameter update;
 //   - the minimum goes to LDS.
-// After up to 8 packets, one lane per neighbourhood sums its members' minima in
+// After up to 10 packets, one lane per neighbourhood sums its members' minima in
 // member order (the paper's ReduceByKey<Add>), checks the neighbourhood's
 // convergence window and adds the sum to its lane's energy total.  At the end
 // of a chunk the wave reduces its lanes' statistics with a fixed butterfly into
@@ -73,7 +73,7 @@ constexpr int kRecMax = 3 * kMaxLabels + 4;
 constexpr int kSuperChunks = 4;    // chunks per block and record (fixed: part of the result's definition)
 constexpr int kGroupTiles = kChunkTiles;  // packets per neighbourhood-sum group (LDS buffer of 64 minima each)
 #ifndef PMRF_ITER_WAVES_PER_EU
-#define PMRF_ITER_WAVES_PER_EU 5
+#define PMRF_ITER_WAVES_PER_EU 4
 #endif
 constexpr int kVertPerBlock = 1024;
 
@@ -1001,7 +1001,7 @@ __device__ bool chunk_slots(const Ctx &c, int ck, bool done, const Theta<LMAX> &
   return true;
 }
 
-// One statistics chunk: packets [ck*8, min(ntiles, ck*8+8)).
+// One statistics chunk: packets [ck * kChunkTiles, min(ntiles, (ck + 1) * kChunkTiles)).
 //
 // Chunks without a LARGE packet (window <= 4) take the slot layout, where the
 // wave waits for memory twice per chunk (chunk_slots).  The others go packet by

@@ -36,7 +36,7 @@ struct TileDesc {
 static_assert(sizeof(TileDesc) == 24, "TileDesc layout");
 
 #ifndef PMRF_CHUNK_TILES
-#define PMRF_CHUNK_TILES 8
+#define PMRF_CHUNK_TILES 10
 #endif
 constexpr int kChunkTiles = PMRF_CHUNK_TILES;  // packets per statistics chunk (part of the result's definition)
 static_assert(kChunkTiles >= 1 && kChunkTiles <= 23, "chunk header layout");
