@@ -300,10 +300,16 @@ def bench_batched(args, dev):
         return (time.perf_counter() - t) / steps
 
     steps = max(1, min(args.steps, 5))
+    # each path runs with the launch shape the autotuner finds fastest for it
+    # (results are independent of the shape)
+    shape_plain, _ = pmrf.autotune_launch(plain, reps=1)
     t_plain = timed(plain, steps)
     res_plain = [p.results(params) for p in probs]
+    shape_batch, tune = pmrf.autotune_launch(batched, reps=2)
     t_batch = timed(batched, steps)
     res_batch = [p.results(params) for p in probs]
+    log(f"autotuned launch shapes: plain {shape_plain}, batched {shape_batch} "
+        f"({', '.join(f'{k}: {v * 1e3:.2f} ms' for k, v in tune.items())})")
     same = all(np.array_equal(a[k], b[k]) for a, b in zip(res_plain, res_batch) for k in ("x", "mu", "sigma", "trace"))
     pmrf.pmrf_profile_begin()
     batched()
@@ -318,6 +324,8 @@ def bench_batched(args, dev):
            "vs_baseline": None, "dtype": "f64", "data": "synthetic", "config": cfg,
            "plain": {"value": evals / t_plain, "ms_per_step": t_plain * 1e3},
            "batched_over_plain": t_plain / t_batch, "bitwise_equal_plain_batched": same,
+           "launch_shape": {"plain": list(shape_plain), "batched": list(shape_batch),
+                            "fields": "mode, waves_per_block, tiles_per_wave, blocks_per_cu"},
            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": f"k_iter<{4 if L > 2 else 2}>",
                         "alg_bytes_per_launch": b_iter, "avg_launch_us": avg * 1e6, "launches_timed": launches}}

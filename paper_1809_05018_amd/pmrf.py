@@ -11,6 +11,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import time
 from ctypes import POINTER, Structure, c_char_p, c_double, c_int32, c_int64, c_void_p
 
 import numpy as np
@@ -269,6 +270,41 @@ def pmrf_profile_end():
     ms, n = c_double(), c_int64()
     _check(lib.pmrf_profile_end(ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
+
+
+# Launch shapes the autotuner tries: (mode, waves_per_block, tiles_per_wave,
+# blocks_per_cu).  Graph replay with 2, 4 or 8 waves per block, and the
+# persistent grid with 4 or 8 resident blocks per compute unit.
+AUTOTUNE_SHAPES = ((1, 4, 0, 0), (1, 2, 0, 0), (1, 8, 0, 0), (2, 4, 0, 4), (2, 4, 0, 8))
+
+
+def autotune_launch(run, shapes=AUTOTUNE_SHAPES, reps=3, sync=None, clock=time.perf_counter):
+    """Pick the fastest launch shape for a workload and keep it selected.
+
+    ``run()`` enqueues the work once (one pmrf_em_run or pmrf_em_batch on the
+    device); ``sync()`` waits for the device (default: torch.cuda.synchronize).
+    Every shape is tried once untimed (graph capture), then timed over ``reps``
+    runs; the shape with the lowest mean time is set with pmrf_set_launch.
+    Results do not depend on the launch shape (every reduction order is fixed
+    by the graph), so this only changes speed.  Returns (best_shape,
+    {shape: seconds per run})."""
+    if sync is None:
+        import torch
+
+        sync = torch.cuda.synchronize
+    timings = {}
+    for shape in shapes:
+        pmrf_set_launch(*shape)
+        run()
+        sync()
+        t0 = clock()
+        for _ in range(reps):
+            run()
+        sync()
+        timings[tuple(shape)] = (clock() - t0) / reps
+    best = min(timings, key=timings.get)
+    pmrf_set_launch(*best)
+    return best, timings
 
 
 # --------------------------------------------------------------------------

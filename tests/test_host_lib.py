@@ -163,3 +163,22 @@ def test_launch_config_roundtrip():
             pmrf.pmrf_set_launch(0, 17, 0, 0)
     finally:
         pmrf.pmrf_set_launch(**old)
+
+
+def test_autotune_picks_fastest_shape_and_keeps_it():
+    old = pmrf.pmrf_get_launch()
+    now = [0.0]
+    cost = {(1, 4, 0, 0): 3.0, (1, 2, 0, 0): 5.0, (2, 4, 0, 4): 1.5}
+
+    def run():  # a fake workload whose duration depends on the selected shape
+        cfg = pmrf.pmrf_get_launch()
+        now[0] += cost[(cfg["mode"], cfg["waves_per_block"], cfg["tiles_per_wave"], cfg["blocks_per_cu"])]
+
+    try:
+        best, timings = pmrf.autotune_launch(run, shapes=list(cost), reps=2, sync=lambda: None,
+                                             clock=lambda: now[0])
+        assert best == (2, 4, 0, 4)
+        assert timings == cost
+        assert pmrf.pmrf_get_launch() == {"mode": 2, "waves_per_block": 4, "tiles_per_wave": 0, "blocks_per_cu": 4}
+    finally:
+        pmrf.pmrf_set_launch(**old)
