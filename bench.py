@@ -204,7 +204,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "k_iter<2>", "alg_bytes_per_launch": b_launch,
                      "avg_launch_us": avg_launch_s * 1e6, "launches_timed": launches,
-                     "timing": "HIP events around each EM-iteration launch, second timed region of the same steps"},
+                     "timing": "HIP events stamped with each EM iteration's kernel dispatch begin and end (hipExtLaunchKernel), second timed region of the same steps"},
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:

@@ -31,6 +31,7 @@
 // Chunks and their order are fixed by the graph alone, so the results do not
 // depend on the launch shape or on how graphs are batched.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <cstddef>
@@ -129,6 +130,12 @@ struct DescPack {
 
 // Order the wave's own LDS writes before its LDS reads (a single wave executes
 // its LDS instructions in order; this also stops the compiler moving them).
+// The calling thread's wave within its block.  The value is the same on every
+// lane, which the compiler cannot see from threadIdx.x alone; reading it from
+// the first lane keeps it (and all chunk bookkeeping derived from it) in
+// scalar registers.
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
+
 __device__ __forceinline__ void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 
 // Sums across the 64 lanes in one fixed order, with DPP lane moves (no trip
@@ -769,9 +776,11 @@ __device__ __forceinline__ void slot_elem(const Ctx &c, int eoff, bool mid, int 
   const int j = (int)(sv >> kSlotJShift);
   const int base = lane - j;
   if (valid && (unsigned)xv >= (unsigned)c.L) cs.err |= 1;
+  // all PMAX planes: for valid labels (below L) the planes past the graph's
+  // own count are zero, and an invalid label fails the run anyway
   uint64_t planes[PMAX];
 #pragma unroll
-  for (int k = 0; k < PMAX; ++k) planes[k] = (k < c.P) ? __ballot(valid && ((xv >> k) & 1)) : 0ull;
+  for (int k = 0; k < PMAX; ++k) planes[k] = __ballot(valid && ((xv >> k) & 1));
   int deg, cnt[LMAX];
   uint32_t own;  // the element's own bit: set for the owner element of its vertex
   if (!mid) {
@@ -788,10 +797,10 @@ __device__ __forceinline__ void slot_elem(const Ctx &c, int eoff, bool mid, int 
         uint32_t eq = ~0u;
 #pragma unroll
         for (int k = 0; k < PMAX; ++k)
-          if (k < c.P) {
-            const uint32_t pk = (uint32_t)(planes[k] >> base);
-            eq &= ((l >> k) & 1) ? pk : ~pk;
-          }
+        {
+          const uint32_t pk = (uint32_t)(planes[k] >> base);
+          eq &= ((l >> k) & 1) ? pk : ~pk;
+        }
         cnt[l] = __popc(nbr & eq);
       }
     }
@@ -811,10 +820,10 @@ __device__ __forceinline__ void slot_elem(const Ctx &c, int eoff, bool mid, int 
         uint64_t eq = ~0ull;
 #pragma unroll
         for (int k = 0; k < PMAX; ++k)
-          if (k < c.P) {
-            const uint64_t pk = planes[k] >> base;
-            eq &= ((l >> k) & 1) ? pk : ~pk;
-          }
+        {
+          const uint64_t pk = planes[k] >> base;
+          eq &= ((l >> k) & 1) ? pk : ~pk;
+        }
         cnt[l] = __popcll(nbr & eq);
       }
     }
@@ -924,16 +933,18 @@ __device__ bool chunk_slots(const Ctx &c, int ck, bool done, const Theta<LMAX> &
                             double *od, int *oa, int lane) {
   const int tb = ck * kChunkTiles;
   const int nt = min(kChunkTiles, c.ntiles - tb);
+  // The slot arrays are padded to whole chunks, so every packet slot of the
+  // chunk can be read; chunk bases are uniform, each load is base + lane * 4 +
+  // an immediate.
+  const gptr<const int32_t> svb = c.svid + (size_t)tb * kWave;
+  const gptr<const uint32_t> smb = c.smask + (size_t)tb * kWave;
+  const unsigned ul = (unsigned)lane;
   int v[kChunkTiles];
   uint32_t am[kChunkTiles];
 #pragma unroll
   for (int i = 0; i < kChunkTiles; ++i) {
-    v[i] = -1;
-    am[i] = 0;
-    if (i < nt) {
-      v[i] = c.svid[(size_t)(tb + i) * kWave + lane];
-      am[i] = c.smask[(size_t)(tb + i) * kWave + lane];
-    }
+    v[i] = svb[i * kWave + ul];
+    am[i] = smb[i * kWave + ul];
   }
   // the header: dword k in lane k (one load), fields read out with readlane
   // once it has arrived
@@ -952,16 +963,13 @@ __device__ bool chunk_slots(const Ctx &c, int ck, bool done, const Theta<LMAX> &
   uint32_t ah[kChunkTiles];
 #pragma unroll
   for (int i = 0; i < kChunkTiles; ++i) {
-    xv[i] = 0;
-    yv[i] = 0.0;
+    // an empty slot reads vertex 0; nothing of an empty slot is used
+    const unsigned vv = (uint32_t)v[i] != kSlotEmpty ? (uint32_t)v[i] & kSlotVidMask : 0u;
+    xv[i] = c.xr[vv];
+    yv[i] = c.y[vv];
     ah[i] = 0;
-    if (i < nt && (uint32_t)v[i] != kSlotEmpty) {
-      const int vv = (int)((uint32_t)v[i] & kSlotVidMask);
-      xv[i] = c.xr[vv];
-      yv[i] = c.y[vv];
-    }
-    if (kPrefetchHi<LMAX> && i < nt && ((flags >> (kHdrMidShift + i)) & 1))
-      ah[i] = c.smask_hi[(size_t)(tb + i) * kWave + lane];
+    if (kPrefetchHi<LMAX> && ((flags >> (kHdrMidShift + i)) & 1))
+      ah[i] = (c.smask_hi + (size_t)tb * kWave)[i * kWave + ul];
   }
   HoodPre pre{0, 0, {}};
   {
@@ -1109,7 +1117,7 @@ __global__ __launch_bounds__(256) void k_mstep_init(const GraphDev *graphs, int 
       if (l == xv) cv = c[l];
     ls.add_owner(xv, y[v] - cv);
   }
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = wave_id(), lane = threadIdx.x & 63;
   ls.store(&part[wave][0], 1, L, lane);
   __syncthreads();
   if (threadIdx.x >= 64) return;
@@ -1129,7 +1137,7 @@ __global__ __launch_bounds__(kFoldThreads) void k_fin_init(const GraphDev *graph
   const GraphDev &G = graphs[blockIdx.x];
   GraphState *st = G.st;
   if (!G.init_from_labels || st->done) return;
-  fold_records<LMAX>(gbl((const double *)G.rec), G.vnblocks, G.L, tot, part, blockDim.x >> 6, threadIdx.x >> 6,
+  fold_records<LMAX>(gbl((const double *)G.rec), G.vnblocks, G.L, tot, part, blockDim.x >> 6, wave_id(),
                      threadIdx.x & 63);
   if (threadIdx.x != 0) return;
   if (tot[3 * G.L + 3] != 0.0) {
@@ -1220,9 +1228,9 @@ template <int LMAX, bool SINGLE>
 __global__ __launch_bounds__(kFoldThreads) void k_fold(const GraphDev *graphs, const GraphDev g1, int B, int t) {
   __shared__ FoldLds<LMAX> sh;
   if constexpr (SINGLE)
-    fold_iteration<LMAX>(g1, t, sh, blockDim.x >> 6, threadIdx.x >> 6, threadIdx.x & 63);
+    fold_iteration<LMAX>(g1, t, sh, blockDim.x >> 6, wave_id(), threadIdx.x & 63);
   else
-    fold_iteration<LMAX>(graphs[blockIdx.x], t, sh, blockDim.x >> 6, threadIdx.x >> 6, threadIdx.x & 63);
+    fold_iteration<LMAX>(graphs[blockIdx.x], t, sh, blockDim.x >> 6, wave_id(), threadIdx.x & 63);
 }
 
 // One EM iteration over every graph of the launch.  Superchunk b of a graph
@@ -1293,7 +1301,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(LMAX <= 2 
     const GraphDev *__restrict__ graphs, const GraphDev g1, int B, int nsuper_total, int t) {
   extern __shared__ double smem[];
   __shared__ double part[kSuperChunks][rec_words(LMAX)];
-  const int nw = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nw = blockDim.x >> 6, wave = wave_id(), lane = threadIdx.x & 63;
   double *mb = smem + wave * kWaveLds;
   uint64_t *pl = reinterpret_cast<uint64_t *>(mb + kGroupTiles * 64);
   double *od = mb + kGroupTiles * 64 + 64;
@@ -1324,7 +1332,7 @@ template <int LMAX>
 __global__ __launch_bounds__(1024) void k_iter_packets(const GraphDev *__restrict__ graphs, int B, int t) {
   extern __shared__ double smem[];
   __shared__ double part[kSuperChunks][rec_words(LMAX)];
-  const int nw = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nw = blockDim.x >> 6, wave = wave_id(), lane = threadIdx.x & 63;
   double *mb = smem + wave * kWaveLds;
   uint64_t *pl = reinterpret_cast<uint64_t *>(mb + kGroupTiles * 64);
   double *od = mb + kGroupTiles * 64 + 64;
@@ -1369,26 +1377,33 @@ __global__ void k_final(const GraphDev *graphs, int B) {
 std::mutex g_launch_mu;
 pmrf_launch g_launch{0, 0, 0, 0};
 
-// event pairs bracketing iteration launches while profiling is on
+// While profiling is on, each EM iteration's work kernels are launched with a
+// start/stop event pair that the runtime stamps with the kernels' own dispatch
+// begin and end times (hipExtLaunchKernel), so no marker packet sits between
+// the stamps and the kernel.
 struct Profiler {
   bool on = false;
   size_t used = 0;
   std::vector<hipEvent_t> start, stop;
 } g_prof;
 
-hipError_t prof_mark(hipStream_t stream, bool begin) {
+// events for the next iteration (nullptr pair when profiling is off)
+hipError_t prof_pair(hipEvent_t *a, hipEvent_t *b) {
+  *a = *b = nullptr;
   if (!g_prof.on) return hipSuccess;
-  if (begin && g_prof.used == g_prof.start.size()) {
-    hipEvent_t a, b;
-    hipError_t e = hipEventCreate(&a);
+  if (g_prof.used == g_prof.start.size()) {
+    hipEvent_t x, y;
+    hipError_t e = hipEventCreate(&x);
     if (e != hipSuccess) return e;
-    e = hipEventCreate(&b);
+    e = hipEventCreate(&y);
     if (e != hipSuccess) return e;
-    g_prof.start.push_back(a);
-    g_prof.stop.push_back(b);
+    g_prof.start.push_back(x);
+    g_prof.stop.push_back(y);
   }
-  if (begin) return hipEventRecord(g_prof.start[g_prof.used], stream);
-  return hipEventRecord(g_prof.stop[g_prof.used++], stream);
+  *a = g_prof.start[g_prof.used];
+  *b = g_prof.stop[g_prof.used];
+  ++g_prof.used;
+  return hipSuccess;
 }
 
 constexpr int kModeGraph = 1, kModePersistent = 2, kModeDirect = 3;
@@ -1610,22 +1625,35 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
       }
     }
     for (int t = 0; t < max_iters; ++t) {
-      if (events) HIP_TRY(prof_mark(s, true));
+      // the iteration's first kernel carries the start event, its last the stop event
+      hipEvent_t ev0 = nullptr, ev1 = nullptr;
+      if (events && (blocks_iter > 0 || blocks_pk > 0)) HIP_TRY(prof_pair(&ev0, &ev1));
+      hipEvent_t slot_start = ev0, slot_stop = blocks_pk > 0 ? nullptr : ev1;
+      hipEvent_t pk_start = blocks_iter > 0 ? nullptr : ev0, pk_stop = ev1;
+// plain launches unless the iteration is being timed (graph capture never is)
+#define PMRF_LAUNCH(KERNEL, GRID, START, STOP, ...)                                                          \
+  do {                                                                                                        \
+    if ((START) || (STOP))                                                                                    \
+      hipExtLaunchKernelGGL(KERNEL, GRID, dim3(threads), lds, s, START, STOP, 0, __VA_ARGS__);                \
+    else                                                                                                      \
+      hipLaunchKernelGGL(KERNEL, GRID, dim3(threads), lds, s, __VA_ARGS__);                                   \
+  } while (0)
 #define PMRF_LAUNCH_ITER(LM)                                                                                  \
   do {                                                                                                        \
     if (persist && B == 1)                                                                                    \
-      hipLaunchKernelGGL((k_iter<LM, true, true>), dim3(grid_iter), dim3(threads), lds, s, gd, desc[0], B,     \
-                         blocks_iter, t);                                                                     \
+      PMRF_LAUNCH((k_iter<LM, true, true>), dim3(grid_iter), slot_start, slot_stop, gd, desc[0], B,           \
+                  blocks_iter, t);                                                                            \
     else if (persist)                                                                                         \
-      hipLaunchKernelGGL((k_iter<LM, true, false>), dim3(grid_iter), dim3(threads), lds, s, gd, desc[0], B,    \
-                         blocks_iter, t);                                                                     \
+      PMRF_LAUNCH((k_iter<LM, true, false>), dim3(grid_iter), slot_start, slot_stop, gd, desc[0], B,          \
+                  blocks_iter, t);                                                                            \
     else if (B == 1)                                                                                          \
-      hipLaunchKernelGGL((k_iter<LM, false, true>), dim3(grid_iter), dim3(threads), lds, s, gd, desc[0], B,    \
-                         blocks_iter, t);                                                                     \
+      PMRF_LAUNCH((k_iter<LM, false, true>), dim3(grid_iter), slot_start, slot_stop, gd, desc[0], B,          \
+                  blocks_iter, t);                                                                            \
     else                                                                                                      \
-      hipLaunchKernelGGL((k_iter<LM, false, false>), dim3(grid_iter), dim3(threads), lds, s, gd, desc[0], B,   \
-                         blocks_iter, t);                                                                     \
+      PMRF_LAUNCH((k_iter<LM, false, false>), dim3(grid_iter), slot_start, slot_stop, gd, desc[0], B,         \
+                  blocks_iter, t);                                                                            \
   } while (0)
+#define PMRF_LAUNCH_PK(LM) PMRF_LAUNCH(k_iter_packets<LM>, dim3(blocks_pk), pk_start, pk_stop, gd, B, t)
       if (blocks_iter > 0) {
         switch (lm) {
           case 2: PMRF_LAUNCH_ITER(2); break;
@@ -1637,15 +1665,16 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
       }
       if (blocks_pk > 0) {
         switch (lm) {
-          case 2: hipLaunchKernelGGL(k_iter_packets<2>, dim3(blocks_pk), dim3(threads), lds, s, gd, B, t); break;
-          case 4: hipLaunchKernelGGL(k_iter_packets<4>, dim3(blocks_pk), dim3(threads), lds, s, gd, B, t); break;
-          case 8: hipLaunchKernelGGL(k_iter_packets<8>, dim3(blocks_pk), dim3(threads), lds, s, gd, B, t); break;
-          default: hipLaunchKernelGGL(k_iter_packets<16>, dim3(blocks_pk), dim3(threads), lds, s, gd, B, t); break;
+          case 2: PMRF_LAUNCH_PK(2); break;
+          case 4: PMRF_LAUNCH_PK(4); break;
+          case 8: PMRF_LAUNCH_PK(8); break;
+          default: PMRF_LAUNCH_PK(16); break;
         }
       }
 #undef PMRF_LAUNCH_ITER
+#undef PMRF_LAUNCH_PK
+#undef PMRF_LAUNCH
       HIP_TRY(hipGetLastError());
-      if (events) HIP_TRY(prof_mark(s, false));
 #define PMRF_LAUNCH_FOLD(LM)                                                                                \
   do {                                                                                                      \
     if (B == 1)                                                                                             \

@@ -286,9 +286,11 @@ extern "C" pmrf_status pmrf_build_neighborhoods(int32_t n, const int32_t *row_pt
     const int64_t nchunks = (ntiles + kChunkTiles - 1) / kChunkTiles;
     bool any_mid = false;
     for (const TileDesc &t : hd->tiles) any_mid |= t.kind == kMid;
-    hd->svid.assign((size_t)ntiles * kWave, (int32_t)kSlotEmpty);
-    hd->smask.assign((size_t)ntiles * kWave, 0u);
-    hd->smask_hi.assign(any_mid ? (size_t)ntiles * kWave : 0, 0u);
+    // padded to whole chunks (empty slots), so a chunk's loads need no bounds
+    const size_t slots = (size_t)(nchunks * kChunkTiles) * kWave;
+    hd->svid.assign(slots, (int32_t)kSlotEmpty);
+    hd->smask.assign(slots, 0u);
+    hd->smask_hi.assign(any_mid ? slots : 0, 0u);
     hd->chdr.assign((size_t)nchunks, ChunkHdr{});
     for (int64_t ti = 0; ti < ntiles; ++ti) {
       const TileDesc &t = hd->tiles[ti];
