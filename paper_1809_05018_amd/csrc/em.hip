@@ -354,6 +354,19 @@ __device__ __forceinline__ int find_graph(const GraphDev *graphs, int B, int blo
   return lo;
 }
 
+// Workgroups are dealt to the chip's XCDs round-robin (workgroup i on XCD
+// i % kXcds), and each XCD has its own L2.  The block that workgroup i plays is
+// chosen so that each XCD takes one contiguous run of blocks: neighbouring
+// superchunks gather mostly the same vertices, which then stay in one L2
+// instead of being fetched by every XCD.  A bijection on [0, grid), so any
+// device (or a different dealing order) still gets every block exactly once.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_block(int i, int grid) {
+  const int q = grid / kXcds, r = grid % kXcds;
+  const int x = i % kXcds, k = i / kXcds;
+  return x * q + min(x, r) + k;
+}
+
 // ------------------------------------------------------------- tile kernels
 template <int LMAX>
 struct Theta {
@@ -1307,11 +1320,12 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(LMAX <= 2 
   double *od = mb + kGroupTiles * 64 + 64;
   int *oa = reinterpret_cast<int *>(od + kOwnCap);
   if constexpr (!PERSIST) {
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
     if constexpr (SINGLE) {
-      iter_superchunk<LMAX, false>(g1, blockIdx.x, t, part, mb, pl, od, oa, nw, wave, lane);
+      iter_superchunk<LMAX, false>(g1, blk, t, part, mb, pl, od, oa, nw, wave, lane);
     } else {
-      const GraphDev &G = graphs[find_graph(graphs, B, blockIdx.x, kGridSlot)];
-      iter_superchunk<LMAX, false>(G, blockIdx.x - G.block0, t, part, mb, pl, od, oa, nw, wave, lane);
+      const GraphDev &G = graphs[find_graph(graphs, B, blk, kGridSlot)];
+      iter_superchunk<LMAX, false>(G, blk - G.block0, t, part, mb, pl, od, oa, nw, wave, lane);
     }
   } else {
     for (int sc = blockIdx.x; sc < nsuper_total; sc += gridDim.x) {
