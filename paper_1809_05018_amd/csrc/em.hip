@@ -73,8 +73,15 @@ constexpr int kRecMax = 3 * kMaxLabels + 4;
 
 constexpr int kSuperChunks = 4;    // chunks per block and record (fixed: part of the result's definition)
 constexpr int kGroupTiles = kChunkTiles;  // packets per neighbourhood-sum group (LDS buffer of 64 minima each)
+// Register budgets of the two-label iteration kernels, as resident waves per
+// SIMD: one graph (a single round of waves; the lower budget keeps every value
+// in registers) and a batch (many rounds; one more wave hides more latency at
+// the cost of one spilled value outside the packet loop).
 #ifndef PMRF_ITER_WAVES_PER_EU
 #define PMRF_ITER_WAVES_PER_EU 4
+#endif
+#ifndef PMRF_BATCH_WAVES_PER_EU
+#define PMRF_BATCH_WAVES_PER_EU 5
 #endif
 constexpr int kVertPerBlock = 1024;
 
@@ -696,6 +703,8 @@ __device__ __forceinline__ int bcast(int v, int lane_src) { return __builtin_amd
 // list of kOwnCap entries (y - mu_a as double, a as int).
 constexpr int kOwnCap = 128;
 constexpr int kWaveLds = kGroupTiles * 64 + 64 + kOwnCap + kOwnCap / 2;  // in doubles
+static_assert(kGroupTiles * 64 + 64 + 3 <= kWaveLds, "neighbourhood sums read up to 3 minima past 64 members");
+static_assert(kGroupTiles * 64 >= 8 * 64, "record rows pass eight values through the minima buffer");
 
 template <int LMAX>
 struct ChunkStats {
@@ -731,34 +740,50 @@ struct ChunkStats {
       }
     }
   }
-  // butterfly over the lanes; lane 0 writes the record row (LDS)
-  __device__ void store(double *row, int L, int lane) {
+  // Value v of a lane's statistics: for label l = v / 3 its owner count
+  // (v % 3 == 0), sum of y - mu (1) and of its square (2); v = 3 LMAX is the
+  // sum of neighbourhood totals.
+  static constexpr int kValues = 3 * LMAX + 1;
+  __device__ __forceinline__ double value(int v) const {
+    if (v == 3 * LMAX) return T;
+    const int l = v / 3;
+    return v % 3 == 0 ? (double)cnt[l] : v % 3 == 1 ? s1[l] : s2[l];
+  }
+  // Record row of the chunk (LDS), in a fixed order: eight values at a time
+  // pass through the wave's scratch buf (>= 8 * 64 doubles) transposed;
+  // lane 8 v + q adds lanes 8 q .. 8 q + 7 of value v in lane order, and the
+  // eight lanes of value v combine with pair, quad and half-row moves.  Lane
+  // 8 v writes value v.  The caller has synchronised buf.
+  __device__ void store(double *row, double *buf, int L, int lane) {
 #pragma unroll
-    for (int l = 0; l < LMAX; ++l)
-      if (l < L) {
-        const double a = wave_sum(s1[l]);
-        const double b = wave_sum(s2[l]);
-        if (lane == 0) {
-          row[3 * l + 1] = a;
-          row[3 * l + 2] = b;
-        }
+    for (int v0 = 0; v0 < kValues; v0 += 8) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        if (v0 + i < kValues) buf[i * 64 + lane] = value(v0 + i);
+      wave_lds_sync();
+      const int vi = lane >> 3, q = lane & 7;
+      const double *src = buf + vi * 64 + q * 8;
+      double p = 0.0;
+      if (v0 + vi < kValues) {
+        double r[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) r[i] = src[i];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) p = p + r[i];
       }
-#pragma unroll
-    for (int l0 = 0; l0 < LMAX; l0 += 4) {
-      long long packed = 0;
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (l0 + q < LMAX) packed |= (long long)cnt[l0 + q] << (16 * q);
-      packed = wave_sum(packed);  // per-chunk counts stay below 2^16
-      if (lane == 0)
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-          if (l0 + q < L) row[3 * (l0 + q)] = (double)((packed >> (16 * q)) & 0xffff);
+      p = p + dpp_f64<kDppSwap1, 0xf>(p);
+      p = p + dpp_f64<kDppSwap2, 0xf>(p);
+      p = p + dpp_f64<kDppHalfMirror, 0xf>(p);
+      const int v = v0 + vi;
+      if (q == 0 && v < kValues) {
+        const int l = v / 3;
+        if (v == 3 * LMAX) row[3 * L] = p;
+        else if (l < L) row[v] = p;
+      }
+      wave_lds_sync();  // buf is rewritten by the next eight values
     }
-    const double t = wave_sum(T);
     const int e = __popcll(__ballot(err != 0));
     if (lane == 0) {
-      row[3 * L] = t;
       row[3 * L + 1] = (double)ties;
       row[3 * L + 2] = (double)nonconv;
       row[3 * L + 3] = (double)e;
@@ -899,11 +924,21 @@ __device__ __forceinline__ void lean_hoods(const Ctx &c, int h0, int h1, int gst
         for (int w = 1; w <= kPreWindow; ++w)
           if (w <= c.W) prev[w - 1] = c.ring[(size_t)((c.t - w) % slots) * c.H + h];
     }
+    // four minima per step, requested together; a lane whose neighbourhood
+    // has ended keeps its sum.  The reads past a neighbourhood stay inside the
+    // wave's LDS region: o < kGroupTiles * 64 and k + 3 < 64 + 3 (no
+    // neighbourhood on this path has more than 64 members).
+    if (!act) o = 0;
     double S = 0.0;
     for (int k = 0; __ballot(k < s); k += 4) {
+      double m4[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-        if (k + i < s) S = S + mb[o + k + i];
+      for (int i = 0; i < 4; ++i) m4[i] = mb[o + k + i];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const double S1 = S + m4[i];
+        S = k + i < s ? S1 : S;
+      }
     }
     bool conv = true;
     if (act) {
@@ -1018,7 +1053,7 @@ __device__ bool chunk_slots(const Ctx &c, int ck, bool done, const Theta<LMAX> &
   cs.take_owners(od, oa, ocount, lane);
   lean_hoods<LMAX>(c, h0, hend, gstart, pre, cs, mb, lane);
   wave_lds_sync();
-  cs.store(row, c.L, lane);
+  cs.store(row, mb, c.L, lane);  // the minima are no longer needed
   return true;
 }
 
@@ -1310,7 +1345,7 @@ __device__ __forceinline__ void iter_superchunk(const GraphDev &G, int b, int t,
 // without a dependent load); otherwise each block looks its graph up in
 // graphs[0 .. B).
 template <int LMAX, bool PERSIST, bool SINGLE>
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(LMAX <= 2 ? PMRF_ITER_WAVES_PER_EU : 1, 8))) void k_iter(
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(LMAX <= 2 ? (SINGLE ? PMRF_ITER_WAVES_PER_EU : PMRF_BATCH_WAVES_PER_EU) : 1, 8))) void k_iter(
     const GraphDev *__restrict__ graphs, const GraphDev g1, int B, int nsuper_total, int t) {
   extern __shared__ double smem[];
   __shared__ double part[kSuperChunks][rec_words(LMAX)];

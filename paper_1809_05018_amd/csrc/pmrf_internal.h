@@ -39,7 +39,7 @@ static_assert(sizeof(TileDesc) == 24, "TileDesc layout");
 #define PMRF_CHUNK_TILES 10
 #endif
 constexpr int kChunkTiles = PMRF_CHUNK_TILES;  // packets per statistics chunk (part of the result's definition)
-static_assert(kChunkTiles >= 1 && kChunkTiles <= 23, "chunk header layout");
+static_assert(kChunkTiles >= 8 && kChunkTiles <= 23, "chunk header layout; record rows use 8 packets of LDS");
 
 // Header of one chunk of kChunkTiles consecutive packets, for the slot layout:
 // packet t owns slots [64 t, 64 t + 64) of the slot arrays (member id, low and
