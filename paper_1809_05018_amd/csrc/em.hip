@@ -974,10 +974,12 @@ __device__ __forceinline__ int load_theta(const Ctx &c, Theta<LMAX> &th) {
 // element passes, the owner list and the neighbourhood pass.  Returns false,
 // having written nothing, when the chunk has a LARGE packet or the window is
 // longer than kPreWindow (the packet-by-packet path takes those), and true
-// without writing when the run is already done.  done and th arrive with the
-// chunk's loads (they are requested before the kernel's first store).
-template <int LMAX>
-__device__ bool chunk_slots(const Ctx &c, int ck, bool done, const Theta<LMAX> &th, double *row, double *mb,
+// without writing when skip is set (the run has ended or is done) or, with
+// READ_DONE, when the run state's done flag is set (read here, after the
+// chunk's loads are requested).  th arrives with the chunk's loads (requested
+// before the kernel's first store).
+template <int LMAX, bool READ_DONE>
+__device__ bool chunk_slots(const Ctx &c, int ck, bool skip, const Theta<LMAX> &th, double *row, double *mb,
                             double *od, int *oa, int lane) {
   const int tb = ck * kChunkTiles;
   const int nt = min(kChunkTiles, c.ntiles - tb);
@@ -1004,7 +1006,7 @@ __device__ bool chunk_slots(const Ctx &c, int ck, bool done, const Theta<LMAX> &
                 kDwOff = offsetof(ChunkHdr, elem_off) / 4;
   const int flags = (int)hdr(kDwFlags);
   if ((flags & kHdrLarge) || c.W > kPreWindow) return false;
-  if (done) return true;
+  if (skip || (READ_DONE && c.st->done != 0)) return true;
   const int gstart = (int)hdr(kDwElem), h0 = (int)hdr(kDwHood), hend = (int)hdr(kDwHend);
   int xv[kChunkTiles];
   double yv[kChunkTiles];
@@ -1221,19 +1223,19 @@ __device__ __forceinline__ void fold_iteration(const GraphDev &G, int t, FoldLds
   const int done = st->done;
   const long long ties_total = st->ties_total;
   const int map_conv = st->map_conv, em_conv = st->em_conv;
-  if (tp >= max_iters) return;
-  fold_records<LMAX>(gbl((const double *)G.rec) + (size_t)(tp & 1) * G.rec_stride, G.nsuper, L, sh.tot, sh.part,
-                     nw, wave, lane);
-  if (wave != 0 || done) return;
-  // wave 0: label `lane`'s parameters of tp and the energy total of iteration
-  // tp - lane - 1 (thist holds max(1, max_iters) entries; used where tp >= lane + 1)
+  // label `lane`'s parameters of tp and the energy total of iteration
+  // tp - lane - 1 (thist holds max(1, max_iters) entries; used where
+  // tp >= lane + 1), requested with the records; only wave 0 uses them
   const int ll = lane < kMaxLabels ? lane : 0;
   double mu = st->th[tp & 1][ll].mu, sg = st->th[tp & 1][ll].sigma;
   double wl = st->th[tp & 1][ll].w, lg = st->th[tp & 1][ll].lg;
   const double hist = thist[min(max(0, tp - lane - 1), max(0, max_iters - 1))];
-  // both requests are in flight before either is waited for (no branch may
-  // separate them)
-  asm volatile("" ::"v"(mu), "v"(sg), "v"(wl), "v"(lg), "v"(hist));
+  // a graph whose run has ended (tp >= max_iters, in a batch of mixed run
+  // lengths) folds but stores nothing; testing it after the fold lets every
+  // load above be requested at once
+  fold_records<LMAX>(gbl((const double *)G.rec) + (size_t)(tp & 1) * G.rec_stride, G.nsuper, L, sh.tot, sh.part,
+                     nw, wave, lane);
+  if (tp >= max_iters || wave != 0 || done) return;
   if (sh.tot[3 * L + 3] != 0.0) {
     if (lane == 0) {
       st->status = PMRF_EBADLABEL;
@@ -1287,11 +1289,14 @@ __global__ __launch_bounds__(kFoldThreads) void k_fold(const GraphDev *graphs, c
 // into record b (buffer t & 1).  PACKET: the superchunk holds a LARGE packet
 // (or the window is longer than kPreWindow) and goes packet by packet over the
 // element arrays; otherwise every chunk takes the slot layout.
-template <int LMAX, bool PACKET>
+template <int LMAX, bool PACKET, bool SINGLE = false>
 __device__ __forceinline__ void iter_superchunk(const GraphDev &G, int b, int t, double (*part)[rec_words(LMAX)],
                                                 double *mb, uint64_t *pl, double *od, int *oa, int nw, int wave,
                                                 int lane) {
-  if (t >= G.max_iters) return;
+  // A graph whose run has ended (a batch mixes run lengths) computes and
+  // writes nothing; the test joins the run state's done flag instead of
+  // returning first, so the chunk's loads need not wait for it (they only read).
+  const bool ended = t >= G.max_iters;
   {
     Ctx c;
     c.tiles = gbl(G.tiles);
@@ -1320,14 +1325,25 @@ __device__ __forceinline__ void iter_superchunk(const GraphDev &G, int b, int t,
     const int c0 = b * kSuperChunks;
     const int c1 = min(G.nchunks, c0 + kSuperChunks);
     Theta<LMAX> th;
-    const bool done = load_theta<LMAX>(c, th);  // uniform scalar loads, waited for with the chunk's loads
-    for (int ck = c0 + wave; ck < c1; ck += nw) {
-      if constexpr (PACKET) {
-        if (!done) chunk_packets<LMAX>(c, ck, th, part[ck - c0], mb, pl, lane);
-      } else {
-        chunk_slots<LMAX>(c, ck, done, th, part[ck - c0], mb, od, oa, lane);
-      }
+    const int done_flag = load_theta<LMAX>(c, th);  // scalar loads, waited for with the chunk's
+    if constexpr (!PACKET) {
+      // single graph: the slot path's descriptor fields (kernel arguments)
+      // arrive in one batch of scalar loads, before the first branch
+      // (otherwise each branch waits for the fields it tests before the next
+      // ones are even requested); the run state's done flag is read inside
+      // the chunk, after the chunk's loads are requested.  (A batch looks its
+      // descriptor up in memory; pinning it there costs registers.)
+      if constexpr (SINGLE)
+        asm volatile("" ::"s"(c.chdr), "s"(c.svid), "s"(c.smask), "s"(c.st), "s"(c.hood_ptr), "s"(c.y), "s"(c.xr),
+                     "s"(c.xw), "s"(c.ring), "s"(c.H), "s"(c.W), "s"(c.L), "s"(c.ntiles), "s"(c.nchunks), "s"(nw));
+      const bool skip = SINGLE ? ended : (done_flag != 0 || ended);
+      for (int ck = c0 + wave; ck < c1; ck += nw)
+        chunk_slots<LMAX, SINGLE>(c, ck, skip, th, part[ck - c0], mb, od, oa, lane);
+    } else {
+      if (!(done_flag != 0 || ended))
+        for (int ck = c0 + wave; ck < c1; ck += nw) chunk_packets<LMAX>(c, ck, th, part[ck - c0], mb, pl, lane);
     }
+    const bool done = done_flag != 0 || ended;
     __syncthreads();
     const int words = rec_words(c.L);
     if (!done && threadIdx.x < words) {
@@ -1357,7 +1373,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(LMAX <= 2 
   if constexpr (!PERSIST) {
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     if constexpr (SINGLE) {
-      iter_superchunk<LMAX, false>(g1, blk, t, part, mb, pl, od, oa, nw, wave, lane);
+      iter_superchunk<LMAX, false, true>(g1, blk, t, part, mb, pl, od, oa, nw, wave, lane);
     } else {
       const GraphDev &G = graphs[find_graph(graphs, B, blk, kGridSlot)];
       iter_superchunk<LMAX, false>(G, blk - G.block0, t, part, mb, pl, od, oa, nw, wave, lane);
@@ -1365,7 +1381,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(LMAX <= 2 
   } else {
     for (int sc = blockIdx.x; sc < nsuper_total; sc += gridDim.x) {
       if constexpr (SINGLE) {
-        iter_superchunk<LMAX, false>(g1, sc, t, part, mb, pl, od, oa, nw, wave, lane);
+        iter_superchunk<LMAX, false, true>(g1, sc, t, part, mb, pl, od, oa, nw, wave, lane);
       } else {
         const GraphDev &G = graphs[find_graph(graphs, B, sc, kGridSlot)];
         iter_superchunk<LMAX, false>(G, sc - G.block0, t, part, mb, pl, od, oa, nw, wave, lane);
