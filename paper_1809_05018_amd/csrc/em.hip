@@ -815,14 +815,16 @@ __device__ __forceinline__ void slot_elem(const Ctx &c, int eoff, bool mid, int 
   const int base = lane - j;
   if (valid && (unsigned)xv >= (unsigned)c.L) cs.err |= 1;
   // all PMAX planes: for valid labels (below L) the planes past the graph's
-  // own count are zero, and an invalid label fails the run anyway
+  // own count are zero, and an invalid label fails the run anyway.  Plane bits
+  // of empty slots are never read: they are reached only through adjacency
+  // bits, which name members of the same neighbourhood.
   uint64_t planes[PMAX];
 #pragma unroll
-  for (int k = 0; k < PMAX; ++k) planes[k] = __ballot(valid && ((xv >> k) & 1));
+  for (int k = 0; k < PMAX; ++k) planes[k] = __ballot((xv >> k) & 1);
   int deg, cnt[LMAX];
   uint32_t own;  // the element's own bit: set for the owner element of its vertex
   if (!mid) {
-    const uint32_t self = 1u << j;
+    const uint32_t self = 1u << (j & 31);  // j < 32 in a SMALL packet (empty slots carry 63)
     own = am & self;
     const uint32_t nbr = am & ~self;
     deg = __popc(nbr);
@@ -866,7 +868,7 @@ __device__ __forceinline__ void slot_elem(const Ctx &c, int eoff, bool mid, int 
       }
     }
   }
-  const bool owner = valid && own != 0;
+  const bool owner = own != 0;  // empty slots have no adjacency bits
   double m, gap, dsel;
   int a;
   if constexpr (LMAX == 2) {
@@ -893,7 +895,7 @@ __device__ __forceinline__ void slot_elem(const Ctx &c, int eoff, bool mid, int 
       oa[idx] = a;
     }
     ocount += __popcll(ob);
-    cs.ties += __popcll(__ballot(owner && gap < c.tie_eps));
+    cs.ties += __popcll(ob & __ballot(gap < c.tie_eps));
   }
   if (valid) mb[eoff + lane] = m;
 }
