@@ -703,7 +703,7 @@ __device__ __forceinline__ int bcast(int v, int lane_src) { return __builtin_amd
 // list of kOwnCap entries (y - mu_a as double, a as int).
 constexpr int kOwnCap = 128;
 constexpr int kWaveLds = kGroupTiles * 64 + 64 + kOwnCap + kOwnCap / 2;  // in doubles
-static_assert(kGroupTiles * 64 + 64 + 3 <= kWaveLds, "neighbourhood sums read up to 3 minima past 64 members");
+static_assert(kGroupTiles * 64 + 64 + 7 <= kWaveLds, "neighbourhood sums read up to 7 minima past 64 members");
 static_assert(kGroupTiles * 64 >= 8 * 64, "record rows pass eight values through the minima buffer");
 
 template <int LMAX>
@@ -926,19 +926,19 @@ __device__ __forceinline__ void lean_hoods(const Ctx &c, int h0, int h1, int gst
         for (int w = 1; w <= kPreWindow; ++w)
           if (w <= c.W) prev[w - 1] = c.ring[(size_t)((c.t - w) % slots) * c.H + h];
     }
-    // four minima per step, requested together; a lane whose neighbourhood
+    // eight minima per step, requested together; a lane whose neighbourhood
     // has ended keeps its sum.  The reads past a neighbourhood stay inside the
-    // wave's LDS region: o < kGroupTiles * 64 and k + 3 < 64 + 3 (no
+    // wave's LDS region: o < kGroupTiles * 64 and k + 7 < 64 + 7 (no
     // neighbourhood on this path has more than 64 members).
     if (!act) o = 0;
     double S = 0.0;
-    for (int k = 0; __ballot(k < s); k += 4) {
-      double m4[4];
+    for (int k = 0; __ballot(k < s); k += 8) {
+      double m8[8];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) m4[i] = mb[o + k + i];
+      for (int i = 0; i < 8; ++i) m8[i] = mb[o + k + i];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const double S1 = S + m4[i];
+      for (int i = 0; i < 8; ++i) {
+        const double S1 = S + m8[i];
         S = k + i < s ? S1 : S;
       }
     }
