@@ -972,16 +972,15 @@ __device__ __forceinline__ int load_theta(const Ctx &c, Theta<LMAX> &th) {
 // Chunk on the slot layout.  The chunk's member ids and adjacency words are
 // requested from the chunk index alone, together with its header; then the
 // label and intensity gathers and the offsets and window values of the chunk's
-// first 64 neighbourhoods; then the
-// element passes, the owner list and the neighbourhood pass.  Returns false,
-// having written nothing, when the chunk has a LARGE packet or the window is
-// longer than kPreWindow (the packet-by-packet path takes those), and true
-// without writing when skip is set (the run has ended or is done) or, with
-// READ_DONE, when the run state's done flag is set (read here, after the
-// chunk's loads are requested).  th arrives with the chunk's loads (requested
-// before the kernel's first store).
+// first 64 neighbourhoods; then the element passes, the owner list and the
+// neighbourhood pass.  The slot kernel is given only superchunks without LARGE
+// packets and only windows of at most kPreWindow (the host sends the others to
+// the packet kernel).  Nothing is written when skip is set (the run has ended
+// or is done) or, with READ_DONE, when the run state's done flag is set (read
+// here, after the chunk's loads are requested).  th arrives with the chunk's
+// loads (requested before the kernel's first store).
 template <int LMAX, bool READ_DONE>
-__device__ bool chunk_slots(const Ctx &c, int ck, bool skip, const Theta<LMAX> &th, double *row, double *mb,
+__device__ void chunk_slots(const Ctx &c, int ck, bool skip, const Theta<LMAX> &th, double *row, double *mb,
                             double *od, int *oa, int lane) {
   const int tb = ck * kChunkTiles;
   const int nt = min(kChunkTiles, c.ntiles - tb);
@@ -1007,8 +1006,6 @@ __device__ bool chunk_slots(const Ctx &c, int ck, bool skip, const Theta<LMAX> &
                 kDwHend = offsetof(ChunkHdr, hood_end) / 4, kDwFlags = offsetof(ChunkHdr, flags) / 4,
                 kDwOff = offsetof(ChunkHdr, elem_off) / 4;
   const int flags = (int)hdr(kDwFlags);
-  if ((flags & kHdrLarge) || c.W > kPreWindow) return false;
-  if (skip || (READ_DONE && c.st->done != 0)) return true;
   const int gstart = (int)hdr(kDwElem), h0 = (int)hdr(kDwHood), hend = (int)hdr(kDwHend);
   int xv[kChunkTiles];
   double yv[kChunkTiles];
@@ -1037,6 +1034,9 @@ __device__ bool chunk_slots(const Ctx &c, int ck, bool skip, const Theta<LMAX> &
       }
     }
   }
+  // nothing is written once the run has ended or is done; the test comes
+  // after every load of the chunk is requested (the loads only read)
+  if (skip || (READ_DONE && c.st->done != 0)) return;
   ChunkStats<LMAX> cs;
   cs.clear();
   int ocount = 0;
@@ -1058,7 +1058,6 @@ __device__ bool chunk_slots(const Ctx &c, int ck, bool skip, const Theta<LMAX> &
   lean_hoods<LMAX>(c, h0, hend, gstart, pre, cs, mb, lane);
   wave_lds_sync();
   cs.store(row, mb, c.L, lane);  // the minima are no longer needed
-  return true;
 }
 
 // One statistics chunk: packets [ck * kChunkTiles, min(ntiles, (ck + 1) * kChunkTiles)).
