@@ -236,12 +236,16 @@ pmrf_status pmrf_get_launch(pmrf_launch *launch);
 
 /* ------------------------------------------------------------------------
  * Kernel timing for measurement.  Between pmrf_profile_begin and
- * pmrf_profile_end every EM-iteration launch (the energy / argmin / sum /
- * label / statistics kernel) made by this process is bracketed by a pair of
- * HIP events recorded on the launch's stream.  pmrf_profile_end waits for the
- * last recorded event and returns the summed event-to-event time in
- * milliseconds and the number of bracketed launches.  Timing does not change
- * any result.  Not thread safe: one measuring thread at a time.
+ * pmrf_profile_end the work kernels of every EM iteration made by this
+ * process (the energy / argmin / sum / label / statistics kernels: the slot
+ * kernel, and the packet kernel where a graph has one) carry a pair of HIP
+ * events on their stream, which the runtime stamps with the first kernel's
+ * dispatch begin and the last one's end (hipExtLaunchKernel).
+ * pmrf_profile_end waits for the last event and returns the summed
+ * begin-to-end time in milliseconds and the number of timed iterations
+ * (every iteration launches at least one block, also for an empty graph).
+ * Timing does not change any result.  Not thread safe: one measuring thread
+ * at a time.
  * ------------------------------------------------------------------------ */
 pmrf_status pmrf_profile_begin(void);
 pmrf_status pmrf_profile_end(double *total_ms, int64_t *launches);

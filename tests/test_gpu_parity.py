@@ -180,3 +180,27 @@ def test_convergence_window_lengths(W):
     prob = pmrf.Problem(g.n, g.row_ptr, g.col_idx, g.y, 2)
     gpu = gpu_run(prob, x0, mu0, s0, beta=0.5, max_iters=12, conv_window=W)
     compare_runs(gpu, ref, f"window{W}")
+
+
+def test_profile_events_time_each_iteration():
+    """Profiling mode stamps one event pair per EM iteration (around the slot
+    kernel, or the slot and packet kernels together) and changes no result;
+    an empty graph still runs one (empty) block per iteration, which is timed."""
+    cases = [(synth.workload_small(), 2, 9),
+             (synth.powerlaw_graph(99, 20000, phases=4, dmax=80, exponent=2.0), 4, 5)]
+    for g, L, iters in cases:
+        x0, mu0, s0 = init_state(g, L)
+        prob = pmrf.Problem(g.n, g.row_ptr, g.col_idx, g.y, L)
+        plain = gpu_run(prob, x0, mu0, s0, beta=0.5, max_iters=iters)
+        pmrf.pmrf_profile_begin()
+        timed = gpu_run(prob, x0, mu0, s0, beta=0.5, max_iters=iters)
+        ms, launches = pmrf.pmrf_profile_end()
+        assert launches == iters and ms > 0.0, (g.name, launches, ms)
+        for k in ("x", "mu", "sigma", "S", "trace", "near_ties", "nonconv"):
+            assert np.array_equal(timed[k], plain[k]), (g.name, k)
+    rp, ci = np.zeros(1, np.int32), np.zeros(0, np.int32)
+    prob = pmrf.Problem(0, rp, ci, np.zeros(0), 2)
+    pmrf.pmrf_profile_begin()
+    gpu_run(prob, np.zeros(0, np.int32), [50.0, 150.0], [20.0, 20.0], beta=0.5, max_iters=3)
+    ms, launches = pmrf.pmrf_profile_end()
+    assert launches == 3 and ms > 0.0
