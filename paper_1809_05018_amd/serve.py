@@ -16,6 +16,14 @@ and batching does not change any result).  The convergence bookkeeping
 (per-iteration non-converged counts, first converged iteration) restarts at
 each call and is reported per step.
 
+A request with ``early_exit`` stops as soon as every neighbourhood sum has
+converged (the window test of the EM loop): the device stops iterating that
+graph inside the batched call, the call reports fewer iterations than it was
+given, and the loop retires the request at once, freeing its memory for
+waiting requests.  Because the bookkeeping restarts at each call, the test can
+fire from the (W+1)-th iteration of a call on (W = 3), so ``iters_per_step``
+should be at least W + 1 for it to fire at all.
+
 The executor does the device work; ``GpuExecutor`` drives the HIP library.  A
 test executor with the same methods can stand in for it.
 """
@@ -40,6 +48,7 @@ class Request:
     iters: int
     arrival: float = 0.0  # seconds after the start of the run
     x0: np.ndarray | None = None  # starting labels (default: threshold labelling)
+    early_exit: bool = False  # stop (and retire) once the neighbourhood sums have converged
     # filled in by the server
     admitted: float | None = None
     finished: float | None = None
@@ -101,7 +110,8 @@ class GpuExecutor:
         for req, slot in active:
             prob = slot["prob"]
             todo = min(k, req.iters - req.done_iters)
-            params = pm.pmrf_em_params(L=req.L, beta=req.beta, max_iters=todo, init_from_labels=slot["first"])
+            params = pm.pmrf_em_params(L=req.L, beta=req.beta, max_iters=todo, init_from_labels=slot["first"],
+                                       early_exit=req.early_exit)
             it = prob.item(params)
             it.d_trace = prob.trace.data_ptr() + 8 * req.done_iters
             it.d_iter_stats = prob.iter_stats.data_ptr() + 16 * req.done_iters

@@ -32,3 +32,48 @@ def test_serving_mix_equals_solo():
                                                             init_from_labels=True))
         for k in ("x", "mu", "sigma", "S", "trace"):
             assert np.array_equal(np.asarray(r.result[k]), np.asarray(solo[k])), (r.rid, k)
+
+
+def solo_schedule(r, k):
+    """The request run alone in the calls the server makes: min(k, remaining)
+    iterations per call, early exit on, until a call stops early."""
+    prob = pmrf.Problem(r.n, r.row_ptr, r.col_idx, r.y, r.L)
+    prob.set_state(serve.threshold_start(r.y, r.L), np.zeros(r.L), np.ones(r.L))
+    done, first, trace = 0, True, []
+    while done < r.iters:
+        todo = min(k, r.iters - done)
+        params = pmrf.pmrf_em_params(L=r.L, beta=r.beta, max_iters=todo, init_from_labels=first, early_exit=True)
+        prob.run(params)
+        out = prob.results(params)
+        assert out["status"] == 0
+        trace += out["trace"][: out["iters"]].tolist()
+        done += out["iters"]
+        first = False
+        if out["iters"] < todo:
+            break
+    return done, out, np.array(trace)
+
+
+def test_serving_early_exit_retires_converged_requests():
+    rng = np.random.default_rng(23)
+    reqs = []
+    for j in range(10):
+        regions = int(np.exp(rng.uniform(np.log(300), np.log(8000))))
+        side = int(round(np.sqrt(26.2 * regions)))
+        g = synth.image_graph(900 + j, side, regions, 2)
+        early = j % 2 == 0
+        reqs.append(serve.Request(rid=j, n=g.n, row_ptr=g.row_ptr, col_idx=g.col_idx, y=g.y, L=2,
+                                  beta=0.0 if early else 0.5, iters=40 if early else 12,
+                                  arrival=0.002 * j, early_exit=early))
+    srv = serve.Server(serve.GpuExecutor("cuda"), hbm_budget=1 << 34, iters_per_step=6)
+    stats = srv.run(reqs)
+    assert stats.requests == len(reqs)
+    early = [r for r in reqs if r.early_exit]
+    assert any(r.done_iters < r.iters for r in early)
+    for r in early:
+        done, out, trace = solo_schedule(r, 6)
+        assert r.done_iters == done, (r.rid, r.done_iters, done)
+        for key in ("x", "mu", "sigma"):
+            assert np.array_equal(np.asarray(r.result[key]), np.asarray(out[key])), (r.rid, key)
+        assert np.array_equal(np.asarray(r.result["trace"]), trace), r.rid
+    assert all(r.done_iters == r.iters for r in reqs if not r.early_exit)

@@ -41,7 +41,7 @@ class OracleExecutor:
         for req, slot in active:
             todo = min(k, req.iters - req.done_iters)
             r = slot["og"].em_run(req.y, req.L, req.beta, slot["x"], slot["mu"], slot["sigma"], todo,
-                                  init_from_labels=slot["first"])
+                                  init_from_labels=slot["first"], early_exit=req.early_exit)
             slot.update(x=r["x"], mu=r["mu"], sigma=r["sigma"], first=False, S=r["S"])
             slot["trace"].extend(r["trace"].tolist())
             out.append(r["iters"])
@@ -96,3 +96,42 @@ def test_request_above_budget_is_refused():
     srv = serve.Server(ex, hbm_budget=100, clock=clock, sleep=clock.sleep)
     with pytest.raises(ValueError):
         srv.run(reqs)
+
+
+def schedule_reference(req, k):
+    """The oracle run in the calls the server makes for an early-exit request:
+    min(k, remaining) iterations per call until a call stops early."""
+    og = oracle.OracleGraph(req.n, req.row_ptr, req.col_idx)
+    x, mu, sigma = serve.threshold_start(req.y, req.L), np.zeros(req.L), np.ones(req.L)
+    done, first, trace = 0, True, []
+    while done < req.iters:
+        todo = min(k, req.iters - done)
+        r = og.em_run(req.y, req.L, req.beta, x, mu, sigma, todo, init_from_labels=first, early_exit=True)
+        x, mu, sigma, first = r["x"], r["mu"], r["sigma"], False
+        trace += r["trace"].tolist()
+        done += r["iters"]
+        if r["iters"] < todo:
+            break
+    return done, x, mu, sigma, np.array(trace)
+
+
+def test_early_exit_requests_retire_when_converged():
+    clock = VirtualClock()
+    ex = OracleExecutor(clock)
+    reqs = make_requests(count=8, seed=21)
+    for r in reqs[::2]:  # beta = 0 converges within a few iterations
+        r.beta, r.iters, r.early_exit = 0.0, 40, True
+    srv = serve.Server(ex, hbm_budget=10**12, iters_per_step=6, clock=clock, sleep=clock.sleep)
+    stats = srv.run(reqs)
+    assert stats.requests == len(reqs)
+    early = [r for r in reqs if r.early_exit]
+    assert any(r.done_iters < r.iters for r in early)  # some stopped before their budget
+    for r in early:
+        done, x, mu, sigma, trace = schedule_reference(r, 6)
+        assert r.done_iters == done
+        assert np.array_equal(r.result["x"], x)
+        assert np.array_equal(r.result["mu"], mu) and np.array_equal(r.result["sigma"], sigma)
+        assert np.array_equal(r.result["trace"], trace)
+    for r in reqs:
+        if not r.early_exit:
+            assert r.done_iters == r.iters
