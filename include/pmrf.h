@@ -250,6 +250,49 @@ pmrf_status pmrf_get_launch(pmrf_launch *launch);
 pmrf_status pmrf_profile_begin(void);
 pmrf_status pmrf_profile_end(double *total_ms, int64_t *launches);
 
+/* ------------------------------------------------------------------------
+ * Image in, segmentation out (the input and output of the paper's Alg. 2:
+ * an image with its oversegmentation in, a labelling of the pixels out; the
+ * optimisation in between takes the regions' graph, Sec. 5).
+ *
+ * pmrf_image_graph: the region adjacency graph and the region means of an
+ * oversegmented 8-bit image, on the device.  d_regions (int32, height x width,
+ * row-major) holds each pixel's region id in [0, n); d_pixels (uint8, same
+ * layout) the intensities.  Regions u != v are adjacent when a pixel of u and
+ * a pixel of v are horizontal or vertical neighbours (4-connectivity).
+ * Outputs: d_row_ptr (int32[n + 1]) and d_col_idx (int32[col_capacity]) the
+ * symmetric CSR with every row ascending (the form pmrf_build_neighborhoods
+ * takes, after a copy to the host), d_means (double[n]) the sum of a region's
+ * pixel values over its pixel count (0 for a region without pixels), *nnz
+ * (host) the number of adjacency entries.  d_ws: a device workspace of at
+ * least pmrf_image_graph_workspace_bytes(width, height, n) bytes.  The call
+ * waits for the stream twice (the sort sizes come back to the host) and
+ * returns with the outputs enqueued.  Errors: PMRF_EINVAL (NULL or negative
+ * argument, a region id outside [0, n): nothing written), PMRF_ENOMEM
+ * (workspace too small; col_capacity below the entry count, which is then in
+ * *nnz: nothing else written), PMRF_EUNSUPPORTED (more than 2^28 pixels),
+ * PMRF_EDEVICE.  Results are deterministic (integer sums, sorted edges).
+ *
+ * pmrf_labels_to_pixels: d_out[p] = d_labels[d_regions[p]] as uint8 for
+ * npixels pixels (255 where the id is outside [0, n) or the label outside
+ * [0, 255)); stream-ordered, nothing waited for.
+ *
+ * pmrf_confusion: d_counts[a * k + b] (int64[k * k], device) = number of
+ * pixels p with d_a[p] = a and d_b[p] = b, for a, b < k (pixels with a value
+ * >= k in either image are not counted); 1 <= k <= 16.  With a = the
+ * segmentation and b = the ground truth these are the TP, TN, FP and FN counts
+ * of the verification metrics (precision, recall, accuracy) and the void
+ * fraction of the porosity (Sec. 4.1.2).  Stream-ordered.
+ * ------------------------------------------------------------------------ */
+pmrf_status pmrf_image_graph_workspace_bytes(int32_t width, int32_t height, int32_t n, int64_t *bytes);
+pmrf_status pmrf_image_graph(const int32_t *d_regions, const uint8_t *d_pixels, int32_t width, int32_t height,
+                             int32_t n, int32_t *d_row_ptr, int32_t *d_col_idx, int64_t col_capacity,
+                             double *d_means, int64_t *nnz, void *d_ws, int64_t ws_bytes, void *hip_stream);
+pmrf_status pmrf_labels_to_pixels(const int32_t *d_regions, const int32_t *d_labels, int64_t npixels, int32_t n,
+                                  uint8_t *d_out, void *hip_stream);
+pmrf_status pmrf_confusion(const uint8_t *d_a, const uint8_t *d_b, int64_t npixels, int32_t k, int64_t *d_counts,
+                           void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

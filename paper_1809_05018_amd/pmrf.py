@@ -36,7 +36,8 @@ EXPORTED = (
     "pmrf_hoods_export", "pmrf_hoods_upload", "pmrf_replicate_indices", "pmrf_replicate_hood_array",
     "pmrf_hoods_free", "pmrf_em_params_default", "pmrf_em_workspace_bytes", "pmrf_em_run",
     "pmrf_em_batch_workspace_bytes", "pmrf_em_batch", "pmrf_set_launch", "pmrf_get_launch",
-    "pmrf_profile_begin", "pmrf_profile_end",
+    "pmrf_profile_begin", "pmrf_profile_end", "pmrf_image_graph_workspace_bytes", "pmrf_image_graph",
+    "pmrf_labels_to_pixels", "pmrf_confusion",
 )
 
 
@@ -94,6 +95,11 @@ def _load():
     lib.pmrf_get_launch.argtypes = [P(Launch)]
     lib.pmrf_profile_begin.argtypes = []
     lib.pmrf_profile_end.argtypes = [P(c_double), P(c_int64)]
+    lib.pmrf_image_graph_workspace_bytes.argtypes = [c_int32, c_int32, c_int32, P(c_int64)]
+    lib.pmrf_image_graph.argtypes = [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_int64,
+                                     c_void_p, P(c_int64), c_void_p, c_int64, c_void_p]
+    lib.pmrf_labels_to_pixels.argtypes = [c_void_p, c_void_p, c_int64, c_int32, c_void_p, c_void_p]
+    lib.pmrf_confusion.argtypes = [c_void_p, c_void_p, c_int64, c_int32, c_void_p, c_void_p]
     for name in EXPORTED:
         if name not in ("pmrf_last_error", "pmrf_abi_version", "pmrf_hoods_free", "pmrf_em_params_default"):
             getattr(lib, name).restype = c_int32
@@ -391,3 +397,81 @@ def solve(n, row_ptr, col_idx, y, x0, mu0, sigma0, params: EmParams, device="cud
     if out["status"] != 0:
         raise PmrfError(out["status"], "device-reported error")
     return out
+
+
+# ---------------------------------------------------------------- image in/out
+def pmrf_image_graph_workspace_bytes(width, height, n) -> int:
+    b = c_int64()
+    _check(lib.pmrf_image_graph_workspace_bytes(int(width), int(height), int(n), ctypes.byref(b)))
+    return b.value
+
+
+def image_graph(regions, pixels, n, ws=None, stream=None):
+    """Region adjacency graph and region means of an oversegmented image on the
+    device: ``regions`` (int32, height x width) and ``pixels`` (uint8, same
+    shape) are device tensors; returns device tensors (row_ptr int32[n+1],
+    col_idx int32[nnz], means float64[n])."""
+    import torch
+
+    height, width = (int(d) for d in regions.shape)
+    dev = regions.device
+    _ptr(regions, torch.int32, height * width, "regions")
+    _ptr(pixels, torch.uint8, height * width, "pixels")
+    if ws is None:
+        ws = torch.empty(pmrf_image_graph_workspace_bytes(width, height, n), dtype=torch.uint8, device=dev)
+    s = _stream(stream, dev)
+    row_ptr = torch.empty(n + 1, dtype=torch.int32, device=dev)
+    means = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
+    cap = max(12, 6 * n)  # a 4-connected region graph is planar: at most 3n - 6 edges
+    nnz = c_int64()
+    while True:
+        col = torch.empty(cap, dtype=torch.int32, device=dev)
+        code = lib.pmrf_image_graph(regions.data_ptr(), pixels.data_ptr(), width, height, int(n),
+                                    row_ptr.data_ptr(), col.data_ptr(), cap, means.data_ptr(), ctypes.byref(nnz),
+                                    ws.data_ptr(), ws.numel(), s)
+        if code == PMRF_ENOMEM and nnz.value > cap:
+            cap = nnz.value
+            continue
+        _check(code)
+        return row_ptr, col[: nnz.value], means[:n]
+
+
+def labels_to_pixels(regions, labels, n, stream=None):
+    """uint8 image of the labels of each pixel's region (device tensors)."""
+    import torch
+
+    _ptr(regions, torch.int32, regions.numel(), "regions")
+    _ptr(labels, torch.int32, n, "labels")
+    out = torch.empty(regions.shape, dtype=torch.uint8, device=regions.device)
+    _check(lib.pmrf_labels_to_pixels(regions.data_ptr(), labels.data_ptr(), regions.numel(), int(n),
+                                     out.data_ptr(), _stream(stream, regions.device)))
+    return out
+
+
+def confusion(a, b, k, stream=None):
+    """int64 (k, k) device tensor: counts[i, j] = pixels with a = i and b = j."""
+    import torch
+
+    _ptr(a, torch.uint8, a.numel(), "a")
+    _ptr(b, torch.uint8, a.numel(), "b")
+    counts = torch.empty((k, k), dtype=torch.int64, device=a.device)
+    _check(lib.pmrf_confusion(a.data_ptr(), b.data_ptr(), a.numel(), int(k), counts.data_ptr(),
+                              _stream(stream, a.device)))
+    return counts
+
+
+def segmentation_scores(counts, positive=1, void=0):
+    """The verification metrics of the paper (Sec. 4.1.2) from confusion
+    counts (rows: segmentation, columns: ground truth): precision, recall and
+    accuracy of the ``positive`` label, and the porosity of the segmentation
+    (share of pixels labelled ``void``)."""
+    c = np.asarray(counts, dtype=np.int64)
+    total = int(c.sum())
+    tp = int(c[positive, positive])
+    fp = int(c[positive].sum()) - tp
+    fn = int(c[:, positive].sum()) - tp
+    tn = total - tp - fp - fn
+    return {"precision": tp / (tp + fp) if tp + fp else float("nan"),
+            "recall": tp / (tp + fn) if tp + fn else float("nan"),
+            "accuracy": (tp + tn) / total if total else float("nan"),
+            "porosity": int(c[void].sum()) / total if total else float("nan")}

@@ -111,14 +111,22 @@ def csr_from_edges(n: int, a: np.ndarray, b: np.ndarray):
     return row_ptr.astype(np.int32), dst.astype(np.int32)
 
 
-def image_graph(seed: int, side: int, regions: int, phases: int = 2, name: str = "") -> GraphInput:
-    """Image slice -> oversegmentation -> RAG with region-mean intensities.
+def image_slice(seed: int, side: int, regions: int, phases: int = 2):
+    """The inputs of an image slice: the uint8 image, its oversegmentation
+    (int32 region id per pixel) and the generating phase per pixel.
 
     Draw order from ``default_rng(seed)``: smoothing noise (side^2 normals),
     pixel noise (side^2 normals), seed jitter (2 g^2 uniforms)."""
     rng = np.random.default_rng(seed)
     img, ph = two_phase_image(rng, side, phases)
     lab = jittered_voronoi(rng, side, regions)
+    return img, lab, ph
+
+
+def image_graph(seed: int, side: int, regions: int, phases: int = 2, name: str = "") -> GraphInput:
+    """Image slice -> oversegmentation -> RAG with region-mean intensities
+    (the draws of ``image_slice``)."""
+    img, lab, ph = image_slice(seed, side, regions, phases)
     row_ptr, col_idx = rag_csr(lab)
     n = row_ptr.size - 1
     cnt = np.bincount(lab.ravel(), minlength=n).astype(np.float64)
