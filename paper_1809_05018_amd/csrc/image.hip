@@ -29,6 +29,9 @@ namespace {
 
 constexpr int kImgThreads = 256;
 constexpr int kRunPixels = 16;  // pixels of one row per thread in the region sums
+constexpr int kWavePixels = 64 * 16;  // consecutive pixels per wave in the boundary passes
+
+int64_t boundary_waves(int64_t npix) { return std::max<int64_t>(1, (npix + kWavePixels - 1) / kWavePixels); }
 
 // Workspace of pmrf_image_graph, in 256-byte aligned pieces.
 struct ImgPlan {
@@ -36,6 +39,7 @@ struct ImgPlan {
   size_t keys_a = 0, keys_b = 0;       // uint64[2 * pairs] each
   size_t sums = 0, counts = 0;         // int64[n] each
   size_t scalars = 0;                  // int64[4]: pair count, unique count, bad ids, spare
+  size_t wcount = 0, woff = 0;         // uint32[boundary waves] each: pairs per wave, their offsets
   size_t temp = 0, temp_bytes = 0;     // hipCUB scratch
   size_t total = 0;
 };
@@ -57,61 +61,102 @@ ImgPlan plan_image(int64_t width, int64_t height, int64_t n) {
   off = align256(off + (size_t)std::max<int64_t>(1, n) * 8);
   p.scalars = off;
   off = align256(off + 4 * 8);
-  size_t sort_bytes = 0, uniq_bytes = 0;
+  const int64_t waves = boundary_waves(width * height);
+  p.wcount = off;
+  off = align256(off + (size_t)waves * 4);
+  p.woff = off;
+  off = align256(off + (size_t)waves * 4);
+  size_t sort_bytes = 0, uniq_bytes = 0, scan_bytes = 0;
+  (void)hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, (const uint32_t *)nullptr, (uint32_t *)nullptr,
+                                         (int)waves);
   (void)hipcub::DeviceRadixSort::SortKeys(nullptr, sort_bytes, (const uint64_t *)nullptr, (uint64_t *)nullptr, (int)keys);
   (void)hipcub::DeviceSelect::Unique(nullptr, uniq_bytes, (const uint64_t *)nullptr, (uint64_t *)nullptr,
                                (int64_t *)nullptr, (int)keys);
   p.temp = off;
-  p.temp_bytes = std::max<size_t>(256, std::max(sort_bytes, uniq_bytes));
+  p.temp_bytes = std::max<size_t>(256, std::max(scan_bytes, std::max(sort_bytes, uniq_bytes)));
   off = align256(off + p.temp_bytes);
   p.total = off;
   return p;
 }
 
-// Boundary pairs: pixel (r, c) against its right and lower neighbours; a pair
-// of different regions becomes the key (min << 32) | max.  Slots are taken
-// with one atomic per wave (ballot + rank), so the list is complete but in no
-// particular order (it is sorted next).  Ids outside [0, n) are counted.
-__global__ __launch_bounds__(kImgThreads) void k_boundary(const int32_t *__restrict__ reg, int32_t width,
-                                                           int32_t height, int32_t n, uint64_t *__restrict__ keys,
-                                                           unsigned long long *__restrict__ scal) {
+// Boundary pairs: pixel (r, c) against its right and lower neighbour; a pair
+// of different regions becomes the key (min << 32) | max.  Two passes over
+// the same pixels: wave w takes pixels [w * kWavePixels, (w + 1) *
+// kWavePixels), 64 at a time; the first pass counts its pairs, an exclusive
+// scan turns the counts into offsets, the second pass writes the keys there in
+// pixel order (right before down within each 64 pixels), ranks from ballots.
+// Ids outside [0, n) are counted by the first pass.
+struct PixelPairs {
+  bool right, down, bad;
+  uint64_t kr, kd;
+};
+
+__device__ __forceinline__ PixelPairs pixel_pairs(const int32_t *__restrict__ reg, int64_t p, int64_t npix,
+                                                  int32_t width, int32_t height, int32_t n) {
+  PixelPairs q{false, false, false, 0, 0};
+  if (p < npix) {
+    const int32_t r = (int32_t)(p / width), c = (int32_t)(p - (int64_t)r * width);
+    const int32_t u = reg[p];
+    q.bad = u < 0 || u >= n;
+    if (c + 1 < width) {
+      const int32_t v = reg[p + 1];
+      q.bad |= v < 0 || v >= n;
+      q.right = u != v;
+      q.kr = ((uint64_t)(uint32_t)min(u, v) << 32) | (uint32_t)max(u, v);
+    }
+    if (r + 1 < height) {
+      const int32_t v = reg[p + width];
+      q.bad |= v < 0 || v >= n;
+      q.down = u != v;
+      q.kd = ((uint64_t)(uint32_t)min(u, v) << 32) | (uint32_t)max(u, v);
+    }
+  }
+  return q;
+}
+
+__global__ __launch_bounds__(kImgThreads) void k_boundary_count(const int32_t *__restrict__ reg, int32_t width,
+                                                                 int32_t height, int32_t n, int64_t waves,
+                                                                 uint32_t *__restrict__ wcount,
+                                                                 unsigned long long *__restrict__ scal) {
   const int64_t npix = (int64_t)width * height;
   const int lane = threadIdx.x & 63;
-  for (int64_t p0 = (int64_t)blockIdx.x * blockDim.x; p0 < npix; p0 += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t p = p0 + threadIdx.x;
-    bool right = false, down = false, bad = false;
-    uint64_t kr = 0, kd = 0;
-    if (p < npix) {
-      const int32_t r = (int32_t)(p / width), c = (int32_t)(p - (int64_t)r * width);
-      const int32_t u = reg[p];
-      bad = u < 0 || u >= n;
-      if (c + 1 < width) {
-        const int32_t v = reg[p + 1];
-        bad |= v < 0 || v >= n;
-        right = u != v;
-        kr = ((uint64_t)(uint32_t)min(u, v) << 32) | (uint32_t)max(u, v);
-      }
-      if (r + 1 < height) {
-        const int32_t v = reg[p + width];
-        bad |= v < 0 || v >= n;
-        down = u != v;
-        kd = ((uint64_t)(uint32_t)min(u, v) << 32) | (uint32_t)max(u, v);
-      }
-    }
-    const uint64_t br = __ballot(right), bd = __ballot(down), bb = __ballot(bad);
-    const int cnt = __popcll(br) + __popcll(bd);
-    unsigned long long base = 0;
-    if (lane == 0) {
-      if (cnt) base = atomicAdd(&scal[0], (unsigned long long)cnt);
-      if (bb) atomicAdd(&scal[2], (unsigned long long)__popcll(bb));
-    }
-    base = __shfl(base, 0);
-    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const int rank_r = __popcll(br & below);
-    const int rank_d = __popcll(br) + __popcll(bd & below);
-    if (right) keys[base + rank_r] = kr;
-    if (down) keys[base + rank_d] = kd;
+  const int64_t w = (int64_t)blockIdx.x * (kImgThreads / 64) + (threadIdx.x >> 6);
+  if (w >= waves) return;
+  uint32_t cnt = 0, bad = 0;
+  for (int i = 0; i < kWavePixels / 64; ++i) {
+    const PixelPairs q = pixel_pairs(reg, w * kWavePixels + i * 64 + lane, npix, width, height, n);
+    cnt += (uint32_t)(__popcll(__ballot(q.right)) + __popcll(__ballot(q.down)));
+    bad += (uint32_t)__popcll(__ballot(q.bad));
   }
+  if (lane == 0) {
+    wcount[w] = cnt;
+    if (bad) atomicAdd(&scal[2], (unsigned long long)bad);
+  }
+}
+
+__global__ __launch_bounds__(kImgThreads) void k_boundary_emit(const int32_t *__restrict__ reg, int32_t width,
+                                                                int32_t height, int32_t n, int64_t waves,
+                                                                const uint32_t *__restrict__ woff,
+                                                                uint64_t *__restrict__ keys) {
+  const int64_t npix = (int64_t)width * height;
+  const int lane = threadIdx.x & 63;
+  const int64_t w = (int64_t)blockIdx.x * (kImgThreads / 64) + (threadIdx.x >> 6);
+  if (w >= waves) return;
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  uint64_t base = woff[w];
+  for (int i = 0; i < kWavePixels / 64; ++i) {
+    const PixelPairs q = pixel_pairs(reg, w * kWavePixels + i * 64 + lane, npix, width, height, n);
+    const uint64_t br = __ballot(q.right), bd = __ballot(q.down);
+    if (q.right) keys[base + __popcll(br & below)] = q.kr;
+    if (q.down) keys[base + __popcll(br) + __popcll(bd & below)] = q.kd;
+    base += __popcll(br) + __popcll(bd);
+  }
+}
+
+// Total pair count from the last wave's offset and count.
+__global__ void k_pair_total(const uint32_t *__restrict__ wcount, const uint32_t *__restrict__ woff, int64_t waves,
+                             unsigned long long *__restrict__ scal) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) scal[0] = (unsigned long long)woff[waves - 1] + wcount[waves - 1];
 }
 
 // Directed edges: unique pair i = (a, b) gives (a, b) and (b, a).
@@ -150,7 +195,7 @@ __global__ __launch_bounds__(kImgThreads) void k_zero64(long long *__restrict__ 
 // Pixel sums and counts per region: a thread walks kRunPixels pixels of one
 // row and adds each run of equal ids with one integer atomic (integer sums,
 // so the totals do not depend on the order of the atomics).  Ids outside
-// [0, n) are skipped (k_boundary has counted them).
+// [0, n) are skipped (k_boundary_count has counted them).
 __global__ __launch_bounds__(kImgThreads) void k_region_sums(const int32_t *__restrict__ reg,
                                                               const uint8_t *__restrict__ pix, int32_t width,
                                                               int32_t height, int32_t n,
@@ -265,9 +310,20 @@ extern "C" pmrf_status pmrf_image_graph(const int32_t *d_regions, const uint8_t 
   IMG_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_zero64, dim3(1), dim3(kImgThreads), 0, s, (long long *)scal, (int64_t)4);
   IMG_TRY(hipGetLastError());
+  const int64_t waves = boundary_waves(npix);
+  uint32_t *wcount = (uint32_t *)(ws + plan.wcount), *woff = (uint32_t *)(ws + plan.woff);
   if (npix > 0) {
-    hipLaunchKernelGGL(k_boundary, dim3(grid_for(npix)), dim3(kImgThreads), 0, s, d_regions, width, height, n, ka,
-                       scal);
+    const int blocks = (int)((waves + kImgThreads / 64 - 1) / (kImgThreads / 64));
+    hipLaunchKernelGGL(k_boundary_count, dim3(blocks), dim3(kImgThreads), 0, s, d_regions, width, height, n, waves,
+                       wcount, scal);
+    IMG_TRY(hipGetLastError());
+    size_t tb = plan.temp_bytes;
+    IMG_TRY(hipcub::DeviceScan::ExclusiveSum(temp, tb, (const uint32_t *)wcount, woff, (int)waves, s));
+    hipLaunchKernelGGL(k_pair_total, dim3(1), dim3(64), 0, s, (const uint32_t *)wcount, (const uint32_t *)woff,
+                       waves, scal);
+    IMG_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_boundary_emit, dim3(blocks), dim3(kImgThreads), 0, s, d_regions, width, height, n, waves,
+                       (const uint32_t *)woff, ka);
     IMG_TRY(hipGetLastError());
   }
   unsigned long long host_scal[4] = {0, 0, 0, 0};
