@@ -33,6 +33,14 @@ constexpr int kWavePixels = 64 * 16;  // consecutive pixels per wave in the boun
 
 int64_t boundary_waves(int64_t npix) { return std::max<int64_t>(1, (npix + kWavePixels - 1) / kWavePixels); }
 
+// Keys pack a pair of region ids as (first << B) | second with B the bit width
+// of n - 1 (at least 1), so the sorts look at 2B bits only.
+int id_bits(int64_t n) {
+  int b = 1;
+  while (b < 31 && ((int64_t)1 << b) < n) ++b;
+  return b;
+}
+
 // Workspace of pmrf_image_graph, in 256-byte aligned pieces.
 struct ImgPlan {
   int64_t pairs = 0;                   // upper bound on boundary pixel pairs
@@ -80,7 +88,7 @@ ImgPlan plan_image(int64_t width, int64_t height, int64_t n) {
 }
 
 // Boundary pairs: pixel (r, c) against its right and lower neighbour; a pair
-// of different regions becomes the key (min << 32) | max.  Two passes over
+// of different regions becomes the key (min << B) | max.  Two passes over
 // the same pixels: wave w takes pixels [w * kWavePixels, (w + 1) *
 // kWavePixels), 64 at a time; the first pass counts its pairs, an exclusive
 // scan turns the counts into offsets, the second pass writes the keys there in
@@ -92,7 +100,7 @@ struct PixelPairs {
 };
 
 __device__ __forceinline__ PixelPairs pixel_pairs(const int32_t *__restrict__ reg, int64_t p, int64_t npix,
-                                                  int32_t width, int32_t height, int32_t n) {
+                                                  int32_t width, int32_t height, int32_t n, int B) {
   PixelPairs q{false, false, false, 0, 0};
   if (p < npix) {
     const int32_t r = (int32_t)(p / width), c = (int32_t)(p - (int64_t)r * width);
@@ -102,20 +110,20 @@ __device__ __forceinline__ PixelPairs pixel_pairs(const int32_t *__restrict__ re
       const int32_t v = reg[p + 1];
       q.bad |= v < 0 || v >= n;
       q.right = u != v;
-      q.kr = ((uint64_t)(uint32_t)min(u, v) << 32) | (uint32_t)max(u, v);
+      q.kr = ((uint64_t)(uint32_t)min(u, v) << B) | (uint32_t)max(u, v);
     }
     if (r + 1 < height) {
       const int32_t v = reg[p + width];
       q.bad |= v < 0 || v >= n;
       q.down = u != v;
-      q.kd = ((uint64_t)(uint32_t)min(u, v) << 32) | (uint32_t)max(u, v);
+      q.kd = ((uint64_t)(uint32_t)min(u, v) << B) | (uint32_t)max(u, v);
     }
   }
   return q;
 }
 
 __global__ __launch_bounds__(kImgThreads) void k_boundary_count(const int32_t *__restrict__ reg, int32_t width,
-                                                                 int32_t height, int32_t n, int64_t waves,
+                                                                 int32_t height, int32_t n, int B, int64_t waves,
                                                                  uint32_t *__restrict__ wcount,
                                                                  unsigned long long *__restrict__ scal) {
   const int64_t npix = (int64_t)width * height;
@@ -124,7 +132,7 @@ __global__ __launch_bounds__(kImgThreads) void k_boundary_count(const int32_t *_
   if (w >= waves) return;
   uint32_t cnt = 0, bad = 0;
   for (int i = 0; i < kWavePixels / 64; ++i) {
-    const PixelPairs q = pixel_pairs(reg, w * kWavePixels + i * 64 + lane, npix, width, height, n);
+    const PixelPairs q = pixel_pairs(reg, w * kWavePixels + i * 64 + lane, npix, width, height, n, B);
     cnt += (uint32_t)(__popcll(__ballot(q.right)) + __popcll(__ballot(q.down)));
     bad += (uint32_t)__popcll(__ballot(q.bad));
   }
@@ -135,7 +143,7 @@ __global__ __launch_bounds__(kImgThreads) void k_boundary_count(const int32_t *_
 }
 
 __global__ __launch_bounds__(kImgThreads) void k_boundary_emit(const int32_t *__restrict__ reg, int32_t width,
-                                                                int32_t height, int32_t n, int64_t waves,
+                                                                int32_t height, int32_t n, int B, int64_t waves,
                                                                 const uint32_t *__restrict__ woff,
                                                                 uint64_t *__restrict__ keys) {
   const int64_t npix = (int64_t)width * height;
@@ -145,7 +153,7 @@ __global__ __launch_bounds__(kImgThreads) void k_boundary_emit(const int32_t *__
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   uint64_t base = woff[w];
   for (int i = 0; i < kWavePixels / 64; ++i) {
-    const PixelPairs q = pixel_pairs(reg, w * kWavePixels + i * 64 + lane, npix, width, height, n);
+    const PixelPairs q = pixel_pairs(reg, w * kWavePixels + i * 64 + lane, npix, width, height, n, B);
     const uint64_t br = __ballot(q.right), bd = __ballot(q.down);
     if (q.right) keys[base + __popcll(br & below)] = q.kr;
     if (q.down) keys[base + __popcll(br) + __popcll(bd & below)] = q.kd;
@@ -160,27 +168,29 @@ __global__ void k_pair_total(const uint32_t *__restrict__ wcount, const uint32_t
 }
 
 // Directed edges: unique pair i = (a, b) gives (a, b) and (b, a).
-__global__ __launch_bounds__(kImgThreads) void k_expand(const uint64_t *__restrict__ uniq, int64_t m,
+__global__ __launch_bounds__(kImgThreads) void k_expand(const uint64_t *__restrict__ uniq, int64_t m, int B,
                                                          uint64_t *__restrict__ out) {
+  const uint64_t low = ((uint64_t)1 << B) - 1;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
     const uint64_t k = uniq[i];
     out[2 * i] = k;
-    out[2 * i + 1] = (k << 32) | (k >> 32);
+    out[2 * i + 1] = ((k & low) << B) | (k >> B);
   }
 }
 
 // CSR from the sorted directed edges: row_ptr[r] = first edge whose row is
-// >= r (binary search), col_idx = the low halves in order.
-__global__ __launch_bounds__(kImgThreads) void k_csr(const uint64_t *__restrict__ e, int64_t nnz, int32_t n,
+// >= r (binary search), col_idx = the low B bits in order.
+__global__ __launch_bounds__(kImgThreads) void k_csr(const uint64_t *__restrict__ e, int64_t nnz, int32_t n, int B,
                                                       int32_t *__restrict__ row_ptr, int32_t *__restrict__ col_idx) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const uint64_t low = ((uint64_t)1 << B) - 1;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nnz; i += stride)
-    col_idx[i] = (int32_t)(uint32_t)(e[i] & 0xffffffffull);
+    col_idx[i] = (int32_t)(uint32_t)(e[i] & low);
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r <= n; r += stride) {
     int64_t lo = 0, hi = nnz;
     while (lo < hi) {
       const int64_t mid = (lo + hi) >> 1;
-      if ((int64_t)(e[mid] >> 32) < r) lo = mid + 1;
+      if ((int64_t)(e[mid] >> B) < r) lo = mid + 1;
       else hi = mid;
     }
     row_ptr[r] = (int32_t)lo;
@@ -311,19 +321,20 @@ extern "C" pmrf_status pmrf_image_graph(const int32_t *d_regions, const uint8_t 
   hipLaunchKernelGGL(k_zero64, dim3(1), dim3(kImgThreads), 0, s, (long long *)scal, (int64_t)4);
   IMG_TRY(hipGetLastError());
   const int64_t waves = boundary_waves(npix);
+  const int B = id_bits(n);
   uint32_t *wcount = (uint32_t *)(ws + plan.wcount), *woff = (uint32_t *)(ws + plan.woff);
   if (npix > 0) {
     const int blocks = (int)((waves + kImgThreads / 64 - 1) / (kImgThreads / 64));
-    hipLaunchKernelGGL(k_boundary_count, dim3(blocks), dim3(kImgThreads), 0, s, d_regions, width, height, n, waves,
-                       wcount, scal);
+    hipLaunchKernelGGL(k_boundary_count, dim3(blocks), dim3(kImgThreads), 0, s, d_regions, width, height, n, B,
+                       waves, wcount, scal);
     IMG_TRY(hipGetLastError());
     size_t tb = plan.temp_bytes;
     IMG_TRY(hipcub::DeviceScan::ExclusiveSum(temp, tb, (const uint32_t *)wcount, woff, (int)waves, s));
     hipLaunchKernelGGL(k_pair_total, dim3(1), dim3(64), 0, s, (const uint32_t *)wcount, (const uint32_t *)woff,
                        waves, scal);
     IMG_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_boundary_emit, dim3(blocks), dim3(kImgThreads), 0, s, d_regions, width, height, n, waves,
-                       (const uint32_t *)woff, ka);
+    hipLaunchKernelGGL(k_boundary_emit, dim3(blocks), dim3(kImgThreads), 0, s, d_regions, width, height, n, B,
+                       waves, (const uint32_t *)woff, ka);
     IMG_TRY(hipGetLastError());
   }
   unsigned long long host_scal[4] = {0, 0, 0, 0};
@@ -334,7 +345,7 @@ extern "C" pmrf_status pmrf_image_graph(const int32_t *d_regions, const uint8_t 
   int64_t m = 0;  // unique undirected pairs
   if (pairs > 0) {
     size_t tb = plan.temp_bytes;
-    IMG_TRY(hipcub::DeviceRadixSort::SortKeys(temp, tb, (const uint64_t *)ka, kb, (int)pairs, 0, 64, s));
+    IMG_TRY(hipcub::DeviceRadixSort::SortKeys(temp, tb, (const uint64_t *)ka, kb, (int)pairs, 0, 2 * B, s));
     tb = plan.temp_bytes;
     IMG_TRY(hipcub::DeviceSelect::Unique(temp, tb, (const uint64_t *)kb, ka, (int64_t *)(scal + 1), (int)pairs, s));
     IMG_TRY(hipMemcpyAsync(host_scal, scal, sizeof(host_scal), hipMemcpyDeviceToHost, s));
@@ -348,13 +359,13 @@ extern "C" pmrf_status pmrf_image_graph(const int32_t *d_regions, const uint8_t 
   }
   if (edges > 0 && !d_col_idx) return fail(PMRF_EINVAL, "NULL col_idx");
   if (m > 0) {
-    hipLaunchKernelGGL(k_expand, dim3(grid_for(m)), dim3(kImgThreads), 0, s, (const uint64_t *)ka, m, kb);
+    hipLaunchKernelGGL(k_expand, dim3(grid_for(m)), dim3(kImgThreads), 0, s, (const uint64_t *)ka, m, B, kb);
     IMG_TRY(hipGetLastError());
     size_t tb = plan.temp_bytes;
-    IMG_TRY(hipcub::DeviceRadixSort::SortKeys(temp, tb, (const uint64_t *)kb, ka, (int)edges, 0, 64, s));
+    IMG_TRY(hipcub::DeviceRadixSort::SortKeys(temp, tb, (const uint64_t *)kb, ka, (int)edges, 0, 2 * B, s));
   }
   hipLaunchKernelGGL(k_csr, dim3(grid_for(std::max<int64_t>(edges, (int64_t)n + 1))), dim3(kImgThreads), 0, s,
-                     (const uint64_t *)ka, edges, n, d_row_ptr, d_col_idx);
+                     (const uint64_t *)ka, edges, n, B, d_row_ptr, d_col_idx);
   IMG_TRY(hipGetLastError());
   if (npix > 0) {
     const int64_t runs = (int64_t)height * ((width + kRunPixels - 1) / kRunPixels);
