@@ -1138,6 +1138,14 @@ __global__ void k_setup(const GraphDev *graphs, int B) {
   for (int l = 0; l < G.L; ++l) set_label_theta(st->th[0], l, st->th[0][l].mu, st->th[0][l].sigma);
 }
 
+// Graph of every slot-kernel block, written once per run (batches only):
+// blocks [block0, block0 + nblocks) of graph g map to g, so a block finds its
+// descriptor with one load instead of a search over the graphs.
+__global__ void k_block_graph(const GraphDev *graphs, int32_t *table) {
+  const GraphDev &G = graphs[blockIdx.x];
+  for (int i = threadIdx.x; i < G.nblocks; i += blockDim.x) table[G.block0 + i] = (int32_t)blockIdx.x;
+}
+
 // Parameter update from the starting labels (used when init_from_labels is
 // set): pass 0 sums y per label (mean), pass 1 sums (y - mean) and (y - mean)^2.
 // Block b covers vertices [b*1024, b*1024 + 1024), thread t the vertices
@@ -1363,7 +1371,8 @@ __device__ __forceinline__ void iter_superchunk(const GraphDev &G, int b, int t,
 // graphs[0 .. B).
 template <int LMAX, bool PERSIST, bool SINGLE>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(LMAX <= 2 ? (SINGLE ? PMRF_ITER_WAVES_PER_EU : PMRF_BATCH_WAVES_PER_EU) : 1, 8))) void k_iter(
-    const GraphDev *__restrict__ graphs, const GraphDev g1, int B, int nsuper_total, int t) {
+    const GraphDev *__restrict__ graphs, const int32_t *__restrict__ block_graph, const GraphDev g1, int B,
+    int nsuper_total, int t) {
   extern __shared__ double smem[];
   __shared__ double part[kSuperChunks][rec_words(LMAX)];
   const int nw = blockDim.x >> 6, wave = wave_id(), lane = threadIdx.x & 63;
@@ -1376,7 +1385,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(LMAX <= 2 
     if constexpr (SINGLE) {
       iter_superchunk<LMAX, false, true>(g1, blk, t, part, mb, pl, od, oa, nw, wave, lane);
     } else {
-      const GraphDev &G = graphs[find_graph(graphs, B, blk, kGridSlot)];
+      const GraphDev &G = graphs[block_graph[blk]];
       iter_superchunk<LMAX, false>(G, blk - G.block0, t, part, mb, pl, od, oa, nw, wave, lane);
     }
   } else {
@@ -1384,7 +1393,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(LMAX <= 2 
       if constexpr (SINGLE) {
         iter_superchunk<LMAX, false, true>(g1, sc, t, part, mb, pl, od, oa, nw, wave, lane);
       } else {
-        const GraphDev &G = graphs[find_graph(graphs, B, sc, kGridSlot)];
+        const GraphDev &G = graphs[block_graph[sc]];
         iter_superchunk<LMAX, false>(G, sc - G.block0, t, part, mb, pl, od, oa, nw, wave, lane);
       }
       __syncthreads();  // part[] is reused by the next superchunk
@@ -1509,6 +1518,7 @@ hipStream_t capture_stream(int dev) {
 
 struct WsPlan {
   int64_t desc_off = 0;
+  int64_t block_graph_off = 0, slot_blocks = 0;  // int32 graph of every slot-kernel block
   std::vector<int64_t> state_off, x1_off, ring_off, thist_off, rec_off;
   int64_t total = 0;
 };
@@ -1543,11 +1553,24 @@ int64_t vert_blocks(const pmrf_hoods *h) { return std::max<int64_t>(1, ((int64_t
 int64_t n_super(const pmrf_hoods *h) { return std::max<int64_t>(1, (n_chunks(h) + kSuperChunks - 1) / kSuperChunks); }
 int64_t max_records(const pmrf_hoods *h) { return std::max<int64_t>(n_super(h), vert_blocks(h)); }
 
+// Superchunks of a graph that take the slot kernel: those before the first
+// LARGE packet (all of them when there is none), none when the window is
+// longer than kPreWindow; the rest take the packet kernel.
+int32_t slot_supers(const pmrf_hoods *h, const pmrf_em_params &params) {
+  const int64_t per_super = (int64_t)kChunkTiles * kSuperChunks;
+  int32_t nslot = h->slot_tiles == (int64_t)h->tiles.size() ? (int32_t)n_super(h) : (int32_t)(h->slot_tiles / per_super);
+  if (params.conv_window > kPreWindow) nslot = 0;
+  return nslot;
+}
+
 WsPlan plan_workspace(int B, const pmrf_em_item *items) {
   WsPlan p;
   int64_t off = 0;
   p.desc_off = off;
   off += align_up((int64_t)B * (int64_t)sizeof(GraphDev), 256);
+  for (int i = 0; i < B; ++i) p.slot_blocks += slot_supers(items[i].hoods, items[i].params);
+  p.block_graph_off = off;
+  off += align_up(std::max<int64_t>(1, p.slot_blocks) * 4, 256);
   for (int i = 0; i < B; ++i) {
     const pmrf_hoods *h = items[i].hoods;
     p.state_off.push_back(off);
@@ -1629,11 +1652,7 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
     G.block0 = blocks_iter;
     G.nchunks = (int32_t)n_chunks(h);
     G.nsuper = (int32_t)n_super(h);
-    // superchunks before the first LARGE packet take the slot kernel, the rest
-    // the packet kernel (all of them when the window is longer than kPreWindow)
-    const int64_t per_super = (int64_t)kChunkTiles * kSuperChunks;
-    int32_t nslot = h->slot_tiles == (int64_t)h->tiles.size() ? G.nsuper : (int32_t)(h->slot_tiles / per_super);
-    if (it.params.conv_window > kPreWindow) nslot = 0;
+    const int32_t nslot = slot_supers(h, it.params);
     G.nblocks = nslot;
     blocks_iter += G.nblocks;
     G.pblock0 = blocks_pk;
@@ -1647,6 +1666,8 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
     Lmax = std::max(Lmax, G.L);
   }
   GraphDev *d_desc = reinterpret_cast<GraphDev *>(ws + plan.desc_off);
+  int32_t *block_graph = reinterpret_cast<int32_t *>(ws + plan.block_graph_off);
+  if (blocks_iter != plan.slot_blocks) return fail(PMRF_EDEVICE, "internal: slot block count differs from the plan");
   bool any_init = false;
   for (int i = 0; i < B; ++i) any_init |= desc[i].init_from_labels != 0;
   const int lm = lmax_for(Lmax);
@@ -1677,6 +1698,10 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
     const GraphDev *gd = d_desc;
     hipLaunchKernelGGL(k_setup, dim3((B + 63) / 64), dim3(64), 0, s, gd, B);
     HIP_TRY(hipGetLastError());
+    if (B > 1 && blocks_iter > 0) {
+      hipLaunchKernelGGL(k_block_graph, dim3(B), dim3(256), 0, s, gd, block_graph);
+      HIP_TRY(hipGetLastError());
+    }
     if (any_init) {
       for (int pass = 0; pass < 2; ++pass) {
         hipLaunchKernelGGL(k_mstep_init, dim3(blocks_vert), dim3(256), 0, s, gd, B, pass);
@@ -1707,16 +1732,16 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
 #define PMRF_LAUNCH_ITER(LM)                                                                                  \
   do {                                                                                                        \
     if (persist && B == 1)                                                                                    \
-      PMRF_LAUNCH((k_iter<LM, true, true>), dim3(grid_iter), slot_start, slot_stop, gd, desc[0], B,           \
+      PMRF_LAUNCH((k_iter<LM, true, true>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, desc[0], B,           \
                   blocks_iter, t);                                                                            \
     else if (persist)                                                                                         \
-      PMRF_LAUNCH((k_iter<LM, true, false>), dim3(grid_iter), slot_start, slot_stop, gd, desc[0], B,          \
+      PMRF_LAUNCH((k_iter<LM, true, false>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, desc[0], B,          \
                   blocks_iter, t);                                                                            \
     else if (B == 1)                                                                                          \
-      PMRF_LAUNCH((k_iter<LM, false, true>), dim3(grid_iter), slot_start, slot_stop, gd, desc[0], B,          \
+      PMRF_LAUNCH((k_iter<LM, false, true>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, desc[0], B,          \
                   blocks_iter, t);                                                                            \
     else                                                                                                      \
-      PMRF_LAUNCH((k_iter<LM, false, false>), dim3(grid_iter), slot_start, slot_stop, gd, desc[0], B,         \
+      PMRF_LAUNCH((k_iter<LM, false, false>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, desc[0], B,         \
                   blocks_iter, t);                                                                            \
   } while (0)
 #define PMRF_LAUNCH_PK(LM) PMRF_LAUNCH(k_iter_packets<LM>, dim3(blocks_pk), pk_start, pk_stop, gd, B, t)
