@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 METRIC = "vertex-label energy evals/sec + HBM GB/s % peak; batched vs plain at bit-exact labels"
 HBM_PEAK_GBS = 8000.0
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_iter_slice2048_100k_traffic.md")
+BATCH_COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_iter_batch64_traffic.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_1809_05018_amd", "csrc", "em.hip")
 
 
@@ -51,12 +52,13 @@ def kernel_sha() -> str:
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch (read + written) from the committed counter summary,
-    if it was taken on the current kernel source; else None.  The summary holds
-    one line ``traffic: {json}`` with ``kernel_sha`` and ``bytes_per_launch``."""
+def measured_traffic(path=None):
+    """HBM bytes per launch (read + written) from a committed counter summary
+    (default: the single-slice one), if it was taken on the current kernel
+    source; else None.  The summary holds one line ``traffic: {json}`` with
+    ``kernel_sha`` and ``bytes_per_launch``."""
     try:
-        lines = open(COUNTERS_FILE).read().splitlines()
+        lines = open(path or COUNTERS_FILE).read().splitlines()
     except OSError:
         return None
     for line in lines:
@@ -329,7 +331,9 @@ def bench_batched(args, dev):
            "launch_shape": {"plain": list(shape_plain), "batched": list(shape_batch),
                             "fields": "mode, waves_per_block, tiles_per_wave, blocks_per_cu"},
            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": f"k_iter<{4 if L > 2 else 2}>",
+                        "frac": achieved / HBM_PEAK_GBS,
+                        "traffic": measured_traffic(BATCH_COUNTERS_FILE) if args.workload == "batch64" else None,
+                        "kernel": f"k_iter<{4 if L > 2 else 2}>",
                         "alg_bytes_per_launch": b_iter, "avg_launch_us": avg * 1e6, "launches_timed": launches}}
     print(json.dumps(out), flush=True)
 
