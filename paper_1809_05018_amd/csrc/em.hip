@@ -20,8 +20,10 @@
 // After up to 10 packets, one lane per neighbourhood sums its members' minima in
 // member order (the paper's ReduceByKey<Add>), checks the neighbourhood's
 // convergence window and adds the sum to its lane's energy total.  At the end
-// of a chunk the wave reduces its lanes' statistics with a fixed butterfly into
-// LDS, and the block adds its 4 chunks in order into one record per superchunk.
+// of a chunk the wave's lane statistics pass through LDS eight values at a
+// time and are summed in a fixed order (eight lanes in order, then DPP moves)
+// into the chunk's row, and the block adds its 4 rows in order into one record
+// per superchunk.
 // There is no cross-block communication and no memory fence inside the launch.
 //
 // k_fold (one block per graph) adds the superchunk records in a fixed order
@@ -664,37 +666,6 @@ struct HoodPre {
   double prev[kPreWindow];
 };
 
-template <int LMAX>
-__device__ __forceinline__ void hood_pass_pre(const Ctx &c, int h0, int h1, int gstart, const HoodPre &pre,
-                                              LaneStats<LMAX> &ls, const double *mb, int lane) {
-  wave_lds_sync();
-  const int slots = c.W + 1;
-  const bool window = c.t >= c.W;
-  {
-    const int h = h0 + lane;
-    const bool act = h < h1;
-    const int o = pre.o - gstart, s = act ? pre.s : 0;
-    double S = 0.0;
-    for (int k = 0; __ballot(k < s); k += 4) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-        if (k + i < s) S = S + mb[o + k + i];
-    }
-    if (act) {
-      c.ring[(size_t)(c.t % slots) * c.H + h] = S;
-      bool conv = window;
-      if (window) {
-#pragma unroll
-        for (int w = 1; w <= kPreWindow; ++w)
-          if (w <= c.W && !(fabs(S - pre.prev[w - 1]) < c.tol)) conv = false;
-      }
-      if (!conv) ls.nonconv += 1;
-      ls.T = ls.T + S;
-    }
-  }
-  wave_lds_sync();
-  if (h0 + 64 < h1) hood_pass<LMAX>(c, h0 + 64, h1, gstart, ls, mb, lane);
-}
 
 __device__ __forceinline__ int bcast(int v, int lane_src) { return __builtin_amdgcn_readlane(v, lane_src); }
 
