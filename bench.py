@@ -104,7 +104,53 @@ def cpu_baseline(g, L, beta, iters, x0, M, min_seconds=10.0, max_reps=12):
     return ref, {"value": M * L * iters / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
                  "sample": f"the full workload, {iters} EM iterations, run {reps} times ({total:.1f} s); "
                            "serial C oracle (-O2), EM loop only",
-                 "seconds_per_run": round(dt, 3), "cpu": platform.processor() or platform.machine()}
+                 "seconds_per_run": round(dt, 3), "cpu": host_cpu()}
+
+
+def host_cpu() -> dict:
+    """CPU model and the cores this process may use, for the baseline records."""
+    model = platform.processor() or platform.machine()
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return {"model": model, "cores_available": cores}
+
+
+def cpu_baseline_parallel(graphs, L, beta, iters, threads):
+    """The oracle's EM loop on one graph per host thread (the graphs are
+    independent, so this is the embarrassingly parallel CPU rate): the first
+    ``threads`` graphs of the workload, ``iters`` iterations each, all at once;
+    graph construction is outside the timing (EM loop only)."""
+    import concurrent.futures as cf
+
+    import numpy as np
+
+    import oracle
+    from paper_1809_05018_amd import synth
+
+    sample = graphs[:threads]
+    with cf.ThreadPoolExecutor(threads) as ex:  # the C oracle runs without the GIL
+        ogs = list(ex.map(lambda g: oracle.OracleGraph(g.n, g.row_ptr, g.col_idx), sample))
+
+    def run(i):
+        g = sample[i]
+        x0 = synth.threshold_labels(g.y, L)
+        ogs[i].em_run(g.y, L, beta, x0, np.zeros(L), np.ones(L), iters, init_from_labels=True)
+        return ogs[i].M * L * iters
+
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(len(sample)) as ex:
+        evals = sum(ex.map(run, range(len(sample))))
+    dt = time.perf_counter() - t0
+    return {"value": evals / dt, "unit": "evals/s", "cores": len(sample), "kind": "oracle",
+            "sample": f"{len(sample)} of the workload's graphs, one per thread, {iters} EM iterations each "
+                      f"({dt:.1f} s wall); serial C oracle (-O2) per graph, EM loop only",
+            "cpu": host_cpu()}
 
 
 def main():
@@ -334,7 +380,15 @@ def bench_batched(args, dev):
                         "frac": achieved / HBM_PEAK_GBS,
                         "traffic": measured_traffic(BATCH_COUNTERS_FILE) if args.workload == "batch64" else None,
                         "kernel": f"k_iter<{4 if L > 2 else 2}>",
-                        "alg_bytes_per_launch": b_iter, "avg_launch_us": avg * 1e6, "launches_timed": launches}}
+                        "alg_bytes_per_launch": b_iter, "avg_launch_us": avg * 1e6, "launches_timed": launches},
+           "cpu_baseline": None}
+    if not args.no_cpu_baseline:
+        threads = max(1, min(16, host_cpu()["cores_available"], len(graphs)))
+        # a bounded sample: all iterations of the slices, a few of the large power-law graphs
+        sample_iters = iters if args.workload == "batch64" else 3
+        log(f"timing the oracle on {threads} graphs in parallel ({sample_iters} iterations each)")
+        out["cpu_baseline"] = cpu_baseline_parallel(graphs, L, beta, sample_iters, threads)
+        out["speedup_vs_oracle"] = out["value"] / out["cpu_baseline"]["value"]
     print(json.dumps(out), flush=True)
 
 
