@@ -170,8 +170,9 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: the EM path of one graph runs on one device and this build "
-              "has no multi-GPU path (see DESIGN.md for how it would shard). Run with --gpus 1.",
+        print("bench.py measures one GPU: the EM path of one graph runs on one device and the library "
+              "has no multi-GPU path (independent graphs would go whole to separate GPUs; one huge graph "
+              "would be split by cliques with a label halo). Run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
 

@@ -41,7 +41,7 @@ typedef int32_t pmrf_status;
 #define PMRF_EINVAL (-1)       /* bad argument or malformed graph */
 #define PMRF_ENOMEM (-2)       /* a caller buffer is too small, or host allocation failed */
 #define PMRF_EDEVICE (-3)      /* a HIP runtime call failed */
-#define PMRF_EUNSUPPORTED (-4) /* valid request outside what this build supports (k != 1, L > 16, neighbourhood > 1024, n > 2^26 - 1) */
+#define PMRF_EUNSUPPORTED (-4) /* valid request outside what this version supports (k != 1, L > 16, neighbourhood > 1024, n > 2^26 - 1) */
 /* device-reported codes, in counters[PMRF_CTR_STATUS] */
 #define PMRF_EBADLABEL (-10)   /* a starting label outside [0, L) */
 #define PMRF_EBADPARAM (-11)   /* a starting sigma <= 0 or a non-finite mu / sigma */
