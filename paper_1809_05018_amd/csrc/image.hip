@@ -28,7 +28,6 @@ using pmrf::fail;
 namespace {
 
 constexpr int kImgThreads = 256;
-constexpr int kRunPixels = 16;  // pixels of one row per thread in the region sums
 constexpr int kWavePixels = 64 * 16;  // consecutive pixels per wave in the boundary passes
 
 int64_t boundary_waves(int64_t npix) { return std::max<int64_t>(1, (npix + kWavePixels - 1) / kWavePixels); }
@@ -202,42 +201,91 @@ __global__ __launch_bounds__(kImgThreads) void k_zero64(long long *__restrict__ 
     a[i] = 0;
 }
 
-// Pixel sums and counts per region: a thread walks kRunPixels pixels of one
-// row and adds each run of equal ids with one integer atomic (integer sums,
-// so the totals do not depend on the order of the atomics).  Ids outside
-// [0, n) are skipped (k_boundary_count has counted them).
+// Pixel sums and counts per region, one block per tile of kTileRows x
+// kTileCols pixels; thread t walks kTileCols / 16 consecutive pixels of one
+// tile row (16 threads per row) and adds each run of equal ids once.  When
+// the valid ids of the tile span fewer than kTileTable values (neighbouring
+// regions have neighbouring ids in the usual oversegmentations) the runs are
+// added in an LDS table indexed by id - (smallest id) and each non-empty entry
+// goes to memory with one atomic; otherwise every run does.  Integer sums, so
+// the totals do not depend on the order.  Ids outside [0, n) are skipped
+// (k_boundary_count has counted them).
+constexpr int kTileRows = kImgThreads / 16, kTileCols = 128, kTileTable = 2048;
+constexpr int kTileSeg = kTileCols / 16;  // pixels per thread
+
 __global__ __launch_bounds__(kImgThreads) void k_region_sums(const int32_t *__restrict__ reg,
                                                               const uint8_t *__restrict__ pix, int32_t width,
                                                               int32_t height, int32_t n,
                                                               unsigned long long *__restrict__ sums,
                                                               unsigned long long *__restrict__ counts) {
-  const int64_t runs_per_row = (width + kRunPixels - 1) / kRunPixels;
-  const int64_t runs = runs_per_row * height;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < runs; t += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = t / runs_per_row;
-    const int32_t c0 = (int32_t)(t - r * runs_per_row) * kRunPixels;
-    const int32_t c1 = min(width, c0 + kRunPixels);
-    const int64_t row = r * width;
-    int32_t cur = -1;
-    unsigned long long s = 0, k = 0;
-    for (int32_t c = c0; c < c1; ++c) {
-      const int32_t u = reg[row + c];
-      if (u != cur) {
-        if (k && cur >= 0 && cur < n) {
-          atomicAdd(&sums[cur], s);
-          atomicAdd(&counts[cur], k);
-        }
-        cur = u;
-        s = 0;
-        k = 0;
-      }
-      s += pix[row + c];
-      k += 1;
+  __shared__ unsigned long long tsum[kTileTable];
+  __shared__ unsigned int tcnt[kTileTable];
+  __shared__ int id_lo, id_hi;
+  const int64_t tiles_x = (width + kTileCols - 1) / kTileCols;
+  const int64_t r = (int64_t)(blockIdx.x / tiles_x) * kTileRows + threadIdx.x / 16;
+  const int32_t c0 = (int32_t)(blockIdx.x % tiles_x) * kTileCols + (threadIdx.x % 16) * kTileSeg;
+  const int32_t c1 = (r < height) ? min(width, c0 + kTileSeg) : c0;  // empty past the last row
+  const int64_t row = r * width;
+  if (threadIdx.x == 0) {
+    id_lo = 0x7fffffff;
+    id_hi = -1;
+  }
+  __syncthreads();
+  int lo = 0x7fffffff, hi = -1;
+  for (int32_t c = c0; c < c1; ++c) {
+    const int32_t u = reg[row + c];
+    if (u >= 0 && u < n) {
+      lo = min(lo, u);
+      hi = max(hi, u);
     }
+  }
+  if (hi >= 0) {
+    atomicMin(&id_lo, lo);
+    atomicMax(&id_hi, hi);
+  }
+  __syncthreads();
+  const int base = id_lo;
+  const bool table = id_hi >= 0 && id_hi - base < kTileTable;  // the same for every thread
+  if (table) {
+    for (int i = threadIdx.x; i < kTileTable; i += blockDim.x) {
+      tsum[i] = 0;
+      tcnt[i] = 0;
+    }
+  }
+  __syncthreads();
+  int32_t cur = -1;
+  unsigned long long sm = 0;
+  unsigned int k = 0;
+  auto flush = [&]() {
     if (k && cur >= 0 && cur < n) {
-      atomicAdd(&sums[cur], s);
-      atomicAdd(&counts[cur], k);
+      if (table) {
+        atomicAdd(&tsum[cur - base], sm);
+        atomicAdd(&tcnt[cur - base], k);
+      } else {
+        atomicAdd(&sums[cur], sm);
+        atomicAdd(&counts[cur], (unsigned long long)k);
+      }
     }
+  };
+  for (int32_t c = c0; c < c1; ++c) {
+    const int32_t u = reg[row + c];
+    if (u != cur) {
+      flush();
+      cur = u;
+      sm = 0;
+      k = 0;
+    }
+    sm += pix[row + c];
+    k += 1;
+  }
+  flush();
+  if (table) {
+    __syncthreads();
+    for (int i = threadIdx.x; i <= id_hi - base; i += blockDim.x)
+      if (tcnt[i]) {
+        atomicAdd(&sums[base + i], tsum[i]);
+        atomicAdd(&counts[base + i], (unsigned long long)tcnt[i]);
+      }
   }
 }
 
@@ -368,8 +416,8 @@ extern "C" pmrf_status pmrf_image_graph(const int32_t *d_regions, const uint8_t 
                      (const uint64_t *)ka, edges, n, B, d_row_ptr, d_col_idx);
   IMG_TRY(hipGetLastError());
   if (npix > 0) {
-    const int64_t runs = (int64_t)height * ((width + kRunPixels - 1) / kRunPixels);
-    hipLaunchKernelGGL(k_region_sums, dim3(grid_for(runs)), dim3(kImgThreads), 0, s, d_regions, d_pixels, width,
+    const int64_t tiles = ((int64_t)height + kTileRows - 1) / kTileRows * (((int64_t)width + kTileCols - 1) / kTileCols);
+    hipLaunchKernelGGL(k_region_sums, dim3((unsigned)tiles), dim3(kImgThreads), 0, s, d_regions, d_pixels, width,
                        height, n, sums, counts);
     IMG_TRY(hipGetLastError());
   }
