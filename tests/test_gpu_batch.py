@@ -90,3 +90,29 @@ def test_batch_rejects_small_workspace_without_writing():
     assert e.value.code == pmrf.PMRF_ENOMEM
     torch.cuda.synchronize()
     assert torch.equal(prob.labels, before)
+
+
+def test_batch_with_a_graph_on_the_packet_kernel_only():
+    """A graph whose window (6) sends every chunk to the packet kernel has no
+    slot-kernel blocks; the graphs after it in the batch must still find their
+    own blocks (block-to-graph table) and every result equals its solo run."""
+    specs = [(synth.image_graph(620, 300, 3000, 2), 3), (synth.image_graph(621, 256, 1500, 2), 6),
+             (synth.image_graph(622, 400, 5000, 2), 3), (synth.image_graph(623, 128, 400, 2), 6)]
+    solos, probs = [], []
+    for g, W in specs:
+        x0, mu0, s0 = init_state(g, 2)
+        prob = pmrf.Problem(g.n, g.row_ptr, g.col_idx, g.y, 2)
+        params = pmrf.pmrf_em_params(L=2, beta=0.5, max_iters=10, conv_window=W)
+        prob.set_state(x0, mu0, s0)
+        prob.run(params)
+        solos.append(prob.results(params))
+        prob.set_state(x0, mu0, s0)
+        probs.append((prob, params))
+    items = [p.item(params) for p, params in probs]
+    ws = torch.empty(pmrf.pmrf_em_batch_workspace_bytes(items), dtype=torch.uint8, device="cuda")
+    pmrf.pmrf_em_batch(items, ws)
+    torch.cuda.synchronize()
+    for (prob, params), solo, (g, W) in zip(probs, solos, specs):
+        out = prob.results(params)
+        for k in KEYS:
+            assert np.array_equal(np.asarray(out[k]), np.asarray(solo[k])), (g.name, W, k)
