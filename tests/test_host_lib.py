@@ -182,3 +182,30 @@ def test_autotune_picks_fastest_shape_and_keeps_it():
         assert pmrf.pmrf_get_launch() == {"mode": 2, "waves_per_block": 4, "tiles_per_wave": 0, "blocks_per_cu": 4}
     finally:
         pmrf.pmrf_set_launch(**old)
+
+
+def test_image_entry_points_reject_bad_arguments_without_device():
+    """Host-side checks of the image entry points: nothing reaches the device."""
+    lib = pmrf.lib
+    b = ctypes.c_int64()
+    assert lib.pmrf_image_graph_workspace_bytes(-1, 4, 4, ctypes.byref(b)) == pmrf.PMRF_EINVAL
+    assert lib.pmrf_image_graph_workspace_bytes(4, 4, 4, None) == pmrf.PMRF_EINVAL
+    assert lib.pmrf_image_graph_workspace_bytes(1 << 15, 1 << 14, 4, ctypes.byref(b)) == pmrf.PMRF_EUNSUPPORTED
+    nnz = ctypes.c_int64()
+    # NULL outputs, negative sizes, pixels without regions, no workspace
+    assert lib.pmrf_image_graph(None, None, 2, 2, 4, None, None, 0, None, ctypes.byref(nnz), None, 0,
+                                None) == pmrf.PMRF_EINVAL
+    fake = ctypes.c_void_p(256)  # never dereferenced: every call below fails its checks first
+    assert lib.pmrf_image_graph(fake, fake, -2, 2, 4, fake, fake, 0, fake, ctypes.byref(nnz), fake, 1 << 20,
+                                None) == pmrf.PMRF_EINVAL
+    assert lib.pmrf_image_graph(fake, fake, 2, 2, 0, fake, fake, 0, fake, ctypes.byref(nnz), fake, 1 << 20,
+                                None) == pmrf.PMRF_EINVAL
+    assert lib.pmrf_image_graph(fake, fake, 2, 2, 4, fake, fake, 16, fake, ctypes.byref(nnz), None, 0,
+                                None) == pmrf.PMRF_ENOMEM
+    assert lib.pmrf_labels_to_pixels(fake, fake, -1, 4, fake, None) == pmrf.PMRF_EINVAL
+    assert lib.pmrf_labels_to_pixels(None, fake, 8, 4, fake, None) == pmrf.PMRF_EINVAL
+    assert lib.pmrf_labels_to_pixels(None, None, 0, 4, None, None) == pmrf.PMRF_OK  # nothing to do
+    assert lib.pmrf_confusion(fake, fake, 8, 0, fake, None) == pmrf.PMRF_EINVAL
+    assert lib.pmrf_confusion(fake, fake, 8, 17, fake, None) == pmrf.PMRF_EINVAL
+    assert lib.pmrf_confusion(fake, fake, 8, 2, None, None) == pmrf.PMRF_EINVAL
+    assert "k <= 16" in lib.pmrf_last_error().decode() or "NULL" in lib.pmrf_last_error().decode()
