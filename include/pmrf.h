@@ -288,6 +288,16 @@ pmrf_status pmrf_image_graph_workspace_bytes(int32_t width, int32_t height, int3
 pmrf_status pmrf_image_graph(const int32_t *d_regions, const uint8_t *d_pixels, int32_t width, int32_t height,
                              int32_t n, int32_t *d_row_ptr, int32_t *d_col_idx, int64_t col_capacity,
                              double *d_means, int64_t *nnz, void *d_ws, int64_t ws_bytes, void *hip_stream);
+/* pmrf_volume_graph: the same for a volume (depth slices of height x width,
+ * slice-major): regions are also adjacent across consecutive slices
+ * (6-connectivity), the 3-D graphs the paper names as the next step
+ * (Sec. 5).  pmrf_image_graph is this call with depth 1; arguments, limits
+ * (at most 2^28 voxels) and errors as there. */
+pmrf_status pmrf_volume_graph_workspace_bytes(int32_t width, int32_t height, int32_t depth, int32_t n,
+                                              int64_t *bytes);
+pmrf_status pmrf_volume_graph(const int32_t *d_regions, const uint8_t *d_voxels, int32_t width, int32_t height,
+                              int32_t depth, int32_t n, int32_t *d_row_ptr, int32_t *d_col_idx, int64_t col_capacity,
+                              double *d_means, int64_t *nnz, void *d_ws, int64_t ws_bytes, void *hip_stream);
 pmrf_status pmrf_labels_to_pixels(const int32_t *d_regions, const int32_t *d_labels, int64_t npixels, int32_t n,
                                   uint8_t *d_out, void *hip_stream);
 pmrf_status pmrf_confusion(const uint8_t *d_a, const uint8_t *d_b, int64_t npixels, int32_t k, int64_t *d_counts,

@@ -15,12 +15,21 @@ import numpy as np
 
 
 def adjacent_pairs(regions: np.ndarray) -> np.ndarray:
-    """Unordered pairs (u, v), u < v, of regions that touch: a pixel of u is the
-    left/right or upper/lower neighbour of a pixel of v (4-connectivity).
-    Returns int64[m, 2] in ascending lexicographic order."""
+    """Unordered pairs (u, v), u < v, of regions that touch: a pixel (voxel) of
+    u and one of v are neighbours along one axis (4-connectivity in an image,
+    6-connectivity in a volume).  Returns int64[m, 2] in ascending
+    lexicographic order."""
     reg = np.asarray(regions, dtype=np.int64)
-    a = np.concatenate([reg[:, :-1].ravel(), reg[:-1, :].ravel()])  # a pixel ...
-    b = np.concatenate([reg[:, 1:].ravel(), reg[1:, :].ravel()])  # ... and its right / lower neighbour
+    a_parts, b_parts = [], []
+    for axis in range(reg.ndim):  # a pixel and its next neighbour along the axis
+        lo = [slice(None)] * reg.ndim
+        hi = [slice(None)] * reg.ndim
+        lo[axis] = slice(None, -1)
+        hi[axis] = slice(1, None)
+        a_parts.append(reg[tuple(lo)].ravel())
+        b_parts.append(reg[tuple(hi)].ravel())
+    a = np.concatenate(a_parts)
+    b = np.concatenate(b_parts)
     differ = a != b
     lo = np.minimum(a[differ], b[differ])
     hi = np.maximum(a[differ], b[differ])

@@ -53,9 +53,11 @@ struct ImgPlan {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-ImgPlan plan_image(int64_t width, int64_t height, int64_t n) {
+ImgPlan plan_image(int64_t width, int64_t height, int64_t depth, int64_t n) {
   ImgPlan p;
-  p.pairs = std::max<int64_t>(1, height * std::max<int64_t>(0, width - 1) + std::max<int64_t>(0, height - 1) * width);
+  const int64_t w1 = std::max<int64_t>(0, width - 1), h1 = std::max<int64_t>(0, height - 1),
+                d1 = std::max<int64_t>(0, depth - 1);
+  p.pairs = std::max<int64_t>(1, depth * height * w1 + depth * h1 * width + d1 * height * width);
   const int64_t keys = 2 * p.pairs;  // both directions of every unique pair fit as well
   size_t off = 0;
   p.keys_a = off;
@@ -68,7 +70,7 @@ ImgPlan plan_image(int64_t width, int64_t height, int64_t n) {
   off = align256(off + (size_t)std::max<int64_t>(1, n) * 8);
   p.scalars = off;
   off = align256(off + 4 * 8);
-  const int64_t waves = boundary_waves(width * height);
+  const int64_t waves = boundary_waves(width * height * depth);
   p.wcount = off;
   off = align256(off + (size_t)waves * 4);
   p.woff = off;
@@ -91,18 +93,22 @@ ImgPlan plan_image(int64_t width, int64_t height, int64_t n) {
 // the same pixels: wave w takes pixels [w * kWavePixels, (w + 1) *
 // kWavePixels), 64 at a time; the first pass counts its pairs, an exclusive
 // scan turns the counts into offsets, the second pass writes the keys there in
-// pixel order (right before down within each 64 pixels), ranks from ballots.
-// Ids outside [0, n) are counted by the first pass.
+// pixel order (right, then lower, then next-slice pairs within each 64
+// pixels), ranks from ballots.  A volume (depth > 1) adds the neighbour in the
+// next slice (6-connectivity).  Ids outside [0, n) are counted by the first
+// pass.
 struct PixelPairs {
-  bool right, down, bad;
-  uint64_t kr, kd;
+  bool right, down, back, bad;
+  uint64_t kr, kd, kb;
 };
 
 __device__ __forceinline__ PixelPairs pixel_pairs(const int32_t *__restrict__ reg, int64_t p, int64_t npix,
                                                   int32_t width, int32_t height, int32_t n, int B) {
-  PixelPairs q{false, false, false, 0, 0};
+  PixelPairs q{false, false, false, false, 0, 0, 0};
   if (p < npix) {
-    const int32_t r = (int32_t)(p / width), c = (int32_t)(p - (int64_t)r * width);
+    const int64_t plane = (int64_t)width * height;
+    const int64_t z = p / plane, rem = p - z * plane;
+    const int32_t r = (int32_t)(rem / width), c = (int32_t)(rem - (int64_t)r * width);
     const int32_t u = reg[p];
     q.bad = u < 0 || u >= n;
     if (c + 1 < width) {
@@ -117,22 +123,28 @@ __device__ __forceinline__ PixelPairs pixel_pairs(const int32_t *__restrict__ re
       q.down = u != v;
       q.kd = ((uint64_t)(uint32_t)min(u, v) << B) | (uint32_t)max(u, v);
     }
+    if (p + plane < npix) {
+      const int32_t v = reg[p + plane];
+      q.bad |= v < 0 || v >= n;
+      q.back = u != v;
+      q.kb = ((uint64_t)(uint32_t)min(u, v) << B) | (uint32_t)max(u, v);
+    }
   }
   return q;
 }
 
 __global__ __launch_bounds__(kImgThreads) void k_boundary_count(const int32_t *__restrict__ reg, int32_t width,
-                                                                 int32_t height, int32_t n, int B, int64_t waves,
-                                                                 uint32_t *__restrict__ wcount,
+                                                                 int32_t height, int32_t depth, int32_t n, int B,
+                                                                 int64_t waves, uint32_t *__restrict__ wcount,
                                                                  unsigned long long *__restrict__ scal) {
-  const int64_t npix = (int64_t)width * height;
+  const int64_t npix = (int64_t)width * height * depth;
   const int lane = threadIdx.x & 63;
   const int64_t w = (int64_t)blockIdx.x * (kImgThreads / 64) + (threadIdx.x >> 6);
   if (w >= waves) return;
   uint32_t cnt = 0, bad = 0;
   for (int i = 0; i < kWavePixels / 64; ++i) {
     const PixelPairs q = pixel_pairs(reg, w * kWavePixels + i * 64 + lane, npix, width, height, n, B);
-    cnt += (uint32_t)(__popcll(__ballot(q.right)) + __popcll(__ballot(q.down)));
+    cnt += (uint32_t)(__popcll(__ballot(q.right)) + __popcll(__ballot(q.down)) + __popcll(__ballot(q.back)));
     bad += (uint32_t)__popcll(__ballot(q.bad));
   }
   if (lane == 0) {
@@ -142,10 +154,10 @@ __global__ __launch_bounds__(kImgThreads) void k_boundary_count(const int32_t *_
 }
 
 __global__ __launch_bounds__(kImgThreads) void k_boundary_emit(const int32_t *__restrict__ reg, int32_t width,
-                                                                int32_t height, int32_t n, int B, int64_t waves,
-                                                                const uint32_t *__restrict__ woff,
+                                                                int32_t height, int32_t depth, int32_t n, int B,
+                                                                int64_t waves, const uint32_t *__restrict__ woff,
                                                                 uint64_t *__restrict__ keys) {
-  const int64_t npix = (int64_t)width * height;
+  const int64_t npix = (int64_t)width * height * depth;
   const int lane = threadIdx.x & 63;
   const int64_t w = (int64_t)blockIdx.x * (kImgThreads / 64) + (threadIdx.x >> 6);
   if (w >= waves) return;
@@ -153,10 +165,11 @@ __global__ __launch_bounds__(kImgThreads) void k_boundary_emit(const int32_t *__
   uint64_t base = woff[w];
   for (int i = 0; i < kWavePixels / 64; ++i) {
     const PixelPairs q = pixel_pairs(reg, w * kWavePixels + i * 64 + lane, npix, width, height, n, B);
-    const uint64_t br = __ballot(q.right), bd = __ballot(q.down);
+    const uint64_t br = __ballot(q.right), bd = __ballot(q.down), bk = __ballot(q.back);
     if (q.right) keys[base + __popcll(br & below)] = q.kr;
     if (q.down) keys[base + __popcll(br) + __popcll(bd & below)] = q.kd;
-    base += __popcll(br) + __popcll(bd);
+    if (q.back) keys[base + __popcll(br) + __popcll(bd) + __popcll(bk & below)] = q.kb;
+    base += __popcll(br) + __popcll(bd) + __popcll(bk);
   }
 }
 
@@ -333,27 +346,31 @@ int grid_for(int64_t work, int per_cu = 8) {
 
 }  // namespace
 
-extern "C" pmrf_status pmrf_image_graph_workspace_bytes(int32_t width, int32_t height, int32_t n, int64_t *bytes) {
+namespace {
+
+pmrf_status workspace_bytes(int32_t width, int32_t height, int32_t depth, int32_t n, int64_t *bytes) {
   clear_error();
   if (!bytes) return fail(PMRF_EINVAL, "NULL argument");
-  if (width < 0 || height < 0 || n < 0) return fail(PMRF_EINVAL, "negative size");
-  if ((int64_t)width * height > (int64_t)1 << 28) return fail(PMRF_EUNSUPPORTED, "more than 2^28 pixels");
-  *bytes = (int64_t)plan_image(width, height, n).total;
+  if (width < 0 || height < 0 || depth < 0 || n < 0) return fail(PMRF_EINVAL, "negative size");
+  if ((int64_t)width * height * depth > (int64_t)1 << 28) return fail(PMRF_EUNSUPPORTED, "more than 2^28 pixels");
+  *bytes = (int64_t)plan_image(width, height, depth, n).total;
   return PMRF_OK;
 }
 
-extern "C" pmrf_status pmrf_image_graph(const int32_t *d_regions, const uint8_t *d_pixels, int32_t width,
-                                        int32_t height, int32_t n, int32_t *d_row_ptr, int32_t *d_col_idx,
-                                        int64_t col_capacity, double *d_means, int64_t *nnz, void *d_ws,
-                                        int64_t ws_bytes, void *hip_stream) {
+// The region graph and means of a depth x height x width volume (an image is
+// the volume of depth 1).
+pmrf_status region_graph(const int32_t *d_regions, const uint8_t *d_pixels, int32_t width, int32_t height,
+                         int32_t depth, int32_t n, int32_t *d_row_ptr, int32_t *d_col_idx, int64_t col_capacity,
+                         double *d_means, int64_t *nnz, void *d_ws, int64_t ws_bytes, void *hip_stream) {
   clear_error();
   if (!nnz || !d_row_ptr || (n > 0 && !d_means)) return fail(PMRF_EINVAL, "NULL argument");
-  if (width < 0 || height < 0 || n < 0 || col_capacity < 0) return fail(PMRF_EINVAL, "negative size");
-  const int64_t npix = (int64_t)width * height;
+  if (width < 0 || height < 0 || depth < 0 || n < 0 || col_capacity < 0) return fail(PMRF_EINVAL, "negative size");
+  if ((int64_t)width * height * depth > (int64_t)1 << 28) return fail(PMRF_EUNSUPPORTED, "more than 2^28 pixels");
+  const int64_t npix = (int64_t)width * height * depth;
   if (npix > (int64_t)1 << 28) return fail(PMRF_EUNSUPPORTED, "more than 2^28 pixels");
   if (npix > 0 && (!d_regions || !d_pixels)) return fail(PMRF_EINVAL, "NULL image");
   if (npix > 0 && n == 0) return fail(PMRF_EINVAL, "pixels but no regions");
-  const ImgPlan plan = plan_image(width, height, n);
+  const ImgPlan plan = plan_image(width, height, depth, n);
   if (!d_ws || ws_bytes < (int64_t)plan.total)
     return fail(PMRF_ENOMEM, "workspace smaller than pmrf_image_graph_workspace_bytes");
   hipStream_t s = (hipStream_t)hip_stream;
@@ -373,16 +390,16 @@ extern "C" pmrf_status pmrf_image_graph(const int32_t *d_regions, const uint8_t 
   uint32_t *wcount = (uint32_t *)(ws + plan.wcount), *woff = (uint32_t *)(ws + plan.woff);
   if (npix > 0) {
     const int blocks = (int)((waves + kImgThreads / 64 - 1) / (kImgThreads / 64));
-    hipLaunchKernelGGL(k_boundary_count, dim3(blocks), dim3(kImgThreads), 0, s, d_regions, width, height, n, B,
-                       waves, wcount, scal);
+    hipLaunchKernelGGL(k_boundary_count, dim3(blocks), dim3(kImgThreads), 0, s, d_regions, width, height, depth, n,
+                       B, waves, wcount, scal);
     IMG_TRY(hipGetLastError());
     size_t tb = plan.temp_bytes;
     IMG_TRY(hipcub::DeviceScan::ExclusiveSum(temp, tb, (const uint32_t *)wcount, woff, (int)waves, s));
     hipLaunchKernelGGL(k_pair_total, dim3(1), dim3(64), 0, s, (const uint32_t *)wcount, (const uint32_t *)woff,
                        waves, scal);
     IMG_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_boundary_emit, dim3(blocks), dim3(kImgThreads), 0, s, d_regions, width, height, n, B,
-                       waves, (const uint32_t *)woff, ka);
+    hipLaunchKernelGGL(k_boundary_emit, dim3(blocks), dim3(kImgThreads), 0, s, d_regions, width, height, depth, n,
+                       B, waves, (const uint32_t *)woff, ka);
     IMG_TRY(hipGetLastError());
   }
   unsigned long long host_scal[4] = {0, 0, 0, 0};
@@ -416,9 +433,10 @@ extern "C" pmrf_status pmrf_image_graph(const int32_t *d_regions, const uint8_t 
                      (const uint64_t *)ka, edges, n, B, d_row_ptr, d_col_idx);
   IMG_TRY(hipGetLastError());
   if (npix > 0) {
-    const int64_t tiles = ((int64_t)height + kTileRows - 1) / kTileRows * (((int64_t)width + kTileCols - 1) / kTileCols);
+    const int64_t rows = (int64_t)height * depth;  // the sums walk rows; slices follow one another
+    const int64_t tiles = (rows + kTileRows - 1) / kTileRows * (((int64_t)width + kTileCols - 1) / kTileCols);
     hipLaunchKernelGGL(k_region_sums, dim3((unsigned)tiles), dim3(kImgThreads), 0, s, d_regions, d_pixels, width,
-                       height, n, sums, counts);
+                       (int32_t)rows, n, sums, counts);
     IMG_TRY(hipGetLastError());
   }
   if (n > 0) {
@@ -428,6 +446,33 @@ extern "C" pmrf_status pmrf_image_graph(const int32_t *d_regions, const uint8_t 
   }
   *nnz = edges;
   return PMRF_OK;
+}
+
+}  // namespace
+
+extern "C" pmrf_status pmrf_image_graph_workspace_bytes(int32_t width, int32_t height, int32_t n, int64_t *bytes) {
+  return workspace_bytes(width, height, 1, n, bytes);
+}
+
+extern "C" pmrf_status pmrf_image_graph(const int32_t *d_regions, const uint8_t *d_pixels, int32_t width,
+                                        int32_t height, int32_t n, int32_t *d_row_ptr, int32_t *d_col_idx,
+                                        int64_t col_capacity, double *d_means, int64_t *nnz, void *d_ws,
+                                        int64_t ws_bytes, void *hip_stream) {
+  return region_graph(d_regions, d_pixels, width, height, 1, n, d_row_ptr, d_col_idx, col_capacity, d_means, nnz,
+                      d_ws, ws_bytes, hip_stream);
+}
+
+extern "C" pmrf_status pmrf_volume_graph_workspace_bytes(int32_t width, int32_t height, int32_t depth, int32_t n,
+                                                         int64_t *bytes) {
+  return workspace_bytes(width, height, depth, n, bytes);
+}
+
+extern "C" pmrf_status pmrf_volume_graph(const int32_t *d_regions, const uint8_t *d_voxels, int32_t width,
+                                         int32_t height, int32_t depth, int32_t n, int32_t *d_row_ptr,
+                                         int32_t *d_col_idx, int64_t col_capacity, double *d_means, int64_t *nnz,
+                                         void *d_ws, int64_t ws_bytes, void *hip_stream) {
+  return region_graph(d_regions, d_voxels, width, height, depth, n, d_row_ptr, d_col_idx, col_capacity, d_means,
+                      nnz, d_ws, ws_bytes, hip_stream);
 }
 
 extern "C" pmrf_status pmrf_labels_to_pixels(const int32_t *d_regions, const int32_t *d_labels, int64_t npixels,

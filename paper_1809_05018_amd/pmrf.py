@@ -37,7 +37,7 @@ EXPORTED = (
     "pmrf_hoods_free", "pmrf_em_params_default", "pmrf_em_workspace_bytes", "pmrf_em_run",
     "pmrf_em_batch_workspace_bytes", "pmrf_em_batch", "pmrf_set_launch", "pmrf_get_launch",
     "pmrf_profile_begin", "pmrf_profile_end", "pmrf_image_graph_workspace_bytes", "pmrf_image_graph",
-    "pmrf_labels_to_pixels", "pmrf_confusion",
+    "pmrf_labels_to_pixels", "pmrf_confusion", "pmrf_volume_graph_workspace_bytes", "pmrf_volume_graph",
 )
 
 
@@ -98,6 +98,9 @@ def _load():
     lib.pmrf_image_graph_workspace_bytes.argtypes = [c_int32, c_int32, c_int32, P(c_int64)]
     lib.pmrf_image_graph.argtypes = [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_int64,
                                      c_void_p, P(c_int64), c_void_p, c_int64, c_void_p]
+    lib.pmrf_volume_graph_workspace_bytes.argtypes = [c_int32, c_int32, c_int32, c_int32, P(c_int64)]
+    lib.pmrf_volume_graph.argtypes = [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_int32, c_void_p, c_void_p,
+                                      c_int64, c_void_p, P(c_int64), c_void_p, c_int64, c_void_p]
     lib.pmrf_labels_to_pixels.argtypes = [c_void_p, c_void_p, c_int64, c_int32, c_void_p, c_void_p]
     lib.pmrf_confusion.argtypes = [c_void_p, c_void_p, c_int64, c_int32, c_void_p, c_void_p]
     for name in EXPORTED:
@@ -406,29 +409,44 @@ def pmrf_image_graph_workspace_bytes(width, height, n) -> int:
     return b.value
 
 
+def pmrf_volume_graph_workspace_bytes(width, height, depth, n) -> int:
+    b = c_int64()
+    _check(lib.pmrf_volume_graph_workspace_bytes(int(width), int(height), int(depth), int(n), ctypes.byref(b)))
+    return b.value
+
+
 def image_graph(regions, pixels, n, ws=None, stream=None):
-    """Region adjacency graph and region means of an oversegmented image on the
-    device: ``regions`` (int32, height x width) and ``pixels`` (uint8, same
-    shape) are device tensors; returns device tensors (row_ptr int32[n+1],
-    col_idx int32[nnz], means float64[n])."""
+    """Region adjacency graph and region means of an oversegmented image
+    (``regions`` int32 and ``pixels`` uint8 device tensors of shape
+    (height, width)) or volume (shape (depth, height, width), 6-connected);
+    returns device tensors (row_ptr int32[n+1], col_idx int32[nnz], means
+    float64[n])."""
     import torch
 
-    height, width = (int(d) for d in regions.shape)
+    shape = tuple(int(d) for d in regions.shape)
+    if len(shape) not in (2, 3):
+        raise ValueError("regions must be (height, width) or (depth, height, width)")
+    depth, height, width = (1,) + shape if len(shape) == 2 else shape
     dev = regions.device
-    _ptr(regions, torch.int32, height * width, "regions")
-    _ptr(pixels, torch.uint8, height * width, "pixels")
+    _ptr(regions, torch.int32, depth * height * width, "regions")
+    _ptr(pixels, torch.uint8, depth * height * width, "pixels")
     if ws is None:
-        ws = torch.empty(pmrf_image_graph_workspace_bytes(width, height, n), dtype=torch.uint8, device=dev)
+        ws = torch.empty(pmrf_volume_graph_workspace_bytes(width, height, depth, n), dtype=torch.uint8, device=dev)
     s = _stream(stream, dev)
     row_ptr = torch.empty(n + 1, dtype=torch.int32, device=dev)
     means = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
-    cap = max(12, 6 * n)  # a 4-connected region graph is planar: at most 3n - 6 edges
+    cap = max(12, 6 * n)  # a 4-connected region graph is planar (at most 3n - 6 edges); volumes may need more
     nnz = c_int64()
     while True:
         col = torch.empty(cap, dtype=torch.int32, device=dev)
-        code = lib.pmrf_image_graph(regions.data_ptr(), pixels.data_ptr(), width, height, int(n),
-                                    row_ptr.data_ptr(), col.data_ptr(), cap, means.data_ptr(), ctypes.byref(nnz),
-                                    ws.data_ptr(), ws.numel(), s)
+        if len(shape) == 2:
+            code = lib.pmrf_image_graph(regions.data_ptr(), pixels.data_ptr(), width, height, int(n),
+                                        row_ptr.data_ptr(), col.data_ptr(), cap, means.data_ptr(), ctypes.byref(nnz),
+                                        ws.data_ptr(), ws.numel(), s)
+        else:
+            code = lib.pmrf_volume_graph(regions.data_ptr(), pixels.data_ptr(), width, height, depth, int(n),
+                                         row_ptr.data_ptr(), col.data_ptr(), cap, means.data_ptr(), ctypes.byref(nnz),
+                                         ws.data_ptr(), ws.numel(), s)
         if code == PMRF_ENOMEM and nnz.value > cap:
             cap = nnz.value
             continue

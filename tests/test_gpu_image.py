@@ -112,3 +112,27 @@ def test_image_to_segmentation():
     for key in ref:
         assert s[key] == ref[key], key
     assert s["accuracy"] > 0.9  # the two synthetic phases are recovered
+
+
+def test_volume_graph_matches_oracle():
+    rng = np.random.default_rng(31)
+    # slices with their own regions (ids offset per slice): regions touch across slices
+    labs, imgs, off = [], [], 0
+    for z in range(5):
+        img, lab, _ = synth.image_slice(40 + z, 96, 300)
+        labs.append(lab + off)
+        imgs.append(img)
+        off += int(lab.max()) + 1
+    vol, pix = np.stack(labs).astype(np.int32), np.stack(imgs)
+    check_graph(vol, pix, off, "stacked slices")
+    # regions running through every slice, plus one region per voxel, plus thin shapes
+    check_graph(np.stack([labs[0]] * 4), np.stack(imgs[:4]), int(labs[0].max()) + 1, "columns")
+    for d, h, w in [(2, 2, 2), (3, 1, 1), (5, 1, 7), (1, 9, 11), (4, 6, 5)]:
+        p = rng.integers(0, 256, size=(d, h, w), dtype=np.uint8)
+        check_graph(np.arange(d * h * w, dtype=np.int32).reshape(d, h, w), p, d * h * w, f"voxels {d}x{h}x{w}")
+    # depth 1 is the image call
+    img, lab, _ = synth.image_slice(44, 128, 500)
+    a = gpu_graph(lab[None], img[None], int(lab.max()) + 1)
+    b = gpu_graph(lab, img, int(lab.max()) + 1)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)

@@ -105,3 +105,36 @@ def test_paint_confusion_and_scores():
     assert s["porosity"] == 3 / 8
     same = oi.scores(oi.confusion(truth, truth, 2))
     assert same["precision"] == same["recall"] == same["accuracy"] == 1.0
+
+
+def test_volume_closed_forms():
+    # one region per voxel of a 2 x 2 x 2 volume: the cube graph (degree 3)
+    cube = np.arange(8, dtype=np.int32).reshape(2, 2, 2)
+    row_ptr, col_idx = oi.region_graph(cube, 8)
+    for u in range(8):
+        assert col_idx[row_ptr[u]:row_ptr[u + 1]].tolist() == sorted(u ^ bit for bit in (1, 2, 4))
+    # blocks of a 3-D grid: the 3-D grid graph
+    bz, by, bx, size = 2, 3, 2, 3
+    zz, yy, xx = np.meshgrid(np.arange(bz * size), np.arange(by * size), np.arange(bx * size), indexing="ij")
+    regions = (((zz // size) * by + yy // size) * bx + xx // size).astype(np.int32)
+    row_ptr, col_idx = oi.region_graph(regions, bz * by * bx)
+    for k in range(bz):
+        for i in range(by):
+            for j in range(bx):
+                u = (k * by + i) * bx + j
+                want = sorted((a * by + b) * bx + c for a, b, c in ((k - 1, i, j), (k + 1, i, j), (k, i - 1, j),
+                                                                    (k, i + 1, j), (k, i, j - 1), (k, i, j + 1))
+                              if 0 <= a < bz and 0 <= b < by and 0 <= c < bx)
+                assert col_idx[row_ptr[u]:row_ptr[u + 1]].tolist() == want
+    # regions that run through every slice: the graph of one slice, means over all slices
+    img, lab, _ = synth.image_slice(7, 64, 100)
+    n = int(lab.max()) + 1
+    vol = np.stack([lab] * 3)
+    pix = np.stack([img, img // 2, img])
+    ref_ptr, ref_col = oi.region_graph(lab, n)
+    row_ptr, col_idx = oi.region_graph(vol, n)
+    assert np.array_equal(row_ptr, ref_ptr) and np.array_equal(col_idx, ref_col)
+    sums = np.zeros(n, np.int64)
+    np.add.at(sums, lab.ravel(), 2 * img.ravel().astype(np.int64) + (img // 2).ravel())
+    counts = np.bincount(lab.ravel(), minlength=n) * 3
+    assert np.array_equal(oi.region_means(vol, pix, n), sums / counts)
