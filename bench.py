@@ -162,7 +162,7 @@ def main():
     ap.add_argument("--iters", type=int, default=30, help="EM iterations per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="slice2048_100k",
-                    choices=["slice2048_100k", "batch64", "powerlaw16", "serving", "image2048"],
+                    choices=["slice2048_100k", "batch64", "powerlaw16", "serving", "image2048", "volume256"],
                     help="default: the single 100k-region slice; the others print their own JSON line")
     ap.add_argument("--requests", type=int, default=128, help="serving: number of requests")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -189,7 +189,7 @@ def main():
         return bench_batched(args, dev)
     if args.workload == "serving":
         return bench_serving(args, dev)
-    if args.workload == "image2048":
+    if args.workload in ("image2048", "volume256"):
         return bench_image(args, dev)
     L, beta, iters = 2, 0.5, args.iters
     log("generating the 2048x2048 / 100k-region slice")
@@ -404,14 +404,28 @@ def bench_image(args, dev):
 
     from paper_1809_05018_amd import pmrf, synth
 
-    log("generating the 2048x2048 image and its 100k-region oversegmentation")
-    img, lab, ph = synth.image_slice(2, 2048, 100_000)
+    if args.workload == "volume256":
+        # 256 slices of 256 x 256, each oversegmented on its own (ids offset per
+        # slice), so regions meet across slices as well as within them
+        log("generating a 256^3 volume (256 slices, 2,500 regions each)")
+        labs, imgs, phs, off = [], [], [], 0
+        for z in range(256):
+            im, lb, p_ = synth.image_slice(6000 + z, 256, 2500)
+            labs.append(lb + off)
+            imgs.append(im)
+            phs.append(p_)
+            off += int(lb.max()) + 1
+        lab, img, ph = np.stack(labs).astype(np.int32), np.stack(imgs), np.stack(phs)
+    else:
+        log("generating the 2048x2048 image and its 100k-region oversegmentation")
+        img, lab, ph = synth.image_slice(2, 2048, 100_000)
     n = int(lab.max()) + 1
-    h, w = lab.shape
+    h, w = lab.shape[-2:]
+    npix = lab.size
     r = torch.from_numpy(lab).to(dev)
     p = torch.from_numpy(img).to(dev)
     truth = torch.from_numpy(ph.astype(np.uint8)).to(dev)
-    ws = torch.empty(pmrf.pmrf_image_graph_workspace_bytes(w, h, n), dtype=torch.uint8, device=dev)
+    ws = torch.empty(pmrf.pmrf_volume_graph_workspace_bytes(w, h, npix // (h * w), n), dtype=torch.uint8, device=dev)
     labels = torch.from_numpy(synth.threshold_labels(np.zeros(n), 2)).to(dev)
 
     def step():
@@ -433,15 +447,18 @@ def bench_image(args, dev):
     nnz = int(col_idx.numel())
     # algorithmic bytes of the graph call: region ids and pixels read once,
     # the CSR and the means written once
-    b_alg = 5 * h * w + 4 * (n + 1) + 4 * nnz + 8 * n
+    b_alg = 5 * npix + 4 * (n + 1) + 4 * nnz + 8 * n
     achieved = b_alg / dt / 1e9
-    log(f"{dt * 1e3:.3f} ms per image (graph, means, paint, confusion), nnz={nnz}")
+    log(f"{dt * 1e3:.3f} ms per {args.workload} (graph, means, paint, confusion), nnz={nnz}")
     result = {
         "metric": "image-to-graph pixels/s (region adjacency graph + region means + paint + confusion)",
-        "value": h * w / dt, "unit": "pixels/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "value": npix / dt, "unit": "pixels/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
         "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "int32/u8 in, f64 means", "data": "synthetic",
-        "config": {"workload": "image2048", "image": "2048x2048 two-phase, seed 2", "regions": n, "adjacency": nnz},
+        "config": {"workload": args.workload,
+                   "image": "2048x2048 two-phase, seed 2" if args.workload == "image2048"
+                   else "256 slices of 256x256 two-phase, seeds 6000+z, 6-connected",
+                   "regions": n, "adjacency": nnz},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "whole graph call",
                      "alg_bytes_per_launch": b_alg,
@@ -455,8 +472,8 @@ def bench_image(args, dev):
         ref_ptr, ref_col = oi.region_graph(lab, n)
         ref_means = oi.region_means(lab, img, n)
         cpu = time.perf_counter() - t1
-        result["cpu_baseline"] = {"value": h * w / cpu, "unit": "pixels/s", "cores": 1, "kind": "oracle",
-                                  "sample": "graph and means of the full image, once (NumPy oracle)"}
+        result["cpu_baseline"] = {"value": npix / cpu, "unit": "pixels/s", "cores": 1, "kind": "oracle",
+                                  "sample": f"graph and means of the full {args.workload}, once (NumPy oracle)"}
         result["parity"] = {"graph_equal": bool(np.array_equal(row_ptr.cpu().numpy(), ref_ptr)
                                                 and np.array_equal(col_idx.cpu().numpy(), ref_col)),
                             "means_equal": bool(np.array_equal(means.cpu().numpy(), ref_means))}
