@@ -369,8 +369,9 @@ int or_mstep(int n, const double *y, int L, const int *x, const double *mu_in, c
  *
  *  energy of element (h,j) = vertex v under label l (MAP criterion of Sec. 2.1:
  *  likelihood energy plus prior energy; the concrete forms are a reading):
- *     data(v,l) = (y_v - mu_l)^2 * (1 / (2 sigma_l^2)) + ln sigma_l
- *                 (Gaussian negative log-likelihood without the constant)
+ *     data(v,l) = (y_v - mu_l)(y_v - mu_l) / (2 sigma_l sigma_l) + ln sigma_l
+ *                 (Gaussian negative log-likelihood without the constant,
+ *                 evaluated per element in exactly this order)
  *     E(h,j,l)  = data(v,l) + beta * #{in-hood neighbours u of v : x_u != l}
  *                 (Potts prior restricted to the neighbourhood)
  *  m(h,j) = min over l of E, a(h,j) = lowest l attaining it,
@@ -389,11 +390,7 @@ int or_em_step(const or_graph *g, const double *y, int L, double beta, const int
                int *x_out, double *mu_out, double *sigma_out, double *S, double *T, i64 *near_ties,
                double *m_out, int *a_out, double *gap_out) {
   if (L < 2 || L > 16) return -1;
-  double w[16], lg[16], E[16];
-  for (int l = 0; l < L; ++l) {
-    w[l] = 1.0 / (2.0 * sigma_in[l] * sigma_in[l]);
-    lg[l] = log(sigma_in[l]);
-  }
+  double E[16];
   double *gap_elem = (double *)malloc((size_t)(g->M > 0 ? g->M : 1) * sizeof(double));
   int *a_elem = (int *)malloc((size_t)(g->M > 0 ? g->M : 1) * sizeof(int));
   double total = 0.0;
@@ -408,7 +405,7 @@ int or_em_step(const or_graph *g, const double *y, int L, double beta, const int
           if (x_in[u] != l) c++;
         }
         double d = y[v] - mu_in[l];
-        double data = (d * d) * w[l] + lg[l];
+        double data = (d * d) / (2.0 * sigma_in[l] * sigma_in[l]) + log(sigma_in[l]);
         E[l] = data + beta * (double)c;
       }
       double m = E[0];

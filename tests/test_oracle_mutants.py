@@ -16,8 +16,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 MUTANTS = {
     "potts_sign": ("if (x_in[u] != l) c++;", "if (x_in[u] == l) c++;"),
-    "drop_log_sigma": ("double data = (d * d) * w[l] + lg[l];", "double data = (d * d) * w[l];"),
-    "variance_factor": ("w[l] = 1.0 / (2.0 * sigma_in[l] * sigma_in[l]);", "w[l] = 1.0 / (sigma_in[l] * sigma_in[l]);"),
+    "drop_log_sigma": ("(2.0 * sigma_in[l] * sigma_in[l]) + log(sigma_in[l]);", "(2.0 * sigma_in[l] * sigma_in[l]);"),
+    "variance_factor": ("(d * d) / (2.0 * sigma_in[l] * sigma_in[l])", "(d * d) / (sigma_in[l] * sigma_in[l])"),
     "tie_highest_label": ("if (E[l] < m) { m = E[l]; a = l; }", "if (E[l] <= m) { m = E[l]; a = l; }"),
     "hood_sum_wrong_term": ("sh = sh + m;", "sh = sh + E[0];"),
     "total_not_summed": ("total = total + sh;", "total = sh;"),
