@@ -46,7 +46,7 @@ typedef int32_t pmrf_status;
 #define PMRF_EBADLABEL (-10)   /* a starting label outside [0, L) */
 #define PMRF_EBADPARAM (-11)   /* a starting sigma <= 0 or a non-finite mu / sigma */
 #define PMRF_ERANGE (-12)      /* reserved: not returned by this version */
-#define PMRF_ETIMEOUT (-13)    /* the persistent kernel's grid barrier did not complete (not co-resident) */
+#define PMRF_ETIMEOUT (-13)    /* reserved: not returned by this version (no kernel waits on another block) */
 
 /* Thread-local text of the last error (never NULL; "" if none). */
 const char *pmrf_last_error(void);
@@ -175,9 +175,11 @@ pmrf_status pmrf_em_workspace_bytes(const pmrf_hoods *hoods, const pmrf_em_param
  *  d_counters[PMRF_NCOUNTERS] out: PMRF_CTR_* (required)
  *  d_ws, ws_bytes       workspace of at least pmrf_em_workspace_bytes bytes, 256-byte aligned;
  *                       its contents on entry do not matter
- * Results do not depend on the launch configuration: every reduction is exact
- * (integer fixed point) or runs in a fixed order.  Runs that share a workspace
- * or outputs must not overlap in time. */
+ * Results do not depend on the launch configuration: counts are exact
+ * integers and every FP64 sum (neighbourhood sums, energy totals, the
+ * per-label sums of the parameter update) is taken in a fixed order set by the
+ * graph alone.  Runs that share a workspace or outputs must not overlap in
+ * time. */
 pmrf_status pmrf_em_run(const pmrf_hoods *hoods, const void *d_hoodbuf, const double *d_y, int32_t *d_labels,
                         double *d_mu, double *d_sigma, double *d_hood_energy, double *d_trace, int64_t *d_iter_stats,
                         int64_t *d_counters, void *d_ws, int64_t ws_bytes, const pmrf_em_params *params,
@@ -211,10 +213,13 @@ pmrf_status pmrf_em_batch(int32_t B, const pmrf_em_item *items, void *d_ws, int6
 /* ------------------------------------------------------------------------
  * Launch configuration (does not change any result, only speed: every
  * reduction order is fixed by the graph, not by the launch shape).
- *  mode: 0 = automatic (currently 1); 1 = the run's kernels are captured once
- *        per distinct argument set into a HIP graph (kept in a small cache) and
- *        the graph is replayed on the caller's stream; the iteration kernel has
- *        one block per superchunk (40 work packets) of every graph;
+ *  mode: 0 = automatic: an argument set runs as direct launches (as mode 3)
+ *        the first time it is seen and as in mode 1 from its second run on, so
+ *        one-off argument sets never pay a graph capture;
+ *        1 = the run's kernels are captured once per distinct argument set
+ *        into a HIP graph (a cache of the 128 most recent sets) and the graph
+ *        is replayed on the caller's stream; the iteration kernel has one block
+ *        per superchunk (40 work packets) of every graph;
  *        2 = as 1, but the iteration kernel is a persistent grid of
  *        blocks_per_cu blocks per compute unit that walk all superchunks;
  *        3 = direct launches on the caller's stream (one block per superchunk).
@@ -233,6 +238,10 @@ typedef struct {
 
 pmrf_status pmrf_set_launch(const pmrf_launch *launch);
 pmrf_status pmrf_get_launch(pmrf_launch *launch);
+
+/* Counts since the library was loaded (host ints): runs that captured a new
+ * HIP graph, runs replayed from the graph cache, runs launched directly. */
+pmrf_status pmrf_launch_stats(int64_t *captures, int64_t *replays, int64_t *direct);
 
 /* ------------------------------------------------------------------------
  * Kernel timing for measurement.  Between pmrf_profile_begin and
@@ -282,7 +291,7 @@ pmrf_status pmrf_profile_end(double *total_ms, int64_t *launches);
  * >= k in either image are not counted); 1 <= k <= 16.  With a = the
  * segmentation and b = the ground truth these are the TP, TN, FP and FN counts
  * of the verification metrics (precision, recall, accuracy) and the void
- * fraction of the porosity (Sec. 4.1.2).  Stream-ordered.
+ * fraction of the porosity (Sec. 4.2.1).  Stream-ordered.
  * ------------------------------------------------------------------------ */
 pmrf_status pmrf_image_graph_workspace_bytes(int32_t width, int32_t height, int32_t n, int64_t *bytes);
 pmrf_status pmrf_image_graph(const int32_t *d_regions, const uint8_t *d_pixels, int32_t width, int32_t height,

@@ -2,7 +2,7 @@
 definitions: the region adjacency graph and region means of an oversegmented
 image (the graph the optimisation takes, Sec. 5; the input of Alg. 2), the
 labels painted back onto the pixels (its output), and the confusion counts
-and verification metrics of Sec. 4.1.2.
+and verification metrics of Sec. 4.2.1.
 
 TEST INFRASTRUCTURE ONLY (imported by ``tests/`` and ``bench.py``'s CPU leg;
 the product path never imports it, and it imports nothing from the product).
@@ -95,7 +95,7 @@ def confusion(a: np.ndarray, b: np.ndarray, k: int) -> np.ndarray:
 
 
 def scores(counts: np.ndarray, positive: int = 1, void: int = 0) -> dict:
-    """Sec. 4.1.2: precision TP/(TP+FP), recall TP/(TP+FN), accuracy
+    """Sec. 4.2.1: precision TP/(TP+FP), recall TP/(TP+FN), accuracy
     (TP+TN)/(TP+TN+FP+FN) for the positive label (rows: segmentation, columns:
     ground truth), and porosity = void volume / total volume of the
     segmentation."""

@@ -1456,6 +1456,7 @@ constexpr int kModeGraph = 1, kModePersistent = 2, kModeDirect = 3;
 
 struct LaunchShape {
   int mode, waves_per_block, tiles_per_wave, blocks_per_cu;
+  bool automatic;  // mode 0: graph replay from an argument set's second run on
 };
 
 LaunchShape resolve_shape() {
@@ -1463,20 +1464,27 @@ LaunchShape resolve_shape() {
   LaunchShape s{g_launch.mode > 0 ? g_launch.mode : kModeGraph,
                 g_launch.waves_per_block > 0 ? g_launch.waves_per_block : 4,
                 g_launch.tiles_per_wave > 0 ? g_launch.tiles_per_wave : 1,
-                g_launch.blocks_per_cu > 0 ? g_launch.blocks_per_cu : 5};
+                g_launch.blocks_per_cu > 0 ? g_launch.blocks_per_cu : 5, g_launch.mode == 0};
   return s;
 }
 
-// Instantiated HIP graphs of recent argument sets (most recent first).
+// Instantiated HIP graphs of recent argument sets (most recent first).  In
+// the automatic mode an argument set runs as direct launches the first time it
+// is seen and is captured on its second run, so one-off sets (a serving step,
+// whose trace offsets and starting flags change every call) never pay a
+// capture; the keys seen once are remembered in a bounded list.
 struct GraphEntry {
   std::string key;
   hipGraphExec_t exec;
   hipEvent_t done;  // recorded after each replay: the entry is idle once it completes
 };
-constexpr size_t kGraphCacheSize = 16;
+constexpr size_t kGraphCacheSize = 128;
+constexpr size_t kSeenKeys = 1024;
 std::mutex g_graph_mu;
 std::list<GraphEntry> g_graphs;
+std::list<std::string> g_seen;  // keys run once as direct launches (most recent first)
 std::map<int, hipStream_t> g_capture_streams;
+int64_t g_captures = 0, g_replays = 0, g_direct = 0;
 
 hipStream_t capture_stream(int dev) {
   auto it = g_capture_streams.find(dev);
@@ -1761,7 +1769,11 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
   // Direct launches when asked for, or while kernel timing is on (the timing
   // events sit between launches); otherwise one cached HIP graph per distinct
   // argument set, replayed on the caller's stream.
-  if (shape.mode == kModeDirect || events) return enqueue(stream);
+  if (shape.mode == kModeDirect || events) {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    ++g_direct;
+    return enqueue(stream);
+  }
   std::string key;
   auto put = [&](const void *p, size_t n) { key.append(static_cast<const char *>(p), n); };
   put(&B, sizeof B);
@@ -1787,7 +1799,19 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
       entry = &g_graphs.front();
       break;
     }
+  if (!entry && shape.automatic) {
+    // automatic mode: the first run of an argument set is direct
+    auto seen = std::find(g_seen.begin(), g_seen.end(), key);
+    if (seen == g_seen.end()) {
+      g_seen.push_front(key);
+      if (g_seen.size() > kSeenKeys) g_seen.pop_back();
+      ++g_direct;
+      return enqueue(stream);
+    }
+    g_seen.erase(seen);
+  }
   if (!entry) {
+    ++g_captures;
     hipStream_t cap = capture_stream(dev);
     if (!cap) return fail(PMRF_EDEVICE, "could not create the capture stream");
     HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
@@ -1815,6 +1839,7 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
     g_graphs.push_front(GraphEntry{key, exec, done});
     entry = &g_graphs.front();
   }
+  ++g_replays;
   HIP_TRY(hipGraphLaunch(entry->exec, stream));
   HIP_TRY(hipEventRecord(entry->done, stream));
   return PMRF_OK;
@@ -1889,6 +1914,16 @@ extern "C" pmrf_status pmrf_get_launch(pmrf_launch *l) {
   if (!l) return fail(PMRF_EINVAL, "launch is NULL");
   std::lock_guard<std::mutex> lk(g_launch_mu);
   *l = g_launch;
+  return PMRF_OK;
+}
+
+extern "C" pmrf_status pmrf_launch_stats(int64_t *captures, int64_t *replays, int64_t *direct) {
+  clear_error();
+  if (!captures || !replays || !direct) return fail(PMRF_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  *captures = g_captures;
+  *replays = g_replays;
+  *direct = g_direct;
   return PMRF_OK;
 }
 

@@ -1,7 +1,7 @@
 // Image in, segmentation out: the region adjacency graph and region means of
 // an oversegmented image (the graph the EM loop consumes), labels painted back
 // onto the pixels, and the confusion counts behind the paper's verification
-// metrics (Sec. 4.1.2).
+// metrics (Sec. 4.2.1).
 //
 // The graph: regions u != v are adjacent when some pixel of u and some pixel
 // of v are horizontal or vertical neighbours (4-connectivity); the CSR is

@@ -38,6 +38,7 @@ EXPORTED = (
     "pmrf_em_batch_workspace_bytes", "pmrf_em_batch", "pmrf_set_launch", "pmrf_get_launch",
     "pmrf_profile_begin", "pmrf_profile_end", "pmrf_image_graph_workspace_bytes", "pmrf_image_graph",
     "pmrf_labels_to_pixels", "pmrf_confusion", "pmrf_volume_graph_workspace_bytes", "pmrf_volume_graph",
+    "pmrf_launch_stats",
 )
 
 
@@ -93,6 +94,7 @@ def _load():
     lib.pmrf_em_batch.argtypes = [c_int32, P(EmItem), c_void_p, c_int64, c_void_p]
     lib.pmrf_set_launch.argtypes = [P(Launch)]
     lib.pmrf_get_launch.argtypes = [P(Launch)]
+    lib.pmrf_launch_stats.argtypes = [P(c_int64), P(c_int64), P(c_int64)]
     lib.pmrf_profile_begin.argtypes = []
     lib.pmrf_profile_end.argtypes = [P(c_double), P(c_int64)]
     lib.pmrf_image_graph_workspace_bytes.argtypes = [c_int32, c_int32, c_int32, P(c_int64)]
@@ -270,6 +272,14 @@ def pmrf_get_launch():
             "blocks_per_cu": out.blocks_per_cu}
 
 
+def pmrf_launch_stats():
+    """{captures, replays, direct}: runs since load that captured a HIP graph,
+    replayed one from the cache, or launched directly."""
+    c, r, d = c_int64(), c_int64(), c_int64()
+    _check(lib.pmrf_launch_stats(ctypes.byref(c), ctypes.byref(r), ctypes.byref(d)))
+    return {"captures": c.value, "replays": r.value, "direct": d.value}
+
+
 def pmrf_profile_begin():
     _check(lib.pmrf_profile_begin())
 
@@ -282,9 +292,10 @@ def pmrf_profile_end():
 
 
 # Launch shapes the autotuner tries: (mode, waves_per_block, tiles_per_wave,
-# blocks_per_cu).  Graph replay with 2, 4 or 8 waves per block, and the
-# persistent grid with 4 or 8 resident blocks per compute unit.
-AUTOTUNE_SHAPES = ((1, 4, 0, 0), (1, 2, 0, 0), (1, 8, 0, 0), (2, 4, 0, 4), (2, 4, 0, 8))
+# blocks_per_cu).  Graph replay with 2, 4 or 8 waves per block, the
+# persistent grid with 4 or 8 resident blocks per compute unit, and direct
+# launches.
+AUTOTUNE_SHAPES = ((1, 4, 0, 0), (1, 2, 0, 0), (1, 8, 0, 0), (2, 4, 0, 4), (2, 4, 0, 8), (3, 4, 0, 0))
 
 
 def autotune_launch(run, shapes=AUTOTUNE_SHAPES, reps=3, sync=None, clock=time.perf_counter):
@@ -415,6 +426,9 @@ def pmrf_volume_graph_workspace_bytes(width, height, depth, n) -> int:
     return b.value
 
 
+_nnz_seen: dict = {}  # (width, height, depth, n) -> adjacency entries of the last call
+
+
 def image_graph(regions, pixels, n, ws=None, stream=None):
     """Region adjacency graph and region means of an oversegmented image
     (``regions`` int32 and ``pixels`` uint8 device tensors of shape
@@ -435,7 +449,12 @@ def image_graph(regions, pixels, n, ws=None, stream=None):
     s = _stream(stream, dev)
     row_ptr = torch.empty(n + 1, dtype=torch.int32, device=dev)
     means = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
-    cap = max(12, 6 * n)  # a 4-connected region graph is planar (at most 3n - 6 edges); volumes may need more
+    # First capacity: a 4-connected region graph is planar (at most 3n - 6
+    # edges, 6n entries); regions of a volume meet about 14 others on average
+    # (3-D cells), so 16n there.  The entry count of the last call with the
+    # same shape is kept, so a repeated call never needs a second pass.
+    key = (width, height, depth, int(n))
+    cap = max(12, 6 * n if depth == 1 else 16 * n, _nnz_seen.get(key, 0))
     nnz = c_int64()
     while True:
         col = torch.empty(cap, dtype=torch.int32, device=dev)
@@ -449,8 +468,10 @@ def image_graph(regions, pixels, n, ws=None, stream=None):
                                          ws.data_ptr(), ws.numel(), s)
         if code == PMRF_ENOMEM and nnz.value > cap:
             cap = nnz.value
+            _nnz_seen[key] = cap
             continue
         _check(code)
+        _nnz_seen[key] = max(_nnz_seen.get(key, 0), nnz.value)
         return row_ptr, col[: nnz.value], means[:n]
 
 
@@ -479,7 +500,7 @@ def confusion(a, b, k, stream=None):
 
 
 def segmentation_scores(counts, positive=1, void=0):
-    """The verification metrics of the paper (Sec. 4.1.2) from confusion
+    """The verification metrics of the paper (Sec. 4.2.1) from confusion
     counts (rows: segmentation, columns: ground truth): precision, recall and
     accuracy of the ``positive`` label, and the porosity of the segmentation
     (share of pixels labelled ``void``)."""

@@ -5,9 +5,12 @@ arrive over time.  The loop keeps a set of active requests whose graph and
 label state stay resident on the device, and advances all of them together,
 ``iters_per_step`` EM iterations per batched call.  Between steps it retires
 finished requests (freeing their memory) and admits arrived ones while the
-device footprint of the active set, including the batch workspace, stays
-within ``hbm_budget`` bytes.  Neighbourhoods of arriving requests are built on
-host worker threads while the device steps.
+device footprint stays within ``hbm_budget`` bytes: the requests' own buffers
+plus the exact workspace of the next batched call over the active set and the
+candidate (``pmrf_em_batch_workspace_bytes``).  A request that could not fit
+even alone is refused on its own (``Request.error``) and the others go on.
+Neighbourhoods of arriving requests are built on host worker threads while the
+device steps.
 
 Splitting a request's iterations over several batched calls gives the same
 labels, parameters, energy trace and neighbourhood sums as one call with all
@@ -55,6 +58,7 @@ class Request:
     build_s: float = 0.0
     done_iters: int = 0
     result: dict | None = None
+    error: str | None = None  # set when the request was refused
 
 
 def threshold_start(y, L):
@@ -62,7 +66,8 @@ def threshold_start(y, L):
 
 
 class GpuExecutor:
-    """Device side of the server: one pmrf.Problem per active request."""
+    """Device side of the server: one pmrf.Problem per active request, one
+    batch workspace sized exactly for each step."""
 
     def __init__(self, device="cuda"):
         import torch
@@ -86,54 +91,62 @@ class GpuExecutor:
         prob.prepare(full, workspace=False)  # trace and statistics buffers for the whole request
         prob.trace.zero_()
         prob.iter_stats.zero_()
-        return {"prob": prob, "first": True}
+        return {"prob": prob, "first": True, "hoods": hoods}
 
     def footprint(self, req: Request, hoods) -> int:
-        """Exact device bytes one request holds while active (its share of the
-        batch workspace included)."""
+        """Exact device bytes of one request's own buffers while it is active
+        (the batch workspace is counted separately, by ``workspace_need``)."""
         pm = self.pmrf
         n1, H1, T = max(1, req.n), max(1, hoods.H), max(1, req.iters)
-        params = pm.pmrf_em_params(L=req.L, beta=req.beta, max_iters=req.iters)
 
         def t(nbytes):  # torch allocations are rounded to 512 bytes
             return (nbytes + 511) // 512 * 512
 
-        own = (t(max(256, hoods.device_bytes)) + t(8 * n1) + t(4 * n1) + 2 * t(8 * req.L) + t(8 * H1)
-               + t(8 * pm.NCOUNTERS) + t(8 * T) + t(16 * T))
-        return own + pm.pmrf_em_workspace_bytes(hoods, params)  # plus its share of the batch workspace
+        return (t(max(256, hoods.device_bytes)) + t(8 * n1) + t(4 * n1) + 2 * t(8 * req.L) + t(8 * H1)
+                + t(8 * pm.NCOUNTERS) + t(8 * T) + t(16 * T))
+
+    def _params(self, req: Request, k: int, first: bool):
+        todo = min(k, req.iters - req.done_iters)
+        return self.pmrf.pmrf_em_params(L=req.L, beta=req.beta, max_iters=todo, init_from_labels=first,
+                                        early_exit=req.early_exit)
+
+    def workspace_need(self, entries: list, k: int) -> int:
+        """Exact bytes of the workspace of the next batched call over
+        ``entries`` = [(request, hoods)] (the library's own sizing)."""
+        if not entries:
+            return 0
+        pm = self.pmrf
+        items = [pm.EmItem(h.handle.value, 0, 0, 0, 0, 0, 0, 0, 0, 0, self._params(r, k, False)) for r, h in entries]
+        return (pm.pmrf_em_batch_workspace_bytes(items) + 511) // 512 * 512
 
     def step(self, active: list, k: int):
         """Advance every active request by min(k, remaining) iterations in one
         batched call; returns the iterations done per request."""
         pm, torch = self.pmrf, self.torch
-        items, steps = [], []
+        items = []
         for req, slot in active:
             prob = slot["prob"]
-            todo = min(k, req.iters - req.done_iters)
-            params = pm.pmrf_em_params(L=req.L, beta=req.beta, max_iters=todo, init_from_labels=slot["first"],
-                                       early_exit=req.early_exit)
-            it = prob.item(params)
+            it = prob.item(self._params(req, k, slot["first"]))
             it.d_trace = prob.trace.data_ptr() + 8 * req.done_iters
             it.d_iter_stats = prob.iter_stats.data_ptr() + 16 * req.done_iters
             items.append(it)
-            steps.append(todo)
             slot["first"] = False
         need = pm.pmrf_em_batch_workspace_bytes(items)
-        if self.ws is None or self.ws.numel() < need:
+        if self.ws is None or self.ws.numel() != need:
+            self.ws = None  # release before allocating: the footprint is the exact need
             self.ws = torch.empty(need, dtype=torch.uint8, device=self.device)
         pm.pmrf_em_batch(items, self.ws)
-        torch.cuda.synchronize(self.device)
+        # one copy back for every request's counters (it waits for the batch)
+        c = torch.stack([slot["prob"].counters for _, slot in active]).cpu().numpy()
         out = []
-        for (req, slot), todo in zip(active, steps):
-            c = slot["prob"].counters.cpu().numpy()
-            if c[pm.CTR_STATUS] != 0:
-                raise pm.PmrfError(int(c[pm.CTR_STATUS]), f"request {req.rid}: device-reported error")
-            out.append(int(c[pm.CTR_ITERS]))
+        for (req, slot), row in zip(active, c):
+            if row[pm.CTR_STATUS] != 0:
+                raise pm.PmrfError(int(row[pm.CTR_STATUS]), f"request {req.rid}: device-reported error")
+            out.append(int(row[pm.CTR_ITERS]))
         return out
 
     def close(self, req: Request, slot) -> dict:
         prob = slot["prob"]
-        self.torch.cuda.synchronize(self.device)
         it = req.done_iters
         res = {"x": prob.labels[: req.n].cpu().numpy(), "mu": prob.mu.cpu().numpy(),
                "sigma": prob.sigma.cpu().numpy(), "S": prob.hood_energy[: prob.hoods.H].cpu().numpy(),
@@ -158,6 +171,7 @@ class ServeStats:
     max_footprint: int
     steps: int
     build_s_mean: float
+    rejected: int = 0
 
 
 class Server:
@@ -177,8 +191,9 @@ class Server:
         now = lambda: self.clock() - t0
         builds: dict[int, cf.Future] = {}
         queue: list[Request] = []  # arrived, waiting for admission
-        active: list[tuple[Request, dict, int]] = []  # (request, slot, footprint)
+        active: list[tuple[Request, dict, int]] = []  # (request, slot, own footprint)
         done: list[Request] = []
+        self.rejected: list[Request] = []
         evals = 0
         steps = 0
         max_active = 0
@@ -189,15 +204,17 @@ class Server:
             h = self.ex.build(req)
             return h, time.perf_counter() - b0
 
-        while len(done) < len(pending):
+        while len(done) + len(self.rejected) < len(pending):
             t = now()
             while i < len(pending) and pending[i].arrival <= t:
                 req = pending[i]
                 builds[req.rid] = self.pool.submit(build, req)
                 queue.append(req)
                 i += 1
-            # admission, in arrival order, while the footprint fits
-            used = sum(fp for _, _, fp in active)
+            # admission, in arrival order, while the requests' own buffers and
+            # the next call's workspace fit
+            own = sum(fp for _, _, fp in active)
+            entries = [(r, s["hoods"]) for r, s, _ in active]
             still = []
             for req in queue:
                 fut = builds[req.rid]
@@ -206,18 +223,23 @@ class Server:
                     continue
                 hoods, req.build_s = fut.result()
                 fp = self.ex.footprint(req, hoods)
-                if fp > self.budget:
-                    raise ValueError(f"request {req.rid} needs {fp} bytes, above the budget {self.budget}")
-                if used + fp > self.budget:
+                if fp + self.ex.workspace_need([(req, hoods)], self.k) > self.budget:
+                    req.error = f"request {req.rid} needs more than the budget of {self.budget} bytes alone"
+                    req.finished = now()
+                    self.rejected.append(req)
+                    del builds[req.rid]
+                    continue
+                if own + fp + self.ex.workspace_need(entries + [(req, hoods)], self.k) > self.budget:
                     still.append(req)
                     continue
                 slot = self.ex.open(req, hoods)
+                slot.setdefault("hoods", hoods)
                 req.admitted = now()
                 active.append((req, slot, fp))
-                used += fp
+                entries.append((req, hoods))
+                own += fp
                 del builds[req.rid]
             queue = still
-            self.footprint_log.append(used)
             max_active = max(max_active, len(active))
             if not active:
                 # idle: wait for the next arrival or build
@@ -226,6 +248,7 @@ class Server:
                 elif i < len(pending):
                     self.sleep(max(0.0, pending[i].arrival - now()))
                 continue
+            self.footprint_log.append(own + self.ex.workspace_need(entries, self.k))
             did = self.ex.step([(r, s) for r, s, _ in active], self.k)
             steps += 1
             keep = []
@@ -240,9 +263,11 @@ class Server:
                     keep.append((req, slot, fp))
             active = keep
         wall = now()
-        lat = np.array([r.finished - r.arrival for r in done])
+        lat = np.array([r.finished - r.arrival for r in done]) if done else np.zeros(1)
         return ServeStats(requests=len(done), wall_s=wall, p50_s=float(np.percentile(lat, 50)),
                           p99_s=float(np.percentile(lat, 99)), mean_s=float(lat.mean()),
-                          throughput_rps=len(done) / wall, evals_per_s=evals / wall, max_active=max_active,
+                          throughput_rps=len(done) / wall if wall > 0 else 0.0, evals_per_s=evals / wall if wall > 0 else 0.0,
+                          max_active=max_active,
                           max_footprint=max(self.footprint_log) if self.footprint_log else 0, steps=steps,
-                          build_s_mean=float(np.mean([r.build_s for r in done])))
+                          build_s_mean=float(np.mean([r.build_s for r in done])) if done else 0.0,
+                          rejected=len(self.rejected))

@@ -65,20 +65,57 @@ def compare_runs(gpu, ref, what, check_labels=True):
     assert gpu["total_near_ties"] == ref["total_near_ties"], what
 
 
-def end_to_end(g: synth.GraphInput, L, beta, iters, what, device="cuda", **kw):
-    """Same start on both sides, ``iters`` iterations each, full comparison."""
-    x0, mu0, s0 = init_state(g, L)
+def end_to_end(g: synth.GraphInput, L, beta, iters, what, device="cuda", start=None, **kw):
+    """Same start on both sides, ``iters`` iterations each, full comparison.
+
+    Without near ties in the oracle's run every label must match.  With near
+    ties (owner gap below 1e-9) the two runs may legitimately resolve a tied
+    vertex differently and drift apart afterwards; if the full comparison then
+    fails, the run must still pass the lockstep comparison (both sides fed the
+    device's state every iteration, labels compared at every vertex whose gap is
+    clear), and the first iteration where the independent runs' labels differ
+    must be one with a near tie.  ``start`` = (x0, mu0, sigma0) overrides the
+    threshold start."""
+    x0, mu0, s0 = start if start is not None else init_state(g, L)
     og = oracle.OracleGraph(g.n, g.row_ptr, g.col_idx)
     ref = og.em_run(g.y, L, beta, x0, mu0, s0, iters, **kw)
     prob = pmrf.Problem(g.n, g.row_ptr, g.col_idx, g.y, L, device)
     gpu = gpu_run(prob, x0, mu0, s0, beta=beta, max_iters=iters, **kw)
-    compare_runs(gpu, ref, what, check_labels=ref["total_near_ties"] == 0)
+    if ref["total_near_ties"] == 0:
+        compare_runs(gpu, ref, what)
+        return gpu, ref
+    try:
+        compare_runs(gpu, ref, what)
+        return gpu, ref
+    except AssertionError:
+        pass
+    assert not kw.get("init_from_labels"), f"{what}: near-tie fallback expects explicit starting parameters"
+    # the first iteration at which the independent runs' labels differ
+    first = None
+    xo, mo, so = np.asarray(x0), np.asarray(mu0), np.asarray(s0)
+    xg, mg, sg = xo, mo, so
+    for t in range(ref["iters"]):
+        r = og.em_step(g.y, L, beta, xo, mo, so)
+        d = gpu_run(prob, xg, mg, sg, beta=beta, max_iters=1)
+        if not np.array_equal(r["x"], d["x"]):
+            first = t
+            assert r["near_ties"] > 0, f"{what}: runs diverge at t={t} without a near tie"
+            break
+        xo, mo, so = r["x"], r["mu"], r["sigma"]
+        xg, mg, sg = d["x"], d["mu"], d["sigma"]
+    assert first is not None, f"{what}: stepwise runs agree but the full runs differ"
+    lockstep(g, L, beta, ref["iters"], what, device, start=(x0, mu0, s0))
     return gpu, ref
 
 
-def lockstep(g: synth.GraphInput, L, beta, iters, what, device="cuda"):
-    """Feed both sides the GPU's state each iteration; compare one step."""
-    x, mu, s = init_state(g, L)
+def lockstep(g: synth.GraphInput, L, beta, iters, what, device="cuda", start=None):
+    """Feed both sides the GPU's state each iteration; compare one step.
+
+    Labels are compared at every vertex whose oracle owner gap is at least
+    1e-9; at a near-tie vertex the device's label must still be one of the
+    labels within 1e-9 of the minimum energy.  Parameters are compared
+    whenever the labels agree everywhere."""
+    x, mu, s = start if start is not None else init_state(g, L)
     og = oracle.OracleGraph(g.n, g.row_ptr, g.col_idx)
     prob = pmrf.Problem(g.n, g.row_ptr, g.col_idx, g.y, L, device)
     ties_seen = 0
@@ -89,11 +126,32 @@ def lockstep(g: synth.GraphInput, L, beta, iters, what, device="cuda"):
         clear = gaps >= TIE
         ties_seen += int((~clear).sum())
         assert np.array_equal(gpu["x"][clear], ref["x"][clear]), f"{what} t={t}: labels differ"
+        if (~clear).any():
+            tied = np.flatnonzero(~clear)
+            E = vertex_energies(og, g, L, beta, x, mu, s, tied)
+            got = E[np.arange(tied.size), gpu["x"][tied]]
+            assert np.all(got - E.min(axis=1) < TIE), f"{what} t={t}: a near-tie label is not a minimiser"
         assert gpu["near_ties"][0] == ref["near_ties"], (what, t)
         assert_close(gpu["S"], ref["S"], f"{what} t={t} S_h")
         assert_close(gpu["trace"], [ref["T"]], f"{what} t={t} T")
-        if (~clear).sum() == 0:
+        if np.array_equal(gpu["x"], ref["x"]):
             assert_close(gpu["mu"], ref["mu"], f"{what} t={t} mu")
             assert_close(gpu["sigma"], ref["sigma"], f"{what} t={t} sigma")
         x, mu, s = gpu["x"], gpu["mu"], gpu["sigma"]
     return ties_seen
+
+
+def vertex_energies(og: oracle.OracleGraph, g: synth.GraphInput, L, beta, x, mu, s, verts):
+    """Energy of each label at the given vertices' owner elements, from the
+    oracle's per-element minima: E(l) = data(v, l) + beta * #{neighbours u : x_u != l}
+    with the data term written out (the owner element sees every neighbour)."""
+    verts = np.asarray(verts)
+    y = np.asarray(g.y)[verts]
+    mu, s = np.asarray(mu, dtype=np.float64), np.asarray(s, dtype=np.float64)
+    d = y[:, None] - mu[None, :]
+    E = (d * d) / (2.0 * s * s)[None, :] + np.log(s)[None, :]
+    for k, v in enumerate(verts):
+        nb = np.asarray(x)[g.col_idx[g.row_ptr[v]:g.row_ptr[v + 1]]]
+        for l in range(L):
+            E[k, l] += beta * np.count_nonzero(nb != l)
+    return E

@@ -12,7 +12,7 @@ What pins what:
   adjacency-matrix recomputation          in-hood adjacency, owner rule
   scipy.stats.norm.logpdf                 the Gaussian data term
   per-vertex synchronous ICM on the CSR   label update through neighbourhoods
-  exhaustive labellings (n <= 7)          argmin, Potts count, tie rule
+  exhaustive labellings (n <= 8)          argmin, Potts count, tie rule
   numpy mean / std(ddof=0)                parameter update
   classification EM on y (beta = 0)       the whole loop without smoothness
   constructed sequences                   convergence test
@@ -252,11 +252,16 @@ def global_energy(n, edges, D, beta, x):
 
 def check_exhaustive(lib):
     rng = np.random.default_rng(23)
+    # 24 mixed cases (n = 3..7, L = 2..4), then every 8-vertex case at L = 2 and 3
+    sizes = []
     for s in range(24):
         n = 3 + s % 5
         L = 2 + s % 3
         if L ** n > 20000:
             n = 5
+        sizes.append((n, L))
+    sizes += [(8, 2), (8, 2), (8, 3), (8, 3)]
+    for s, (n, L) in enumerate(sizes):
         rp, ci = synth.small_random_graph(500 + s, n, 0.5)
         edges = [(v, u) for v in range(n) for u in ci[rp[v]:rp[v + 1]] if u > v]
         og = oracle.OracleGraph(n, rp, ci, lib=lib)

@@ -6,7 +6,7 @@ import torch
 
 import oracle
 from paper_1809_05018_amd import pmrf, synth
-from tests.gpu_helpers import compare_runs, init_state
+from tests.gpu_helpers import compare_runs, end_to_end, init_state
 
 pytestmark = pytest.mark.gpu
 
@@ -56,7 +56,13 @@ def test_batch_equals_solo_and_oracle():
         x0, mu0, s0 = init_state(g, L)
         ref = oracle.OracleGraph(g.n, g.row_ptr, g.col_idx).em_run(g.y, L, beta, x0, mu0, s0, iters,
                                                                     early_exit=early)
-        compare_runs(probs[idx][0].results(probs[idx][1]), ref, g.name, check_labels=ref["total_near_ties"] == 0)
+        try:
+            compare_runs(probs[idx][0].results(probs[idx][1]), ref, g.name)
+        except AssertionError:
+            # only a near tie may separate the runs; the solo run equals the
+            # batched one bitwise (checked above), so the solo protocol applies
+            assert ref["total_near_ties"] > 0, g.name
+            end_to_end(g, L, beta, iters, g.name, early_exit=early)
 
 
 def test_batch_shapes_and_graph_modes_agree():

@@ -6,7 +6,8 @@ import torch
 import oracle
 from paper_1809_05018_amd import pmrf, synth
 from tests import pins
-from tests.gpu_helpers import (assert_close, compare_runs, end_to_end, gpu_run, init_state, lockstep)
+from tests.gpu_helpers import (TIE, assert_close, compare_runs, end_to_end, gpu_run, init_state, lockstep,
+                               vertex_energies)
 
 pytestmark = pytest.mark.gpu
 
@@ -204,3 +205,85 @@ def test_profile_events_time_each_iteration():
     gpu_run(prob, np.zeros(0, np.int32), [50.0, 150.0], [20.0, 20.0], beta=0.5, max_iters=3)
     ms, launches = pmrf.pmrf_profile_end()
     assert launches == 3 and ms > 0.0
+
+
+# ------------------------------------------------------------------ ties
+def one_step_both(g, L, beta, x, mu, sigma):
+    og = oracle.OracleGraph(g.n, g.row_ptr, g.col_idx)
+    ref = og.em_step(g.y, L, beta, x, mu, sigma, per_element=True)
+    prob = pmrf.Problem(g.n, g.row_ptr, g.col_idx, g.y, L)
+    gpu = gpu_run(prob, x, mu, sigma, beta=beta, max_iters=1)
+    assert gpu["status"] == 0
+    return og, ref, gpu
+
+
+def test_exact_tie_takes_the_lowest_label():
+    """y halfway between two means with equal sigma: both energies are exactly
+    12.5 on both sides, so both take label 0 and count two near ties; the
+    Potts count breaks the same tie towards the neighbours' label."""
+    rp, ci = pins.csr(2, [(0, 1)])
+    g = synth.GraphInput(n=2, row_ptr=rp, col_idx=ci, y=np.array([5.0, 5.0]), name="edge_tie")
+    for beta, x, want, ties in ((0.0, [1, 1], [0, 0], 2), (0.5, [1, 1], [1, 1], 0), (0.5, [0, 1], [1, 0], 0)):
+        _, ref, gpu = one_step_both(g, 2, beta, np.array(x, np.int32), [0.0, 10.0], [1.0, 1.0])
+        assert list(ref["x"]) == want and ref["near_ties"] == ties
+        assert list(gpu["x"]) == want and gpu["near_ties"][0] == ties, (beta, x, gpu["x"], gpu["near_ties"])
+        assert gpu["trace"][0] == ref["T"]
+
+
+def test_exact_ties_general_labels():
+    """Four labels, the tie between labels 1 and 3 only (general-L kernel):
+    lowest tied label on both sides, on a grid where a third of the vertices
+    sit exactly on the tie."""
+    side = 24
+    edges = [(r * side + c, r * side + c + 1) for r in range(side) for c in range(side - 1)]
+    edges += [(r * side + c, (r + 1) * side + c) for r in range(side - 1) for c in range(side)]
+    rp, ci = pins.csr(side * side, edges)
+    rng = np.random.default_rng(41)
+    y = rng.uniform(0, 255, side * side)
+    y[::3] = 5.0
+    g = synth.GraphInput(n=side * side, row_ptr=rp, col_idx=ci, y=y, name="grid_tie_L4")
+    mu, sigma = [100.0, 0.0, 50.0, 10.0], [1.0, 1.0, 1.0, 1.0]
+    x = rng.integers(0, 4, g.n).astype(np.int32)
+    _, ref, gpu = one_step_both(g, 4, 0.0, x, mu, sigma)
+    assert np.all(ref["x"][::3] == 1) and ref["near_ties"] >= g.n // 3
+    assert np.array_equal(gpu["x"], ref["x"]) and gpu["near_ties"][0] == ref["near_ties"]
+    assert_close(gpu["S"], ref["S"], "S_h")
+
+
+@pytest.mark.parametrize("beta", [0.0, 0.5])
+def test_constructed_near_ties(beta):
+    """Intensities a few units in the last place from the midpoint of two
+    means: gaps of 1e-14 or less, which the two sides may round either way.
+    Near-tie counts must agree, labels must agree at every vertex with a clear
+    gap, and at a near tie the device's label must be a minimiser within 1e-9."""
+    rng = np.random.default_rng(43)
+    gi = synth.image_graph(44, 256, 1000, 2)
+    y = gi.y.copy()
+    tied = rng.random(gi.n) < 0.3
+    y[tied] = 125.0 + rng.integers(-4, 5, tied.sum()) * 2.0 ** -45
+    g = synth.GraphInput(n=gi.n, row_ptr=gi.row_ptr, col_idx=gi.col_idx, y=y, name="near_ties")
+    mu, sigma = [80.0, 170.0], [25.0, 25.0]
+    x = synth.threshold_labels(y, 2)
+    og, ref, gpu = one_step_both(g, 2, beta, x, mu, sigma)
+    gaps = ref["gap"][og.owner()]
+    clear = gaps >= TIE
+    assert beta > 0 or (~clear).sum() > 0
+    assert gpu["near_ties"][0] == ref["near_ties"] == int((~clear).sum())
+    assert np.array_equal(gpu["x"][clear], ref["x"][clear])
+    idx = np.flatnonzero(~clear)
+    E = vertex_energies(og, g, 2, beta, x, mu, sigma, idx)
+    assert np.all(E[np.arange(idx.size), gpu["x"][idx]] - E.min(axis=1) < TIE)
+    assert_close(gpu["S"], ref["S"], "S_h")
+    # and over several iterations (the near-tie protocol of end_to_end)
+    end_to_end(g, 2, beta, 8, f"near_ties_beta{beta}", start=(x, np.array(mu), np.array(sigma)))
+
+
+# ------------------------------------------------------- random starting state
+@pytest.mark.parametrize("which,L", [("slice256_1k", 2), ("slice256_1k", 4), ("slice2048_100k", 2),
+                                     ("slice2048_100k", 4)])
+def test_random_start(which, L):
+    """The paper's initialisation: random labels, mu and sigma drawn uniformly
+    from [0, 255] (sigma from [1, 255] so that it is positive)."""
+    g = synth.workload_small() if which == "slice256_1k" else synth.workload_large()
+    x0, mu0, s0 = synth.random_init(900 + L, g.n, L)
+    end_to_end(g, L, 0.5, 20 if which == "slice256_1k" else 30, f"{which}_random_L{L}", start=(x0, mu0, s0))

@@ -20,10 +20,15 @@ class VirtualClock:
 
 
 class OracleExecutor:
-    """Same methods as serve.GpuExecutor; each step costs 1 ms of virtual time."""
+    """Same methods as serve.GpuExecutor; each step costs 1 ms of virtual time.
+    It keeps its own account of what it holds (each open request's buffers and
+    a workspace sized for each step) and the peak of that account."""
 
     def __init__(self, clock):
         self.clock = clock
+        self.live = 0
+        self.ws = 0
+        self.peak = 0
 
     def build(self, req):
         return oracle.OracleGraph(req.n, req.row_ptr, req.col_idx)
@@ -31,12 +36,21 @@ class OracleExecutor:
     def footprint(self, req, og):
         return 1000 + 40 * og.M + 16 * req.n
 
+    def workspace_need(self, entries, k):
+        # grows with the iterations of the step, like the library's history buffer
+        return sum(300 + 24 * og.H + 4 * r.n + 8 * min(k, r.iters - r.done_iters) for r, og in entries)
+
     def open(self, req, og):
         x0 = serve.threshold_start(req.y, req.L)
-        return {"og": og, "x": x0, "mu": np.zeros(req.L), "sigma": np.ones(req.L), "first": True, "trace": []}
+        self.live += self.footprint(req, og)
+        self.peak = max(self.peak, self.live + self.ws)
+        return {"og": og, "x": x0, "mu": np.zeros(req.L), "sigma": np.ones(req.L), "first": True, "trace": [],
+                "fp": self.footprint(req, og)}
 
     def step(self, active, k):
         self.clock.t += 1e-3
+        self.ws = self.workspace_need([(r, s["og"]) for r, s in active], k)
+        self.peak = max(self.peak, self.live + self.ws)
         out = []
         for req, slot in active:
             todo = min(k, req.iters - req.done_iters)
@@ -48,6 +62,7 @@ class OracleExecutor:
         return out
 
     def close(self, req, slot):
+        self.live -= slot["fp"]
         return {"x": slot["x"], "mu": slot["mu"], "sigma": slot["sigma"], "S": slot["S"],
                 "trace": np.array(slot["trace"]), "evals": slot["og"].M * req.L * req.done_iters}
 
@@ -70,11 +85,12 @@ def test_server_results_and_admission(budget_scale, k):
     clock = VirtualClock()
     ex = OracleExecutor(clock)
     reqs = make_requests()
-    biggest = max(ex.footprint(r, ex.build(r)) for r in reqs)
+    biggest = max(ex.footprint(r, og) + ex.workspace_need([(r, og)], k) for r in reqs for og in [ex.build(r)])
     srv = serve.Server(ex, hbm_budget=int(biggest * budget_scale), iters_per_step=k, clock=clock, sleep=clock.sleep)
     stats = srv.run(reqs)
-    assert stats.requests == len(reqs)
+    assert stats.requests == len(reqs) and stats.rejected == 0
     assert max(srv.footprint_log) <= srv.budget
+    assert ex.peak <= srv.budget  # what the executor really held, workspace included
     if budget_scale < 2:
         assert stats.max_active < len(reqs)  # admission held requests back
         assert any(r.admitted > r.arrival for r in reqs)
@@ -89,13 +105,33 @@ def test_server_results_and_admission(budget_scale, k):
     assert stats.p99_s >= stats.p50_s > 0
 
 
-def test_request_above_budget_is_refused():
+def test_request_above_budget_is_refused_alone():
+    """A request that cannot fit even alone is refused on its own; every other
+    request still completes, with the same result as an uninterrupted run."""
     clock = VirtualClock()
     ex = OracleExecutor(clock)
-    reqs = make_requests(count=2)
-    srv = serve.Server(ex, hbm_budget=100, clock=clock, sleep=clock.sleep)
-    with pytest.raises(ValueError):
-        srv.run(reqs)
+    reqs = make_requests(count=6)
+    need = {r.rid: ex.footprint(r, og) + ex.workspace_need([(r, og)], 4) for r in reqs for og in [ex.build(r)]}
+    big = max(need, key=need.get)
+    budget = max(v for k, v in need.items() if k != big)
+    assert need[big] > budget
+    srv = serve.Server(ex, hbm_budget=budget, iters_per_step=4, clock=clock, sleep=clock.sleep)
+    stats = srv.run(reqs)
+    assert stats.rejected == 1 and stats.requests == len(reqs) - 1
+    for r in reqs:
+        if r.rid == big:
+            assert r.result is None and "budget" in r.error
+        else:
+            assert r.error is None and r.done_iters == r.iters
+            og = oracle.OracleGraph(r.n, r.row_ptr, r.col_idx)
+            ref = og.em_run(r.y, r.L, r.beta, serve.threshold_start(r.y, r.L), np.zeros(r.L), np.ones(r.L),
+                            r.iters, init_from_labels=True)
+            assert np.array_equal(r.result["x"], ref["x"])
+    assert ex.peak <= budget
+    # nothing fits: every request is refused and the loop still ends
+    srv = serve.Server(OracleExecutor(clock), hbm_budget=100, clock=clock, sleep=clock.sleep)
+    stats = srv.run(make_requests(count=2))
+    assert stats.requests == 0 and stats.rejected == 2
 
 
 def schedule_reference(req, k):
