@@ -31,6 +31,7 @@ METRIC = "vertex-label energy evals/sec + HBM GB/s % peak; batched vs plain at b
 HBM_PEAK_GBS = 8000.0
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_iter_slice2048_100k_traffic.md")
 BATCH_COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_iter_batch64_traffic.md")
+POWERLAW_COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_iter_powerlaw16_traffic.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_1809_05018_amd", "csrc", "em.hip")
 
 
@@ -86,24 +87,31 @@ def copy_calibration(dev, mib=256, reps=3):
     print(json.dumps({"copy_calibration_bytes": mib << 20, "copies": reps}), flush=True)
 
 
-def cpu_baseline(g, L, beta, iters, x0, M, min_seconds=10.0, max_reps=12):
-    """The oracle's EM loop on the same problem, repeated until about
-    ``min_seconds`` of CPU work; the rate is the mean over the repetitions."""
+def cpu_baseline(g, L, beta, iters, x0, M, runs=3):
+    """The oracle's EM loop on the same problem, on one host core (the process
+    is pinned to one core while it runs): the median of ``runs`` full runs."""
     import numpy as np
 
     import oracle
 
     og = oracle.OracleGraph(g.n, g.row_ptr, g.col_idx)
-    reps, total, ref = 0, 0.0, None
-    while reps < max_reps and (reps == 0 or total < min_seconds):
-        t0 = time.perf_counter()
-        ref = og.em_run(g.y, L, beta, x0, np.zeros(L), np.ones(L), iters, init_from_labels=True)
-        total += time.perf_counter() - t0
-        reps += 1
-    dt = total / reps
+    pinned = None
+    if hasattr(os, "sched_getaffinity"):
+        pinned = os.sched_getaffinity(0)
+        os.sched_setaffinity(0, {min(pinned)})
+    try:
+        times, ref = [], None
+        for _ in range(runs):
+            t0 = time.perf_counter()
+            ref = og.em_run(g.y, L, beta, x0, np.zeros(L), np.ones(L), iters, init_from_labels=True)
+            times.append(time.perf_counter() - t0)
+    finally:
+        if pinned is not None:
+            os.sched_setaffinity(0, pinned)
+    dt = float(np.median(times))
     return ref, {"value": M * L * iters / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
-                 "sample": f"the full workload, {iters} EM iterations, run {reps} times ({total:.1f} s); "
-                           "serial C oracle (-O2), EM loop only",
+                 "sample": f"the full workload, {iters} EM iterations, median of {runs} runs on one pinned core "
+                           f"({sum(times):.1f} s); serial C oracle (-O2), EM loop only",
                  "seconds_per_run": round(dt, 3), "cpu": host_cpu()}
 
 
@@ -125,7 +133,8 @@ def cpu_baseline_parallel(graphs, L, beta, iters, threads):
     """The oracle's EM loop on one graph per host thread (the graphs are
     independent, so this is the embarrassingly parallel CPU rate): the first
     ``threads`` graphs of the workload, ``iters`` iterations each, all at once;
-    graph construction is outside the timing (EM loop only)."""
+    graph construction is outside the timing (EM loop only).  Returns the
+    baseline record and the oracle's results, graph by graph."""
     import concurrent.futures as cf
 
     import numpy as np
@@ -141,17 +150,43 @@ def cpu_baseline_parallel(graphs, L, beta, iters, threads):
     def run(i):
         g = sample[i]
         x0 = synth.threshold_labels(g.y, L)
-        ogs[i].em_run(g.y, L, beta, x0, np.zeros(L), np.ones(L), iters, init_from_labels=True)
-        return ogs[i].M * L * iters
+        return ogs[i].em_run(g.y, L, beta, x0, np.zeros(L), np.ones(L), iters, init_from_labels=True)
 
     t0 = time.perf_counter()
     with cf.ThreadPoolExecutor(len(sample)) as ex:  # the C EM loop runs without the GIL
-        evals = sum(ex.map(run, range(len(sample))))
+        refs = list(ex.map(run, range(len(sample))))
     dt = time.perf_counter() - t0
+    evals = sum(og.M for og in ogs) * L * iters
     return {"value": evals / dt, "unit": "evals/s", "cores": len(sample), "kind": "oracle",
             "sample": f"{len(sample)} of the workload's graphs, one per thread, {iters} EM iterations each "
                       f"({dt:.1f} s wall); serial C oracle (-O2) per graph, EM loop only",
-            "cpu": host_cpu()}
+            "cpu": host_cpu()}, refs
+
+
+def parity_block(gpu, refs):
+    """GPU results against the oracle's, graph by graph (same start, same
+    iterations): labels must be identical unless the oracle counted a near tie
+    (energy gap below 1e-9, where either label is correct and the runs may
+    drift apart); mu, sigma and the energy trace are compared where the labels
+    agree."""
+    import numpy as np
+
+    def rel(a, b):
+        a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+        if a.size == 0:
+            return 0.0
+        return float(np.max(np.abs(a - b) / np.maximum(np.maximum(np.abs(a), np.abs(b)), 1e-300)))
+
+    eq = [bool(np.array_equal(a["x"], b["x"])) for a, b in zip(gpu, refs)]
+    ties = [int(b["total_near_ties"]) for b in refs]
+    same = [i for i, e in enumerate(eq) if e]
+    errs = {k: max([rel(gpu[i][k], refs[i][k]) for i in same] or [0.0]) for k in ("mu", "sigma", "trace")}
+    ok = all(e or t > 0 for e, t in zip(eq, ties)) and all(v <= 1e-10 for v in errs.values()) and all(
+        a["iters"] == b["iters"] for a, b in zip(gpu, refs))
+    return {"graphs": len(refs), "iters": int(refs[0]["iters"]) if refs else 0, "ok": ok,
+            "graphs_labels_bit_exact": sum(eq), "graphs_with_near_ties": sum(t > 0 for t in ties),
+            "near_ties": sum(ties), "mu_rel": errs["mu"], "sigma_rel": errs["sigma"], "trace_rel": errs["trace"],
+            "bar": "labels identical unless the oracle counted a near tie (gap < 1e-9); mu, sigma, trace within 1e-10 relative"}
 
 
 def main():
@@ -161,10 +196,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--iters", type=int, default=30, help="EM iterations per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="default workload only: skip the 64-slice batched-vs-plain leg")
     ap.add_argument("--workload", default="slice2048_100k",
                     choices=["slice2048_100k", "batch64", "powerlaw16", "serving", "image2048", "volume256"],
-                    help="default: the single 100k-region slice; the others print their own JSON line")
+                    help="default: the single 100k-region slice, followed by the 64-slice batched leg; "
+                         "the others print their own JSON line")
     ap.add_argument("--requests", type=int, default=128, help="serving: number of requests")
+    ap.add_argument("--launch", default=None,
+                    help="pin the launch shape 'mode,waves_per_block,blocks_per_cu' instead of autotuning "
+                         "(for profiles of one shape)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (scale for the HBM byte counters)")
     args = ap.parse_args()
@@ -176,24 +217,55 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
-    import torch
+    from paper_1809_05018_amd import synth
 
-    from paper_1809_05018_amd import pmrf, synth
+    workers = max(1, min(16, host_cpu()["cores_available"]))
+    # inputs are drawn before the GPU is touched (worker processes are forked)
+    graphs = None
+    if args.workload == "slice2048_100k":
+        log("generating the 2048x2048 / 100k-region slice")
+        g = synth.workload_large()
+        if not args.no_batch:
+            log("generating 64 slices (sides log-uniform in [512, 2560])")
+            graphs = synth.workload_batch(64, 3, workers=workers)
+    elif args.workload == "batch64":
+        log("generating 64 slices (sides log-uniform in [512, 2560])")
+        graphs = synth.workload_batch(64, 3, workers=workers)
+    elif args.workload == "powerlaw16":
+        log("generating 16 power-law graphs of 500k vertices")
+        graphs = synth.workload_skewed(16, 500_000, 4, workers=workers)
+
+    import torch
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     dev = torch.device("cuda:0")
     if args.copy_calibration:
         return copy_calibration(dev)
     if args.workload in ("batch64", "powerlaw16"):
-        return bench_batched(args, dev)
+        out = batched_leg(args, dev, args.workload, graphs)
+        print(json.dumps(out), flush=True)
+        return
     if args.workload == "serving":
         return bench_serving(args, dev)
     if args.workload in ("image2048", "volume256"):
         return bench_image(args, dev)
+    result = bench_slice(args, dev, g)
+    if graphs is not None:
+        leg = batched_leg(args, dev, "batch64", graphs)
+        result["batched_over_plain"] = leg["batched_over_plain"]
+        result["bitwise_equal_plain_batched"] = leg["bitwise_equal_plain_batched"]
+        result["batch64"] = leg
+    print(json.dumps(result), flush=True)
+
+
+def bench_slice(args, dev, g):
+    """The 100k-region slice: 30 EM iterations per step (the headline figure)."""
+    import numpy as np
+    import torch
+
+    from paper_1809_05018_amd import pmrf, synth
+
     L, beta, iters = 2, 0.5, args.iters
-    log("generating the 2048x2048 / 100k-region slice")
-    g = synth.workload_large()
     x0 = synth.threshold_labels(g.y, L)
     prob = pmrf.Problem(g.n, g.row_ptr, g.col_idx, g.y, L, dev)
     info = prob.hoods.info
@@ -225,6 +297,13 @@ def main():
     elapsed = time.perf_counter() - t0
     out = prob.results(params)
     assert out["status"] == 0, out["status"]
+    # per-step times (each step synchronised on its own), for the median
+    per_step = []
+    for _ in range(10):
+        t = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        per_step.append(time.perf_counter() - t)
     # timed region 2: the same steps with HIP events around every EM-iteration
     # kernel on its stream (the library then launches directly, without a graph)
     pmrf.pmrf_profile_begin()
@@ -251,7 +330,11 @@ def main():
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "slice2048_100k", "image": "2048x2048 two-phase, seed 2", "regions": info.n,
                    "neighbourhoods": info.H, "elements": info.M, "labels": L, "beta": beta, "em_iters": iters,
-                   "mode": "HIP graph of two kernels per EM iteration"},
+                   "mode": "HIP graph, one iteration kernel per EM iteration"},
+        "step_ms_median": float(np.median(per_step)) * 1e3,
+        "per_iteration": {"alg_bytes": b_launch, "us": ms_step * 1e3 / iters,
+                          "frac": b_launch * iters / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                          "note": "algorithmic bytes of all iterations of a step over the whole step's wall time"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "k_iter<2>", "alg_bytes_per_launch": b_launch,
@@ -263,13 +346,9 @@ def main():
         log("timing the serial oracle on the same workload")
         ref, cpu = cpu_baseline(g, L, beta, iters, x0, info.M)
         result["cpu_baseline"] = cpu
-        labels_equal = bool(np.array_equal(out["x"], ref["x"]))
-        rel = lambda a, b: float(np.max(np.abs(np.asarray(a) - np.asarray(b)) / np.abs(np.asarray(b))))
-        result["parity"] = {"labels_bit_exact": labels_equal, "near_ties": ref["total_near_ties"],
-                            "mu_rel": rel(out["mu"], ref["mu"]), "sigma_rel": rel(out["sigma"], ref["sigma"]),
-                            "trace_rel": rel(out["trace"], ref["trace"])}
+        result["parity"] = parity_block([out], [ref])
         result["speedup_vs_oracle"] = value / cpu["value"]
-    print(json.dumps(result), flush=True)
+    return result
 
 
 def build_all(graphs, workers=8):
@@ -282,27 +361,25 @@ def build_all(graphs, workers=8):
         return list(ex.map(lambda g: pmrf.pmrf_build_neighborhoods(g.n, g.row_ptr, g.col_idx), graphs))
 
 
-def bench_batched(args, dev):
+def batched_leg(args, dev, workload, graphs):
     """Many graphs: one pmrf_em_run per graph in sequence ("plain") against one
     pmrf_em_batch over all of them ("batched"), same starting state, same
-    iterations; results must be bitwise equal."""
+    iterations; results must be bitwise equal.  The oracle runs the first 16
+    graphs (all iterations of the slices; all 40 iterations of two power-law
+    graphs) for the CPU baseline and the parity block."""
     import numpy as np
     import torch
 
     from paper_1809_05018_amd import pmrf, synth
 
-    if args.workload == "batch64":
+    if workload == "batch64":
         L, beta, iters = 2, 0.5, 30
-        log("generating 64 slices (sides log-uniform in [512, 2560])")
-        graphs = synth.workload_batch(64, 3)
-        cfg = {"workload": "batch64", "slices": 64, "sides": "log-uniform 512..2560, seed 3",
+        cfg = {"workload": "batch64", "slices": len(graphs), "sides": "log-uniform 512..2560, seed 3",
                "regions_per_slice": "side^2/26.2", "labels": L, "beta": beta, "em_iters": iters}
     else:
         L, beta, iters = 4, 0.8, 40
-        log("generating 16 power-law graphs of 500k vertices")
-        graphs = synth.workload_skewed(16, 500_000, 4)
-        cfg = {"workload": "powerlaw16", "graphs": 16, "vertices": 500_000, "degrees": "P(d)~d^-2.5 on [3,30]",
-               "labels": L, "beta": beta, "em_iters": iters}
+        cfg = {"workload": "powerlaw16", "graphs": len(graphs), "vertices": 500_000,
+               "degrees": "P(d)~d^-2.5 on [3,30]", "labels": L, "beta": beta, "em_iters": iters}
     t0 = time.perf_counter()
     hoods = build_all(graphs)
     log(f"neighbourhoods built in {time.perf_counter() - t0:.1f} s")
@@ -353,24 +430,33 @@ def bench_batched(args, dev):
 
     steps = max(1, min(args.steps, 5))
     # each path runs with the launch shape the autotuner finds fastest for it
-    # (results are independent of the shape)
-    shape_plain, _ = pmrf.autotune_launch(plain, reps=1)
+    # (results are independent of the shape), unless a shape is pinned
+    saved = pmrf.pmrf_get_launch()
+    if args.launch:
+        mode, waves, bpc = (int(v) for v in args.launch.split(","))
+        shape_plain = shape_batch = (mode, waves, 0, bpc)
+        pmrf.pmrf_set_launch(*shape_plain)
+        tune = {}
+    else:
+        shape_plain, _ = pmrf.autotune_launch(plain, reps=1)
     t_plain = timed(plain, steps)
     res_plain = [p.results(params) for p in probs]
-    shape_batch, tune = pmrf.autotune_launch(batched, reps=2)
+    if not args.launch:
+        shape_batch, tune = pmrf.autotune_launch(batched, reps=2)
     t_batch = timed(batched, steps)
     res_batch = [p.results(params) for p in probs]
-    log(f"autotuned launch shapes: plain {shape_plain}, batched {shape_batch} "
+    log(f"launch shapes: plain {shape_plain}, batched {shape_batch} "
         f"({', '.join(f'{k}: {v * 1e3:.2f} ms' for k, v in tune.items())})")
     same = all(np.array_equal(a[k], b[k]) for a, b in zip(res_plain, res_batch) for k in ("x", "mu", "sigma", "trace"))
     pmrf.pmrf_profile_begin()
     batched()
     torch.cuda.synchronize()
     ev_ms, launches = pmrf.pmrf_profile_end()
+    pmrf.pmrf_set_launch(**saved)
     avg = ev_ms * 1e-3 / max(1, launches)
     achieved = b_iter / avg / 1e9
     log(f"plain {t_plain * 1e3:.2f} ms/step, batched {t_batch * 1e3:.2f} ms/step, ratio {t_plain / t_batch:.2f}, "
-        f"k_iter {avg * 1e6:.1f} us")
+        f"iteration kernels {avg * 1e6:.1f} us")
     out = {"metric": METRIC, "value": evals / t_batch, "unit": "evals/s", "n_gpus": 1, "steps": steps,
            "warmup": args.warmup, "ms_per_step": t_batch * 1e3, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic", "config": cfg,
@@ -380,18 +466,24 @@ def bench_batched(args, dev):
                             "fields": "mode, waves_per_block, tiles_per_wave, blocks_per_cu"},
            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": achieved / HBM_PEAK_GBS,
-                        "traffic": measured_traffic(BATCH_COUNTERS_FILE) if args.workload == "batch64" else None,
-                        "kernel": f"k_iter<{4 if L > 2 else 2}>",
-                        "alg_bytes_per_launch": b_iter, "avg_launch_us": avg * 1e6, "launches_timed": launches},
+                        "traffic": measured_traffic(BATCH_COUNTERS_FILE if workload == "batch64"
+                                                    else POWERLAW_COUNTERS_FILE),
+                        "kernel": f"k_iter<{4 if L > 2 else 2}> batched (+ k_iter_packets where a graph has "
+                                  "neighbourhoods above 64 members)",
+                        "alg_bytes_per_launch": b_iter, "avg_launch_us": avg * 1e6, "launches_timed": launches,
+                        "timing": "HIP events around each EM iteration's work kernels, one batched run"},
            "cpu_baseline": None}
     if not args.no_cpu_baseline:
         threads = max(1, min(16, host_cpu()["cores_available"], len(graphs)))
-        # a bounded sample: all iterations of the slices, a few of the large power-law graphs
-        sample_iters = iters if args.workload == "batch64" else 3
-        log(f"timing the oracle on {threads} graphs in parallel ({sample_iters} iterations each)")
-        out["cpu_baseline"] = cpu_baseline_parallel(graphs, L, beta, sample_iters, threads)
-        out["speedup_vs_oracle"] = out["value"] / out["cpu_baseline"]["value"]
-    print(json.dumps(out), flush=True)
+        # a bounded sample: all iterations of 16 slices; all 40 iterations of
+        # two of the large power-law graphs
+        sample = threads if workload == "batch64" else min(2, len(graphs))
+        log(f"timing the oracle on {sample} graphs in parallel ({iters} iterations each)")
+        cpu, refs = cpu_baseline_parallel(graphs, L, beta, iters, sample)
+        out["cpu_baseline"] = cpu
+        out["speedup_vs_oracle"] = out["value"] / cpu["value"]
+        out["parity"] = parity_block(res_batch[: len(refs)], refs)
+    return out
 
 
 def bench_image(args, dev):

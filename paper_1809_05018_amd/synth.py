@@ -223,19 +223,33 @@ def batch_sides(count: int = 64, seed: int = 3, lo: int = 512, hi: int = 2560):
     return [(int(s), int(round(s * s / 26.2))) for s in sides]
 
 
-def workload_batch(count: int = 64, seed: int = 3, scale: float = 1.0):
-    """Uneven slices for the batched path (``scale`` shrinks sides for tests)."""
-    out = []
+def _draw_all(fn, args, workers: int):
+    """fn(*a) for every a in args, in order; with workers > 1 in forked worker
+    processes (each draw has its own seed, so the result is the same)."""
+    if workers <= 1 or len(args) <= 1:
+        return [fn(*a) for a in args]
+    import multiprocessing as mp
+
+    with mp.get_context("fork").Pool(min(workers, len(args))) as pool:
+        return pool.starmap(fn, args, chunksize=1)
+
+
+def workload_batch(count: int = 64, seed: int = 3, scale: float = 1.0, workers: int = 1):
+    """Uneven slices for the batched path (``scale`` shrinks sides for tests).
+    ``workers`` > 1 draws the slices in forked processes: call it before the
+    process touches a GPU."""
+    args = []
     for i, (s, r) in enumerate(batch_sides(count, seed)):
         s2 = max(32, int(round(s * scale)))
         r2 = max(16, int(round(s2 * s2 / 26.2)))
-        out.append(image_graph(seed * 1000 + i, s2, r2, 2, name=f"batch{i}_{s2}"))
-    return out
+        args.append((seed * 1000 + i, s2, r2, 2, f"batch{i}_{s2}"))
+    return _draw_all(image_graph, args, workers)
 
 
-def workload_skewed(count: int = 16, n: int = 500_000, seed: int = 4):
-    """Power-law graphs, L=4 phases."""
-    return [powerlaw_graph(seed * 1000 + i, n, 4, name=f"powerlaw{i}") for i in range(count)]
+def workload_skewed(count: int = 16, n: int = 500_000, seed: int = 4, workers: int = 1):
+    """Power-law graphs, L=4 phases (``workers`` as for ``workload_batch``)."""
+    args = [(seed * 1000 + i, n, 4, 3, 30, 2.5, 20.0, f"powerlaw{i}") for i in range(count)]
+    return _draw_all(powerlaw_graph, args, workers)
 
 
 def serving_requests(count: int = 256, seed: int = 5, rmin: int = 1000, rmax: int = 1_000_000):
