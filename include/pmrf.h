@@ -19,7 +19,8 @@
  *    memory (for example torch tensors' data_ptr() on a ROCm device).
  *  - The caller owns every buffer it passes.  The library owns only the opaque
  *    host object pmrf_hoods (freed with pmrf_hoods_free).  The library never
- *    allocates device memory: buffers it needs come in as a caller workspace.
+ *    allocates device memory at run time: buffers it needs come in as a caller
+ *    workspace (pmrf_em_run_noalloc uses a static device array instead).
  *  - Device work is enqueued on the given HIP stream (hipStream_t passed as
  *    void*, NULL = the null stream) and is asynchronous; results are valid
  *    after the stream is synchronised.  Errors that only the device can see
@@ -184,6 +185,28 @@ pmrf_status pmrf_em_run(const pmrf_hoods *hoods, const void *d_hoodbuf, const do
                         double *d_mu, double *d_sigma, double *d_hood_energy, double *d_trace, int64_t *d_iter_stats,
                         int64_t *d_counters, void *d_ws, int64_t ws_bytes, const pmrf_em_params *params,
                         void *hip_stream);
+
+/* Allocation-free variant of pmrf_em_run, for callers that cannot allocate
+ * device memory: work recorded under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Arguments and results are those of
+ * pmrf_em_run without d_ws / ws_bytes: the workspace is a static device array
+ * of PMRF_NOALLOC_WS_BYTES bytes that the library holds on every GPU it runs
+ * on, until the process ends.  The call allocates nothing (no hipMalloc, no
+ * graph capture, no timing events): its kernels are launched directly on the
+ * stream, and its results are bitwise those of pmrf_em_run.
+ * Errors: as pmrf_em_run, plus PMRF_ENOMEM, returned before any device call,
+ * when the run needs more workspace than PMRF_NOALLOC_WS_BYTES
+ * (pmrf_em_workspace_bytes gives the need; the 100k-region slice at L = 2
+ * needs about 6.5 MB).
+ * Every call on one GPU uses that GPU's one array, which keeps the last call's
+ * contents (a run initialises whatever part of it it reads): calls that
+ * overlap in time on one GPU (other streams or threads) race and must be
+ * serialised by the caller. */
+#define PMRF_NOALLOC_WS_BYTES (64LL << 20)
+pmrf_status pmrf_em_run_noalloc(const pmrf_hoods *hoods, const void *d_hoodbuf, const double *d_y, int32_t *d_labels,
+                                double *d_mu, double *d_sigma, double *d_hood_energy, double *d_trace,
+                                int64_t *d_iter_stats, int64_t *d_counters, const pmrf_em_params *params,
+                                void *hip_stream);
 
 /* ------------------------------------------------------------------------
  * Batched optimisation: many graphs (for example the slices of a volume, which

@@ -1575,7 +1575,10 @@ int lmax_for(int L) { return L <= 2 ? 2 : L <= 4 ? 4 : L <= 8 ? 8 : 16; }
     if (e_ != hipSuccess) return fail(PMRF_EDEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
   } while (0)
 
-pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_bytes, hipStream_t stream) {
+// no_alloc: enqueue the kernels directly, never capturing a HIP graph and
+// never creating timing events (the allocation-free entry point).
+pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_bytes, hipStream_t stream,
+                      bool no_alloc = false) {
   WsPlan plan = plan_workspace(B, items);
   if (!d_ws) return fail(PMRF_EINVAL, "workspace is NULL");
   if (ws_bytes < plan.total) return fail(PMRF_ENOMEM, "workspace smaller than the required size");
@@ -1651,7 +1654,7 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
   for (int i = 0; i < B; ++i) any_init |= desc[i].init_from_labels != 0;
   const int lm = lmax_for(Lmax);
   const size_t lds = (size_t)(kWaveLds * shape.waves_per_block) * 8;
-  const bool events = g_prof.on;
+  const bool events = g_prof.on && !no_alloc;
   // grid of the iteration kernel: one block per superchunk, or in persistent
   // mode a machine-sized grid whose blocks walk the superchunks
   int grid_iter = blocks_iter;
@@ -1769,7 +1772,7 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
   // Direct launches when asked for, or while kernel timing is on (the timing
   // events sit between launches); otherwise one cached HIP graph per distinct
   // argument set, replayed on the caller's stream.
-  if (shape.mode == kModeDirect || events) {
+  if (no_alloc || shape.mode == kModeDirect || events) {
     std::lock_guard<std::mutex> lk(g_graph_mu);
     ++g_direct;
     return enqueue(stream);
@@ -1872,6 +1875,59 @@ extern "C" pmrf_status pmrf_em_run(const pmrf_hoods *hoods, const void *d_hoodbu
   pmrf_status s = check_item(it, -1);
   if (s != PMRF_OK) return s;
   return run_items(1, &it, d_ws, ws_bytes, static_cast<hipStream_t>(hip_stream));
+}
+
+// ------------------------------------------------- allocation-free entry point
+namespace {
+// Workspace of pmrf_em_run_noalloc: one array per GPU the library runs on,
+// held until the process ends.  In host code the name `scratch` is only a
+// host-side stand-in; kernels get its device address, looked up once per
+// device (with that device current) and kept in g_scratch_ptr.
+constexpr int64_t kScratchBytes = PMRF_NOALLOC_WS_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch_ptr;
+
+pmrf_status scratch_address(void **out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) {
+    *out = it->second;
+    return PMRF_OK;
+  }
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return fail(PMRF_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  g_scratch_ptr[dev] = ptr;
+  *out = ptr;
+  return PMRF_OK;
+}
+
+}  // namespace
+
+extern "C" pmrf_status pmrf_em_run_noalloc(const pmrf_hoods *hoods, const void *d_hoodbuf, const double *d_y,
+                                           int32_t *d_labels, double *d_mu, double *d_sigma, double *d_hood_energy,
+                                           double *d_trace, int64_t *d_iter_stats, int64_t *d_counters,
+                                           const pmrf_em_params *params, void *hip_stream) {
+  clear_error();
+  if (!params) return fail(PMRF_EINVAL, "params is NULL");
+  pmrf_em_item it{hoods, d_hoodbuf, d_y, d_labels, d_mu, d_sigma, d_hood_energy, d_trace, d_iter_stats, d_counters,
+                  *params};
+  pmrf_status s = check_item(it, -1);
+  if (s != PMRF_OK) return s;
+  // the size check needs no device, so an oversized request fails before any HIP call
+  const int64_t need = plan_workspace(1, &it).total;
+  if (need > kScratchBytes)
+    return fail(PMRF_ENOMEM, "the run needs " + std::to_string(need) + " bytes of workspace; the static workspace holds " +
+                                 std::to_string(kScratchBytes));
+  void *ws = nullptr;
+  s = scratch_address(&ws);
+  if (s != PMRF_OK) return s;
+  return run_items(1, &it, ws, kScratchBytes, static_cast<hipStream_t>(hip_stream), true);
 }
 
 extern "C" pmrf_status pmrf_em_batch_workspace_bytes(int32_t B, const pmrf_em_item *items, int64_t *bytes) {

@@ -38,7 +38,7 @@ EXPORTED = (
     "pmrf_em_batch_workspace_bytes", "pmrf_em_batch", "pmrf_set_launch", "pmrf_get_launch",
     "pmrf_profile_begin", "pmrf_profile_end", "pmrf_image_graph_workspace_bytes", "pmrf_image_graph",
     "pmrf_labels_to_pixels", "pmrf_confusion", "pmrf_volume_graph_workspace_bytes", "pmrf_volume_graph",
-    "pmrf_launch_stats",
+    "pmrf_launch_stats", "pmrf_em_run_noalloc",
 )
 
 
@@ -90,6 +90,8 @@ def _load():
     lib.pmrf_em_workspace_bytes.argtypes = [c_void_p, P(EmParams), P(c_int64)]
     lib.pmrf_em_run.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                 c_void_p, c_void_p, c_void_p, c_int64, P(EmParams), c_void_p]
+    lib.pmrf_em_run_noalloc.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                        c_void_p, c_void_p, c_void_p, P(EmParams), c_void_p]
     lib.pmrf_em_batch_workspace_bytes.argtypes = [c_int32, P(EmItem), P(c_int64)]
     lib.pmrf_em_batch.argtypes = [c_int32, P(EmItem), c_void_p, c_int64, c_void_p]
     lib.pmrf_set_launch.argtypes = [P(Launch)]
@@ -245,6 +247,24 @@ def pmrf_em_run(hoods: Hoods, hoodbuf, y, labels, mu, sigma, hood_energy, trace,
         _ptr(trace, torch.float64, T, "trace"), _ptr(iter_stats, torch.int64, 2 * T, "iter_stats"),
         _ptr(counters, torch.int64, NCOUNTERS, "counters"), _ptr(ws, torch.uint8, 0, "ws"),
         ws.numel(), ctypes.byref(params), _stream(stream, ws.device)))
+
+
+NOALLOC_WS_BYTES = 64 << 20  # PMRF_NOALLOC_WS_BYTES
+
+
+def pmrf_em_run_noalloc(hoods: Hoods, hoodbuf, y, labels, mu, sigma, hood_energy, trace, iter_stats, counters,
+                        params: EmParams, stream=None):
+    """pmrf_em_run with the library's static per-GPU workspace (allocates nothing)."""
+    import torch
+
+    L, T = params.L, params.max_iters
+    dev = labels.device if isinstance(labels, torch.Tensor) else None
+    _check(lib.pmrf_em_run_noalloc(
+        hoods.handle, _ptr(hoodbuf, torch.uint8, hoods.device_bytes, "hoodbuf"), _ptr(y, torch.float64, hoods.n, "y"),
+        _ptr(labels, torch.int32, hoods.n, "labels"), _ptr(mu, torch.float64, L, "mu"),
+        _ptr(sigma, torch.float64, L, "sigma"), _ptr(hood_energy, torch.float64, hoods.H, "hood_energy"),
+        _ptr(trace, torch.float64, T, "trace"), _ptr(iter_stats, torch.int64, 2 * T, "iter_stats"),
+        _ptr(counters, torch.int64, NCOUNTERS, "counters"), ctypes.byref(params), _stream(stream, dev)))
 
 
 def pmrf_em_batch_workspace_bytes(items) -> int:
