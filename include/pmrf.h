@@ -242,13 +242,18 @@ pmrf_status pmrf_em_batch(int32_t B, const pmrf_em_item *items, void *d_ws, int6
  *        1 = the run's kernels are captured once per distinct argument set
  *        into a HIP graph (a cache of the 128 most recent sets) and the graph
  *        is replayed on the caller's stream; the iteration kernel has one block
- *        per superchunk (40 work packets) of every graph;
+ *        per superchunk of every graph (4, 8 or 16 chunks of 10 work packets,
+ *        set by the graph's size; a single graph of at most 256 superchunks
+ *        whose blocks have at least 4 waves runs one launch per EM iteration,
+ *        the parameter update of the previous iteration included, otherwise a
+ *        one-block parameter-update launch follows each iteration launch);
  *        2 = as 1, but the iteration kernel is a persistent grid of
  *        blocks_per_cu blocks per compute unit that walk all superchunks;
  *        3 = direct launches on the caller's stream (one block per superchunk).
  *        While kernel timing is on (pmrf_profile_begin), runs use direct
  *        launches with the grid of the selected mode.
- *  waves_per_block: 1..16 (0 = automatic: 4, one wave per chunk of 10 packets)
+ *  waves_per_block: 1..16 (0 = automatic: a single graph one wave per chunk
+ *        of its superchunks, a batch 4)
  *  tiles_per_wave: reserved (0)
  *  blocks_per_cu: blocks per compute unit in mode 2 (0 = automatic: 5)
  * ------------------------------------------------------------------------ */

@@ -1,8 +1,6 @@
 // EM optimisation of DPP-PMRF on gfx950 (Alg. 2, EM loop; Sec. 3.2.2 "EM
 // Parameter Estimation").
 //
-// Each EM iteration is two launches.
-//
 // k_iter works through chunks of 10 consecutive work packets (a packet is up to
 // 64 elements of whole neighbourhoods).  For every packet, one lane per element
 // (neighbourhood h, member v) does, for every label l:
@@ -22,13 +20,17 @@
 // convergence window and adds the sum to its lane's energy total.  At the end
 // of a chunk the wave's lane statistics pass through LDS eight values at a
 // time and are summed in a fixed order (eight lanes in order, then DPP moves)
-// into the chunk's row, and the block adds its 4 rows in order into one record
-// per superchunk.
-// There is no cross-block communication and no memory fence inside the launch.
+// into the chunk's row, and the block adds its 16 rows in order into one
+// record per superchunk.
+// There is no cross-block communication and no memory fence inside a launch.
 //
-// k_fold (one block per graph) adds the superchunk records in a fixed order
-// and turns them into the next parameters (mean, standard deviation) and the
-// per-iteration results.
+// The parameter update folds the superchunk records of an iteration in one
+// fixed order (fold_stage1 / fold_stage2) and turns the totals into the next
+// parameters (mean, standard deviation) and the per-iteration results.  For a
+// single graph every block of iteration t's launch folds the records of t - 1
+// itself (so one launch per EM iteration); otherwise k_fold (one block per
+// graph) does it between the iteration launches.  Both fold in the same order,
+// so the results are the same bits.
 //
 // Chunks and their order are fixed by the graph alone, so the results do not
 // depend on the launch shape or on how graphs are batched.
@@ -73,7 +75,12 @@ __device__ __forceinline__ gptr<T> gbl(T *p) {
 __host__ __device__ constexpr int rec_words(int L) { return 3 * L + 4; }
 constexpr int kRecMax = 3 * kMaxLabels + 4;
 
-constexpr int kSuperChunks = 4;    // chunks per block and record (fixed: part of the result's definition)
+// Chunks per superchunk (one block, one statistics record): 4, 8 or 16, the
+// smallest that keeps a graph's records at or below kFoldLanes (one record
+// per virtual thread of the fold, so a single graph's fold fits the iteration
+// launch).  Chosen from the graph alone (superchunk_chunks), so it is part of
+// the result's definition and never depends on the launch shape or the batch.
+constexpr int kMaxSuperChunks = 16;
 constexpr int kGroupTiles = kChunkTiles;  // packets per neighbourhood-sum group (LDS buffer of 64 minima each)
 // Register budgets of the two-label iteration kernels, as resident waves per
 // SIMD: one graph (a single round of waves; the lower budget keeps every value
@@ -99,6 +106,10 @@ struct GraphState {
   int32_t status;
   int32_t iters;
   int32_t map_conv, em_conv;
+  // stop[t & 1]: the run stops before iteration t (the fused launch of
+  // iteration t + 1 reads it while that of t writes the other slot, so no
+  // launch reads a flag that one of its own blocks writes)
+  int32_t stop[2];
   int32_t pad;
   int64_t ties_total;
 };
@@ -124,9 +135,13 @@ struct GraphDev {
   int64_t M;
   int64_t rec_stride;  // words of one record buffer (records of iteration t at rec + (t & 1) * rec_stride)
   int32_t n, H, ntiles, nchunks, nsuper, L, P, W, max_iters, early_exit, init_from_labels;
+  int32_t sc;        // chunks per superchunk (record)
+  int32_t bc;        // chunks per slot-kernel block (a multiple of sc)
+  int32_t nslot;     // superchunks on the slot kernel: [0, nslot); the rest take the packet kernel
+  int32_t slot_end;  // first chunk past the slot kernel's superchunks
   double beta, tol, sigma_min, tie_eps;
-  int32_t block0, nblocks;    // slot-kernel blocks of this graph: superchunks [0, nblocks)
-  int32_t pblock0, pnblocks;  // packet-kernel blocks: superchunks [nblocks, nsuper)
+  int32_t block0, nblocks;    // slot-kernel blocks of this graph: chunks [bc b, bc (b + 1)) of [0, slot_end)
+  int32_t pblock0, pnblocks;  // packet-kernel blocks: superchunks [nslot, nsuper), one each
   int32_t vblock0, vnblocks;  // blocks of this graph in a vertex-parallel launch
   const int32_t *perm;        // processing index -> canonical neighbourhood
 };
@@ -251,56 +266,82 @@ struct LaneStats {
   }
 };
 
-// Totals of a graph's statistics records in a fixed order that does not
-// depend on the block size: 1024 virtual threads; virtual thread i adds
-// records i, i + 1024, i + 2048, ... in that order; each virtual wave of 64
-// combines its lanes with the butterfly, and thread 0 adds the 16 virtual
-// waves in order.
-// Wave w of the calling block plays virtual waves w, w + nw, ...  Every thread
-// of the block must call; on return tot[] is visible to the whole block.
-constexpr int kFoldWaves = 16;
-constexpr int kFoldThreads = 64 * kFoldWaves;
+// Totals of a graph's statistics records in a fixed order that depends on the
+// record count alone (not on the block size):
+//   stage 1: virtual thread v (0 .. 255) adds records v, v + 256, v + 512, ...
+//            in that order, one partial sum per word;
+//   stage 2: for word w, lane k (0 .. 15) of a row of 16 lanes adds the
+//            partials of virtual threads 16 k .. 16 k + 15 in order, and the
+//            16 lanes combine with pair, quad, half-row and row moves (every
+//            lane of the row ends with the same value: a + b and b + a round
+//            alike).
+// A block of nw waves plays virtual wave q (virtual threads 64 q .. 64 q + 63)
+// with its wave q mod nw.  The partials pass through LDS transposed (slot of
+// virtual thread v: 16 (v mod 16) + v / 16), so stage 2 reads consecutive
+// addresses across a row.
+constexpr int kFoldLanes = 256;    // virtual threads of stage 1
+constexpr int kFoldThreads = 256;  // block size of the fold kernels
+constexpr int kFoldGroup = 16;     // words folded per pass (LDS: 16 x 256 doubles)
 
-template <int LMAX>
-__device__ __forceinline__ void fold_records(gptr<const double> rec, int nrec, int L, double *tot,
-                                             double (*part)[kRecMax], int nw, int wave, int lane) {
-  constexpr int WG = rec_words(LMAX) < 16 ? rec_words(LMAX) : 16;  // words per pass
-  const int words = rec_words(L);
-  for (int vw = wave; vw < kFoldWaves; vw += nw) {
-    const int i = vw * 64 + lane;
-    for (int w0 = 0; w0 < words; w0 += WG) {
+__device__ __forceinline__ int fold_slot(int w, int v) { return w * kFoldLanes + (v & 15) * 16 + (v >> 4); }
+
+// Stage 1 for words [w0, w0 + nwords) (nwords <= kFoldGroup) of records laid
+// out word-major (word w of record r at rec[w * R + r]); partials to scr.
+__device__ __forceinline__ void fold_stage1(gptr<const double> rec, int R, int w0, int nwords, double *scr, int nw,
+                                            int wave, int lane) {
+  constexpr int WG = 8;  // loads requested together
+  for (int q = wave; q < kFoldLanes / 64; q += nw) {
+    const int v = q * 64 + lane;
+    for (int wg = 0; wg < nwords; wg += WG) {
       double acc[WG];
 #pragma unroll
       for (int j = 0; j < WG; ++j) acc[j] = 0.0;
-      // two records per pass, all loads issued before any is used (an absent
-      // record reads as 0)
-      for (int r = i; r < nrec; r += 2 * kFoldThreads) {
-        double v0[WG], v1[WG];
-        const bool has1 = r + kFoldThreads < nrec;
+      for (int r = v; r < R; r += kFoldLanes) {
+        double x[WG];
 #pragma unroll
-        for (int j = 0; j < WG; ++j) {
-          const bool wok = w0 + j < words;
-          v0[j] = wok ? rec[(size_t)(w0 + j) * nrec + r] : 0.0;
-          v1[j] = (wok && has1) ? rec[(size_t)(w0 + j) * nrec + r + kFoldThreads] : 0.0;
-        }
+        for (int j = 0; j < WG; ++j) x[j] = wg + j < nwords ? rec[(size_t)(w0 + wg + j) * R + r] : 0.0;
 #pragma unroll
-        for (int j = 0; j < WG; ++j) acc[j] = (acc[j] + v0[j]) + v1[j];
+        for (int j = 0; j < WG; ++j) acc[j] = acc[j] + x[j];
       }
 #pragma unroll
-      for (int j = 0; j < WG; ++j) {
-        const double r = wave_sum(acc[j]);
-        if (lane == 0 && w0 + j < words) part[vw][w0 + j] = r;
-      }
+      for (int j = 0; j < WG; ++j)
+        if (wg + j < nwords) scr[fold_slot(wg + j, v)] = acc[j];
     }
   }
-  __syncthreads();
-  for (int w = threadIdx.x; w < words; w += blockDim.x) {  // thread w: word w over the virtual waves in order
-    double x = 0.0;
+}
+
+// Stage 2 for nwords words whose partials are in scr; totals to tot[0 .. nwords).
+__device__ __forceinline__ void fold_stage2(const double *scr, int nwords, double *tot, int nw, int wave, int lane) {
+  for (int i0 = wave * 64; i0 < 16 * nwords; i0 += nw * 64) {
+    const int i = i0 + lane, w = i >> 4, k = i & 15;
+    double s = 0.0;
+    if (w < nwords) {
+      const double *p = scr + w * kFoldLanes + k;
+      double r[16];
 #pragma unroll
-    for (int k = 0; k < kFoldWaves; ++k) x = x + part[k][w];
-    tot[w] = x;
+      for (int j = 0; j < 16; ++j) r[j] = p[j * 16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) s = s + r[j];
+    }
+    s = s + dpp_f64<kDppSwap1, 0xf>(s);
+    s = s + dpp_f64<kDppSwap2, 0xf>(s);
+    s = s + dpp_f64<kDppHalfMirror, 0xf>(s);
+    s = s + dpp_f64<kDppMirror, 0xf>(s);
+    if (k == 0 && w < nwords) tot[w] = s;
   }
-  __syncthreads();
+}
+
+// Both stages over all words, by every thread of the block; on return tot[]
+// is visible to the whole block.  scr: kFoldGroup * kFoldLanes doubles of LDS.
+__device__ __forceinline__ void fold_all(gptr<const double> rec, int R, int words, double *scr, double *tot, int nw,
+                                         int wave, int lane) {
+  for (int w0 = 0; w0 < words; w0 += kFoldGroup) {
+    const int nwords = min(kFoldGroup, words - w0);
+    fold_stage1(rec, R, w0, nwords, scr, nw, wave, lane);
+    __syncthreads();
+    fold_stage2(scr, nwords, tot + w0, nw, wave, lane);
+    __syncthreads();
+  }
 }
 
 __device__ __forceinline__ void set_label_theta(LabelTheta *s, int l, double mu, double sigma) {
@@ -662,12 +703,20 @@ __device__ void do_large(const Ctx &c, const TileDesc &td, const Theta<LMAX> &th
 // and window values already loaded, used by the chunk fast path.
 constexpr int kPreWindow = 4;  // window values prefetched (larger windows take the plain pass)
 struct HoodPre {
-  int o, s;
+  int p0, p1;  // hood_ptr[h], hood_ptr[h + 1] as loaded (the size is formed where it is used)
   double prev[kPreWindow];
 };
 
 
 __device__ __forceinline__ int bcast(int v, int lane_src) { return __builtin_amdgcn_readlane(v, lane_src); }
+
+// A value that is the same in every lane, moved to scalar registers.
+__device__ __forceinline__ double uniform_f64(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffff));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
 
 // ---------------------------------------------------------------- lean path
 // Per-wave LDS: 512 minima, 64 label-plane words (LARGE packets), and an owner
@@ -884,8 +933,8 @@ __device__ __forceinline__ void lean_hoods(const Ctx &c, int h0, int h1, int gst
     int o = 0, s = 0;
     double prev[kPreWindow];
     if (hb == h0) {
-      o = pre.o - gstart;
-      s = act ? pre.s : 0;
+      o = pre.p0 - gstart;
+      s = act ? pre.p1 - pre.p0 : 0;
 #pragma unroll
       for (int w = 0; w < kPreWindow; ++w) prev[w] = pre.prev[w];
     } else if (act) {
@@ -940,74 +989,103 @@ __device__ __forceinline__ int load_theta(const Ctx &c, Theta<LMAX> &th) {
   return c.st->done;
 }
 
-// Chunk on the slot layout.  The chunk's member ids and adjacency words are
-// requested from the chunk index alone, together with its header; then the
-// label and intensity gathers and the offsets and window values of the chunk's
-// first 64 neighbourhoods; then the element passes, the owner list and the
-// neighbourhood pass.  The slot kernel is given only superchunks without LARGE
-// packets and only windows of at most kPreWindow (the host sends the others to
-// the packet kernel).  Nothing is written when skip is set (the run has ended
-// or is done) or, with READ_DONE, when the run state's done flag is set (read
-// here, after the chunk's loads are requested).  th arrives with the chunk's
-// loads (requested before the kernel's first store).
-template <int LMAX, bool READ_DONE>
-__device__ void chunk_slots(const Ctx &c, int ck, bool skip, const Theta<LMAX> &th, double *row, double *mb,
-                            double *od, int *oa, int lane) {
+// A chunk's loads on the slot layout, requested by chunk_issue and consumed by
+// chunk_run.
+struct ChunkIn {
+  int v[kChunkTiles];
+  uint32_t am[kChunkTiles];
+  uint32_t hw;  // header: dword k in lane k
+  int xv[kChunkTiles];
+  double yv[kChunkTiles];
+  uint32_t ah[kChunkTiles];
+};
+
+constexpr int kHdrDw = sizeof(ChunkHdr) / 4;
+constexpr int kDwElem = offsetof(ChunkHdr, elem_start) / 4, kDwHood = offsetof(ChunkHdr, hood_start) / 4,
+              kDwHend = offsetof(ChunkHdr, hood_end) / 4, kDwFlags = offsetof(ChunkHdr, flags) / 4,
+              kDwOff = offsetof(ChunkHdr, elem_off) / 4;
+__device__ __forceinline__ uint32_t hdr_field(uint32_t hw, int k) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)hw, k);
+}
+
+// Chunk on the slot layout, first half: the chunk's member ids and adjacency
+// words are requested from the chunk index alone, together with its header;
+// then the label and intensity gathers.  Nothing here writes, and nothing
+// waits for more than the slot words each gather needs.
+template <int LMAX>
+__device__ __forceinline__ void chunk_stream(const Ctx &c, int ck, ChunkIn &in, int lane) {
   const int tb = ck * kChunkTiles;
-  const int nt = min(kChunkTiles, c.ntiles - tb);
   // The slot arrays are padded to whole chunks, so every packet slot of the
   // chunk can be read; chunk bases are uniform, each load is base + lane * 4 +
   // an immediate.
   const gptr<const int32_t> svb = c.svid + (size_t)tb * kWave;
   const gptr<const uint32_t> smb = c.smask + (size_t)tb * kWave;
   const unsigned ul = (unsigned)lane;
-  int v[kChunkTiles];
-  uint32_t am[kChunkTiles];
 #pragma unroll
   for (int i = 0; i < kChunkTiles; ++i) {
-    v[i] = svb[i * kWave + ul];
-    am[i] = smb[i * kWave + ul];
+    in.v[i] = svb[i * kWave + ul];
+    in.am[i] = smb[i * kWave + ul];
   }
   // the header: dword k in lane k (one load), fields read out with readlane
   // once it has arrived
-  constexpr int kHdrDw = sizeof(ChunkHdr) / 4;
-  const uint32_t hw = lane < kHdrDw ? gptr<const uint32_t>(c.chdr + ck)[lane] : 0u;
-  auto hdr = [&](int k) { return (uint32_t)__builtin_amdgcn_readlane((int)hw, k); };
-  constexpr int kDwElem = offsetof(ChunkHdr, elem_start) / 4, kDwHood = offsetof(ChunkHdr, hood_start) / 4,
-                kDwHend = offsetof(ChunkHdr, hood_end) / 4, kDwFlags = offsetof(ChunkHdr, flags) / 4,
-                kDwOff = offsetof(ChunkHdr, elem_off) / 4;
-  const int flags = (int)hdr(kDwFlags);
-  const int gstart = (int)hdr(kDwElem), h0 = (int)hdr(kDwHood), hend = (int)hdr(kDwHend);
-  int xv[kChunkTiles];
-  double yv[kChunkTiles];
-  uint32_t ah[kChunkTiles];
+  in.hw = lane < kHdrDw ? gptr<const uint32_t>(c.chdr + ck)[lane] : 0u;
+}
+
+// The label and intensity gathers of a chunk whose slot words chunk_stream
+// requested (each waits only for its own packet's slot words).
+template <int LMAX>
+__device__ __forceinline__ void chunk_gather(const Ctx &c, int ck, ChunkIn &in, int lane) {
+  const int tb = ck * kChunkTiles;
+  const unsigned ul = (unsigned)lane;
+  const int flags = kPrefetchHi<LMAX> ? (int)hdr_field(in.hw, kDwFlags) : 0;
 #pragma unroll
   for (int i = 0; i < kChunkTiles; ++i) {
     // an empty slot reads vertex 0; nothing of an empty slot is used
-    const unsigned vv = (uint32_t)v[i] != kSlotEmpty ? (uint32_t)v[i] & kSlotVidMask : 0u;
-    xv[i] = c.xr[vv];
-    yv[i] = c.y[vv];
-    ah[i] = 0;
+    const unsigned vv = (uint32_t)in.v[i] != kSlotEmpty ? (uint32_t)in.v[i] & kSlotVidMask : 0u;
+    in.xv[i] = c.xr[vv];
+    in.yv[i] = c.y[vv];
+    in.ah[i] = 0;
     if (kPrefetchHi<LMAX> && ((flags >> (kHdrMidShift + i)) & 1))
-      ah[i] = (c.smask_hi + (size_t)tb * kWave)[i * kWave + ul];
+      in.ah[i] = (c.smask_hi + (size_t)tb * kWave)[i * kWave + ul];
   }
+}
+
+// Offsets and window values of the chunk's first 64 neighbourhoods [h0, hend),
+// lane h - h0 (requested before the element passes, used after them).
+__device__ __forceinline__ HoodPre load_pre(const Ctx &c, int h0, int hend, int lane) {
   HoodPre pre{0, 0, {}};
-  {
-    const int h = h0 + lane;
-    if (h < hend) {
-      pre.o = c.hood_ptr[h];
-      pre.s = c.hood_ptr[h + 1] - pre.o;
-      if (c.t >= c.W) {
-        const int slots = c.W + 1;
+  const int h = h0 + lane;
+  if (h < hend) {
+    pre.p0 = c.hood_ptr[h];
+    pre.p1 = c.hood_ptr[h + 1];
+    if (c.t >= c.W) {
+      const int slots = c.W + 1;
 #pragma unroll
-        for (int w = 1; w <= kPreWindow; ++w)
-          if (w <= c.W) pre.prev[w - 1] = c.ring[(size_t)((c.t - w) % slots) * c.H + h];
-      }
+      for (int w = 1; w <= kPreWindow; ++w)
+        if (w <= c.W) pre.prev[w - 1] = c.ring[(size_t)((c.t - w) % slots) * c.H + h];
     }
   }
-  // nothing is written once the run has ended or is done; the test comes
-  // after every load of the chunk is requested (the loads only read)
-  if (skip || (READ_DONE && c.st->done != 0)) return;
+  return pre;
+}
+
+template <int LMAX>
+__device__ __forceinline__ void chunk_issue(const Ctx &c, int ck, ChunkIn &in, int lane) {
+  chunk_stream<LMAX>(c, ck, in, lane);
+  chunk_gather<LMAX>(c, ck, in, lane);
+}
+
+// Second half: the offsets and window values of the chunk's first 64
+// neighbourhoods are requested, then the element passes, the owner list, the
+// neighbourhood pass and the chunk's record row.
+template <int LMAX>
+__device__ __forceinline__ void chunk_run(const Ctx &c, int ck, const ChunkIn &in, const Theta<LMAX> &th, double *row,
+                                          double *mb, double *od, int *oa, int lane) {
+  const int tb = ck * kChunkTiles;
+  const int nt = min(kChunkTiles, c.ntiles - tb);
+  const int flags = (int)hdr_field(in.hw, kDwFlags);
+  const int gstart = (int)hdr_field(in.hw, kDwElem), h0 = (int)hdr_field(in.hw, kDwHood),
+            hend = (int)hdr_field(in.hw, kDwHend);
+  const HoodPre pre = load_pre(c, h0, hend, lane);
   ChunkStats<LMAX> cs;
   cs.clear();
   int ocount = 0;
@@ -1020,15 +1098,31 @@ __device__ void chunk_slots(const Ctx &c, int ck, bool skip, const Theta<LMAX> &
         ocount = 0;
         wave_lds_sync();
       }
-      const int eoff = (int)((hdr(kDwOff + i / 2) >> (16 * (i & 1))) & 0xffffu);
-      slot_elem<LMAX>(c, eoff, (flags >> (kHdrMidShift + i)) & 1, tb + i, (uint32_t)v[i], am[i], ah[i], xv[i], yv[i],
-                      th, cs, mb, od, oa, ocount, lane);
+      const int eoff = (int)((hdr_field(in.hw, kDwOff + i / 2) >> (16 * (i & 1))) & 0xffffu);
+      slot_elem<LMAX>(c, eoff, (flags >> (kHdrMidShift + i)) & 1, tb + i, (uint32_t)in.v[i], in.am[i], in.ah[i],
+                      in.xv[i], in.yv[i], th, cs, mb, od, oa, ocount, lane);
     }
   wave_lds_sync();
   cs.take_owners(od, oa, ocount, lane);
   lean_hoods<LMAX>(c, h0, hend, gstart, pre, cs, mb, lane);
   wave_lds_sync();
   cs.store(row, mb, c.L, lane);  // the minima are no longer needed
+}
+
+// Chunk on the slot layout: chunk_issue, then chunk_run.  The slot kernel is
+// given only superchunks without LARGE packets and only windows of at most
+// kPreWindow (the host sends the others to the packet kernel).  Nothing is
+// written when skip is set (the run has ended or is done) or, with READ_DONE,
+// when the run state's done flag is set (read after the chunk's loads are
+// requested, so they need not wait for it).  th arrives with the chunk's loads
+// (requested before the kernel's first store).
+template <int LMAX, bool READ_DONE>
+__device__ __forceinline__ void chunk_slots(const Ctx &c, int ck, bool skip, const Theta<LMAX> &th, double *row,
+                                            double *mb, double *od, int *oa, int lane) {
+  ChunkIn in;
+  chunk_issue<LMAX>(c, ck, in, lane);
+  if (skip || (READ_DONE && c.st->done != 0)) return;
+  chunk_run<LMAX>(c, ck, in, th, row, mb, od, oa, lane);
 }
 
 // One statistics chunk: packets [ck * kChunkTiles, min(ntiles, (ck + 1) * kChunkTiles)).
@@ -1089,6 +1183,8 @@ __global__ void k_setup(const GraphDev *graphs, int B) {
   const GraphDev &G = graphs[g];
   GraphState *st = G.st;
   st->done = 0;
+  st->stop[0] = 0;
+  st->stop[1] = 0;
   st->status = 0;
   st->iters = 0;
   st->map_conv = -1;
@@ -1104,6 +1200,7 @@ __global__ void k_setup(const GraphDev *graphs, int B) {
   if (!ok) {
     st->status = PMRF_EBADPARAM;
     st->done = 1;
+    st->stop[0] = 1;
     return;
   }
   for (int l = 0; l < G.L; ++l) set_label_theta(st->th[0], l, st->th[0][l].mu, st->th[0][l].sigma);
@@ -1160,212 +1257,376 @@ __global__ __launch_bounds__(256) void k_mstep_init(const GraphDev *graphs, int 
   }
 }
 
-template <int LMAX>
+// LDS of the parameter update.
+struct FoldLds {
+  double tot[kRecMax];
+  double scr[kFoldGroup * kFoldLanes];
+};
+
 __global__ __launch_bounds__(kFoldThreads) void k_fin_init(const GraphDev *graphs, int B, int pass) {
-  __shared__ double tot[kRecMax];
-  __shared__ double part[kFoldWaves][kRecMax];
+  __shared__ FoldLds sh;
   const GraphDev &G = graphs[blockIdx.x];
   GraphState *st = G.st;
   if (!G.init_from_labels || st->done) return;
-  fold_records<LMAX>(gbl((const double *)G.rec), G.vnblocks, G.L, tot, part, blockDim.x >> 6, wave_id(),
-                     threadIdx.x & 63);
+  fold_all(gbl((const double *)G.rec), G.vnblocks, rec_words(G.L), sh.scr, sh.tot, blockDim.x >> 6, wave_id(),
+           threadIdx.x & 63);
   if (threadIdx.x != 0) return;
-  if (tot[3 * G.L + 3] != 0.0) {
+  if (sh.tot[3 * G.L + 3] != 0.0) {
     st->status = PMRF_EBADLABEL;
     st->done = 1;
+    st->stop[0] = 1;
     return;
   }
-  update_theta(st->th[0], tot, G.L, G.sigma_min, pass == 0);
+  update_theta(st->th[0], sh.tot, G.L, G.sigma_min, pass == 0);
 }
 
-// LDS of the parameter update.
-template <int LMAX>
-struct FoldLds {
-  double tot[kRecMax];
-  double part[kFoldWaves][kRecMax];
+// What the parameter update of iteration tp = t - 1 reads of the run state
+// besides the records, requested before the fold: whether the run had stopped
+// before tp, the running counters, and in lane l label l's parameters of tp
+// and the energy total of iteration tp - l - 1 (thist holds max(1, max_iters)
+// entries; used where tp >= l + 1).
+struct FoldPrev {
+  int done;
+  int map_conv, em_conv;
+  long long ties_total;
+  double mu, sg, wl, lg;
+  double hist;
 };
 
-// Parameter update ("Update Parameters") of iteration tp = t - 1 >= 0 of one
-// graph, by one block: fold the records of tp in the fixed order, derive the
-// parameters of iteration t, and store them with the per-iteration results of
-// tp (energy total, near ties, convergence, iteration count, early exit,
-// errors).  Every value the update reads is requested before any of it is
-// used: the state (uniform, scalar loads), and in wave 0 lane l's label
-// parameters and the energy total of iteration tp - l - 1 travel with the
-// record loads.  Wave 0 then updates label l in lane l.
-template <int LMAX>
-__device__ __forceinline__ void fold_iteration(const GraphDev &G, int t, FoldLds<LMAX> &sh, int nw, int wave,
-                                               int lane) {
-  const int max_iters = G.max_iters, L = G.L, W = G.W;
-  gptr<GraphState> st = gbl(G.st);
+__device__ __forceinline__ FoldPrev fold_prev(const GraphDev &G, int t, int done, int lane) {
+  gptr<const GraphState> st = gbl((const GraphState *)G.st);
   gptr<const double> thist = gbl((const double *)G.thist);
   const int tp = t - 1;
-  const int done = st->done;
-  const long long ties_total = st->ties_total;
-  const int map_conv = st->map_conv, em_conv = st->em_conv;
-  // label `lane`'s parameters of tp and the energy total of iteration
-  // tp - lane - 1 (thist holds max(1, max_iters) entries; used where
-  // tp >= lane + 1), requested with the records; only wave 0 uses them
+  FoldPrev p;
+  p.done = done;
+  p.ties_total = st->ties_total;
+  p.map_conv = st->map_conv;
+  p.em_conv = st->em_conv;
   const int ll = lane < kMaxLabels ? lane : 0;
-  double mu = st->th[tp & 1][ll].mu, sg = st->th[tp & 1][ll].sigma;
-  double wl = st->th[tp & 1][ll].w, lg = st->th[tp & 1][ll].lg;
-  const double hist = thist[min(max(0, tp - lane - 1), max(0, max_iters - 1))];
-  // a graph whose run has ended (tp >= max_iters, in a batch of mixed run
-  // lengths) folds but stores nothing; testing it after the fold lets every
-  // load above be requested at once
-  fold_records<LMAX>(gbl((const double *)G.rec) + (size_t)(tp & 1) * G.rec_stride, G.nsuper, L, sh.tot, sh.part,
-                     nw, wave, lane);
-  if (tp >= max_iters || wave != 0 || done) return;
-  if (sh.tot[3 * L + 3] != 0.0) {
-    if (lane == 0) {
+  p.mu = st->th[tp & 1][ll].mu;
+  p.sg = st->th[tp & 1][ll].sigma;
+  p.wl = st->th[tp & 1][ll].w;
+  p.lg = st->th[tp & 1][ll].lg;
+  p.hist = thist[min(max(0, tp - lane - 1), max(0, G.max_iters - 1))];
+  return p;
+}
+
+// Parameter update ("Update Parameters") and convergence check of iteration
+// tp = t - 1, by one wave, from the record totals tot[]: lane l < L gets label
+// l's parameters of iteration t in (p.mu, p.sg, p.wl, p.lg); with `write`, the
+// parameters and the results of tp (energy total, near ties, convergence,
+// iteration count, early exit, errors) go to the run state (one block per
+// graph writes).  Returns whether the run stops before iteration t: it had
+// stopped before tp, a starting label was out of range, or every neighbourhood
+// converged with early exit on.
+__device__ __forceinline__ bool finish_iteration(const GraphDev &G, int t, const double *tot, FoldPrev &p, bool write,
+                                                 int lane) {
+  const int L = G.L, W = G.W, tp = t - 1;
+  gptr<GraphState> st = gbl(G.st);
+  if (p.done) return true;
+  if (tot[3 * L + 3] != 0.0) {
+    if (write && lane == 0) {
       st->status = PMRF_EBADLABEL;
       st->done = 1;
     }
-    return;
+    return true;
   }
-  const double T = sh.tot[3 * L];
-  const long long ties = (long long)sh.tot[3 * L + 1];
-  const long long nonconv = (long long)sh.tot[3 * L + 2];
+  const double T = tot[3 * L];
+  const long long ties = (long long)tot[3 * L + 1];
+  const long long nonconv = (long long)tot[3 * L + 2];
   // the energy total has converged if it moved less than tol against each of
   // the previous W totals
-  const bool em_ok = __ballot(lane < W && !(fabs(T - hist) < G.tol)) == 0;
+  const bool em_ok = __ballot(lane < W && !(fabs(T - p.hist) < G.tol)) == 0;
   if (lane < L) {
-    next_label_theta(sh.tot[3 * lane], sh.tot[3 * lane + 1], sh.tot[3 * lane + 2], G.sigma_min, false, mu, sg, wl,
-                     lg);
-    st->th[t & 1][lane].mu = mu;
-    st->th[t & 1][lane].sigma = sg;
-    st->th[t & 1][lane].w = wl;
-    st->th[t & 1][lane].lg = lg;
+    next_label_theta(tot[3 * lane], tot[3 * lane + 1], tot[3 * lane + 2], G.sigma_min, false, p.mu, p.sg, p.wl, p.lg);
+    if (write) {
+      st->th[t & 1][lane].mu = p.mu;
+      st->th[t & 1][lane].sigma = p.sg;
+      st->th[t & 1][lane].w = p.wl;
+      st->th[t & 1][lane].lg = p.lg;
+    }
   }
-  if (lane == 0) {
+  const bool stop = G.early_exit && nonconv == 0 && tp >= W;
+  if (write && lane == 0) {
     gbl(G.thist)[tp] = T;
     if (G.out_trace) gbl(G.out_trace)[tp] = T;
     if (G.out_stats) {
       gbl(G.out_stats)[2 * tp] = ties;
       gbl(G.out_stats)[2 * tp + 1] = nonconv;
     }
-    st->ties_total = ties_total + ties;
-    if (nonconv == 0 && tp >= W && map_conv < 0) st->map_conv = tp;
-    if (tp >= W && em_conv < 0 && em_ok) st->em_conv = tp;
+    st->ties_total = p.ties_total + ties;
+    if (nonconv == 0 && tp >= W && p.map_conv < 0) st->map_conv = tp;
+    if (tp >= W && p.em_conv < 0 && em_ok) st->em_conv = tp;
     st->iters = t;
-    if (G.early_exit && nonconv == 0 && tp >= W) st->done = 1;
+    if (stop) st->done = 1;
   }
+  return stop;
+}
+
+// The parameter update of iteration t - 1 of one graph, by one block: fold the
+// records of t - 1 and finish the iteration in wave 0.  Every value the update
+// reads is requested before the fold.
+__device__ __forceinline__ void fold_iteration(const GraphDev &G, int t, FoldLds &sh, int nw, int wave, int lane) {
+  const int tp = t - 1;
+  FoldPrev p = fold_prev(G, t, gbl((const GraphState *)G.st)->done, lane);
+  // a graph whose run has ended (tp >= max_iters, in a batch of mixed run
+  // lengths) folds but stores nothing; testing it after the fold lets every
+  // load above be requested at once
+  fold_all(gbl((const double *)G.rec) + (size_t)(tp & 1) * G.rec_stride, G.nsuper, rec_words(G.L), sh.scr, sh.tot,
+           nw, wave, lane);
+  if (tp >= G.max_iters || wave != 0) return;
+  (void)finish_iteration(G, t, sh.tot, p, true, lane);
 }
 
 // The parameter update of iteration t - 1 (one block per graph; SINGLE: the
 // one graph's descriptor g1 travels in the kernel arguments).
-template <int LMAX, bool SINGLE>
+template <bool SINGLE>
 __global__ __launch_bounds__(kFoldThreads) void k_fold(const GraphDev *graphs, const GraphDev g1, int B, int t) {
-  __shared__ FoldLds<LMAX> sh;
+  __shared__ FoldLds sh;
   if constexpr (SINGLE)
-    fold_iteration<LMAX>(g1, t, sh, blockDim.x >> 6, wave_id(), threadIdx.x & 63);
+    fold_iteration(g1, t, sh, blockDim.x >> 6, wave_id(), threadIdx.x & 63);
   else
-    fold_iteration<LMAX>(graphs[blockIdx.x], t, sh, blockDim.x >> 6, wave_id(), threadIdx.x & 63);
+    fold_iteration(graphs[blockIdx.x], t, sh, blockDim.x >> 6, wave_id(), threadIdx.x & 63);
 }
 
-// One EM iteration over every graph of the launch.  Superchunk b of a graph
-// (chunks 4b .. 4b+3) belongs to one block; its waves take the chunks in turn,
-// leave each chunk's statistics in LDS, and the block adds them in chunk order
-// into record b (buffer t & 1).  PACKET: the superchunk holds a LARGE packet
-// (or the window is longer than kPreWindow) and goes packet by packet over the
-// element arrays; otherwise every chunk takes the slot layout.
+// Registers of one iteration launch for a graph.
+__device__ __forceinline__ Ctx make_ctx(const GraphDev &G, int t) {
+  Ctx c;
+  c.tiles = gbl(G.tiles);
+  c.vid = gbl(G.vid);
+  c.mask = gbl(G.mask);
+  c.chdr = gbl(G.chdr);
+  c.svid = gbl(G.svid);
+  c.smask = gbl(G.smask);
+  c.smask_hi = gbl(G.smask_hi);
+  c.st = gbl((const GraphState *)G.st);
+  c.hood_ptr = gbl(G.hood_ptr);
+  c.y = gbl(G.y);
+  c.xr = gbl((const int32_t *)((t & 1) ? G.x1 : G.x0));
+  c.xw = gbl((t & 1) ? G.x0 : G.x1);
+  c.ring = gbl(G.ring);
+  c.H = G.H;
+  c.W = G.W;
+  c.L = G.L;
+  c.P = G.P;
+  c.t = t;
+  c.ntiles = G.ntiles;
+  c.nchunks = G.nchunks;
+  c.beta = G.beta;
+  c.tol = G.tol;
+  c.tie_eps = G.tie_eps;
+  return c;
+}
+
+// The block's records: superchunk s of chunks [c0, c1) (c0 a superchunk
+// boundary) gets its chunk rows added in chunk order; an empty graph's one
+// block writes record 0 (zeros).  The caller has synchronised the block.
+template <int LMAX>
+__device__ __forceinline__ void store_records(const GraphDev &G, int c0, int c1, int t,
+                                              double (*part)[rec_words(LMAX)]) {
+  const int words = rec_words(G.L), sc = G.sc;
+  const int s0 = c0 / sc, ns = max(1, (c1 - c0 + sc - 1) / sc);
+  gptr<double> rec = gbl(G.rec) + (size_t)(t & 1) * G.rec_stride;
+  for (int i = threadIdx.x; i < ns * words; i += blockDim.x) {
+    const int r = i / words, w = i - r * words;
+    const int k1 = min((r + 1) * sc, c1 - c0);
+    double out = 0.0;
+    for (int k = r * sc; k < k1; ++k) out = out + part[k][w];
+    rec[(size_t)w * G.nsuper + s0 + r] = out;
+  }
+}
+
+// One EM iteration over every graph of the launch.  A block takes chunks
+// [c0, c1) of a graph (whole superchunks: one on the packet kernel and for a
+// single graph, up to 16 chunks' worth in a batch); its waves take the chunks
+// in turn, leave each chunk's statistics in LDS, and the block adds them in
+// chunk order into one record per superchunk (buffer t & 1).  PACKET: the
+// superchunk holds a LARGE packet (or the window is longer than kPreWindow)
+// and goes packet by packet over the element arrays; otherwise every chunk
+// takes the slot layout.
 template <int LMAX, bool PACKET, bool SINGLE = false>
-__device__ __forceinline__ void iter_superchunk(const GraphDev &G, int b, int t, double (*part)[rec_words(LMAX)],
-                                                double *mb, uint64_t *pl, double *od, int *oa, int nw, int wave,
-                                                int lane) {
+__device__ __forceinline__ void iter_superchunk(const GraphDev &G, int c0, int c1, int t,
+                                                double (*part)[rec_words(LMAX)], double *mb, uint64_t *pl, double *od,
+                                                int *oa, int nw, int wave, int lane) {
   // A graph whose run has ended (a batch mixes run lengths) computes and
   // writes nothing; the test joins the run state's done flag instead of
   // returning first, so the chunk's loads need not wait for it (they only read).
   const bool ended = t >= G.max_iters;
+  const Ctx c = make_ctx(G, t);
+  Theta<LMAX> th;
+  const int done_flag = load_theta<LMAX>(c, th);  // scalar loads, waited for with the chunk's
+  if constexpr (!PACKET) {
+    // single graph: the slot path's descriptor fields (kernel arguments)
+    // arrive in one batch of scalar loads, before the first branch
+    // (otherwise each branch waits for the fields it tests before the next
+    // ones are even requested); the run state's done flag is read inside
+    // the chunk, after the chunk's loads are requested.  (A batch looks its
+    // descriptor up in memory; pinning it there costs registers.)
+    if constexpr (SINGLE)
+      asm volatile("" ::"s"(c.chdr), "s"(c.svid), "s"(c.smask), "s"(c.st), "s"(c.hood_ptr), "s"(c.y), "s"(c.xr),
+                   "s"(c.xw), "s"(c.ring), "s"(c.H), "s"(c.W), "s"(c.L), "s"(c.ntiles), "s"(c.nchunks), "s"(nw));
+    const bool skip = SINGLE ? ended : (done_flag != 0 || ended);
+    for (int ck = c0 + wave; ck < c1; ck += nw)
+      chunk_slots<LMAX, SINGLE>(c, ck, skip, th, part[ck - c0], mb, od, oa, lane);
+  } else {
+    if (!(done_flag != 0 || ended))
+      for (int ck = c0 + wave; ck < c1; ck += nw) chunk_packets<LMAX>(c, ck, th, part[ck - c0], mb, pl, lane);
+  }
+  const bool done = done_flag != 0 || ended;
+  __syncthreads();
+  if (!done) store_records<LMAX>(G, c0, c1, t, part);
+}
+
+// Chunks of slot-kernel block b of a graph, and of packet-kernel block i.
+__device__ __forceinline__ int slot_c0(const GraphDev &G, int b) { return b * G.bc; }
+__device__ __forceinline__ int slot_c1(const GraphDev &G, int b) { return min(G.slot_end, (b + 1) * G.bc); }
+__device__ __forceinline__ int packet_c0(const GraphDev &G, int i) { return (G.nslot + i) * G.sc; }
+__device__ __forceinline__ int packet_c1(const GraphDev &G, int i) { return min(G.nchunks, (G.nslot + i + 1) * G.sc); }
+
+// Element v of a row of nrec doubles, or 0.0 when v >= nrec: a raw buffer
+// load, whose range check returns zero past the row's end (no memory is read
+// there).  The resource's last dword is the gfx9 raw-buffer format.
+__device__ __forceinline__ double row_load(const double *row, int nrec, int v) {
+  const __amdgpu_buffer_rsrc_t r =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(row), (short)0, nrec * 8, 0x00020000);
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, v * 8, 0, 0));
+}
+
+// LDS of the fused launch: the record totals, the parameters of the iteration
+// and the stop flag, handed from wave 0 to the block.
+template <int LMAX>
+struct FusedLds {
+  double tot[kRecMax];
+  double mu[LMAX], w[LMAX], lg[LMAX];
+  int stop;
+};
+
+// Iteration t >= 1 of a single graph whose superchunks all take the slot
+// kernel and number at most kFoldLanes (one record per virtual thread of the
+// fold): the parameter update of iteration t - 1 happens here instead of in a
+// launch of its own.  Every block folds the records of t - 1 in the fold
+// kernel's order (so every block derives the same bits, and the same bits as
+// k_fold) and computes the parameters of iteration t in wave 0; the block that
+// plays superchunk 0 also stores them with the results of t - 1 in the run
+// state, as k_fold would.  Records of t - 1 (virtual wave q by wave q), the run
+// state and the first chunk's loads are all requested before the fold waits,
+// so the fold overlaps the chunk's trip to memory.  The launch reads the stop
+// flag of t - 1 and its superchunk-0 block writes that of t (the other slot).
+// The block has at least kFoldLanes / 64 waves (wave q plays virtual wave q)
+// and the graph at least one chunk.
+// scr: at least rec_words(L) * kFoldLanes doubles of LDS (the waves' minima
+// buffers, unused until the fold is over).
+template <int LMAX>
+__device__ __forceinline__ void iter_superchunk_fused(const GraphDev &G, int b, int t,
+                                                      double (*part)[rec_words(LMAX)], double *scr, double *mb,
+                                                      double *od, int *oa, FusedLds<LMAX> &fl, int nw, int wave,
+                                                      int lane) {
+  // one superchunk per block (bc == sc, every superchunk on the slot kernel)
+  constexpr int WORDS = rec_words(LMAX);
+  static_assert(WORDS <= kFoldGroup, "the fused fold takes one pass of words");
+  const int tp = t - 1, R = G.nsuper, words = rec_words(G.L);
+  gptr<GraphState> st = gbl(G.st);
+  const bool writer = b == 0;
+  // this wave's virtual fold thread: at most one record
+  // (range-checked loads: a lane past the records, a word past the label
+  // count and every lane of a wave that plays no virtual wave read 0.0, with
+  // no branch or select the compiler could turn into a wait)
+  double rv[WORDS];
   {
-    Ctx c;
-    c.tiles = gbl(G.tiles);
-    c.vid = gbl(G.vid);
-    c.mask = gbl(G.mask);
-    c.chdr = gbl(G.chdr);
-    c.svid = gbl(G.svid);
-    c.smask = gbl(G.smask);
-    c.smask_hi = gbl(G.smask_hi);
-    c.st = gbl((const GraphState *)G.st);
-    c.hood_ptr = gbl(G.hood_ptr);
-    c.y = gbl(G.y);
-    c.xr = gbl((const int32_t *)((t & 1) ? G.x1 : G.x0));
-    c.xw = gbl((t & 1) ? G.x0 : G.x1);
-    c.ring = gbl(G.ring);
-    c.H = G.H;
-    c.W = G.W;
-    c.L = G.L;
-    c.P = G.P;
-    c.t = t;
-    c.ntiles = G.ntiles;
-    c.nchunks = G.nchunks;
-    c.beta = G.beta;
-    c.tol = G.tol;
-    c.tie_eps = G.tie_eps;
-    const int c0 = b * kSuperChunks;
-    const int c1 = min(G.nchunks, c0 + kSuperChunks);
-    Theta<LMAX> th;
-    const int done_flag = load_theta<LMAX>(c, th);  // scalar loads, waited for with the chunk's
-    if constexpr (!PACKET) {
-      // single graph: the slot path's descriptor fields (kernel arguments)
-      // arrive in one batch of scalar loads, before the first branch
-      // (otherwise each branch waits for the fields it tests before the next
-      // ones are even requested); the run state's done flag is read inside
-      // the chunk, after the chunk's loads are requested.  (A batch looks its
-      // descriptor up in memory; pinning it there costs registers.)
-      if constexpr (SINGLE)
-        asm volatile("" ::"s"(c.chdr), "s"(c.svid), "s"(c.smask), "s"(c.st), "s"(c.hood_ptr), "s"(c.y), "s"(c.xr),
-                     "s"(c.xw), "s"(c.ring), "s"(c.H), "s"(c.W), "s"(c.L), "s"(c.ntiles), "s"(c.nchunks), "s"(nw));
-      const bool skip = SINGLE ? ended : (done_flag != 0 || ended);
-      for (int ck = c0 + wave; ck < c1; ck += nw)
-        chunk_slots<LMAX, SINGLE>(c, ck, skip, th, part[ck - c0], mb, od, oa, lane);
-    } else {
-      if (!(done_flag != 0 || ended))
-        for (int ck = c0 + wave; ck < c1; ck += nw) chunk_packets<LMAX>(c, ck, th, part[ck - c0], mb, pl, lane);
+    const double *rec = G.rec + (size_t)(tp & 1) * G.rec_stride;
+    const int nrec = wave < kFoldLanes / 64 ? R : 0;
+    const int v = wave * 64 + lane;
+#pragma unroll
+    for (int j = 0; j < WORDS; ++j) rv[j] = row_load(rec + (size_t)j * R, j < words ? nrec : 0, v);
+  }
+  FoldPrev pv = fold_prev(G, t, st->stop[tp & 1], lane);  // used by wave 0
+  const Ctx c = make_ctx(G, t);
+  const int c0 = slot_c0(G, b), c1 = slot_c1(G, b);
+  const int ck0 = c0 + wave;
+  // requested unconditionally (a wave without a chunk of its own requests the
+  // superchunk's last one and drops it), so no branch joins the loads in
+  // flight during the fold
+  ChunkIn in;
+  const int ckl = min(ck0, c1 - 1);
+  chunk_stream<LMAX>(c, ckl, in, lane);
+  if (wave < kFoldLanes / 64) {
+    const int v = wave * 64 + lane;
+#pragma unroll
+    for (int j = 0; j < WORDS; ++j) scr[fold_slot(j, v)] = rv[j];  // words >= L's are zero and never read
+  }
+  __syncthreads();
+  if (wave == 0) {
+    fold_stage2(scr, words, fl.tot, 1, 0, lane);
+    wave_lds_sync();
+    const bool stop = finish_iteration(G, t, fl.tot, pv, writer, lane);
+    if (lane < LMAX) {
+      const bool ok = lane < G.L;
+      fl.mu[lane] = ok ? pv.mu : 0.0;
+      fl.w[lane] = ok ? pv.wl : 0.0;
+      fl.lg[lane] = ok ? pv.lg : 0.0;
     }
-    const bool done = done_flag != 0 || ended;
-    __syncthreads();
-    const int words = rec_words(c.L);
-    if (!done && threadIdx.x < words) {
-      const int w = threadIdx.x;
-      double out = 0.0;
-      for (int k = 0; k < c1 - c0; ++k) out = out + part[k][w];
-      gbl(G.rec)[(size_t)(t & 1) * G.rec_stride + (size_t)w * G.nsuper + b] = out;
+    if (lane == 0) {
+      fl.stop = stop ? 1 : 0;
+      if (writer) st->stop[t & 1] = stop ? 1 : 0;
     }
   }
+  __syncthreads();
+  // the parameters are uniform: scalar registers
+  Theta<LMAX> th;
+#pragma unroll
+  for (int l = 0; l < LMAX; ++l) {
+    th.mu[l] = uniform_f64(fl.mu[l]);
+    th.w[l] = uniform_f64(fl.w[l]);
+    th.lg[l] = uniform_f64(fl.lg[l]);
+  }
+  const bool stop = __builtin_amdgcn_readfirstlane(fl.stop) != 0;
+  chunk_gather<LMAX>(c, ckl, in, lane);
+  if (!stop && ck0 < c1) chunk_run<LMAX>(c, ck0, in, th, part[ck0 - c0], mb, od, oa, lane);
+  for (int ck = ck0 + nw; ck < c1; ck += nw) chunk_slots<LMAX, false>(c, ck, stop, th, part[ck - c0], mb, od, oa, lane);
+  __syncthreads();
+  if (!stop) store_records<LMAX>(G, c0, c1, t, part);
 }
 
 // PERSIST = false: block b works on superchunk b.  PERSIST = true: a grid sized
 // to the machine whose blocks walk all superchunks.  SINGLE: one graph, whose
 // descriptor g1 travels in the kernel arguments (its fields are then at hand
 // without a dependent load); otherwise each block looks its graph up in
-// graphs[0 .. B).
-template <int LMAX, bool PERSIST, bool SINGLE>
+// graphs[0 .. B).  FUSED (single graph, t >= 1, not persistent): the launch
+// also does the parameter update of iteration t - 1 (iter_superchunk_fused).
+template <int LMAX, bool PERSIST, bool SINGLE, bool FUSED = false>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(LMAX <= 2 ? (SINGLE ? PMRF_ITER_WAVES_PER_EU : PMRF_BATCH_WAVES_PER_EU) : 1, 8))) void k_iter(
     const GraphDev *__restrict__ graphs, const int32_t *__restrict__ block_graph, const GraphDev g1, int B,
     int nsuper_total, int t) {
+  static_assert(!FUSED || (SINGLE && !PERSIST), "the fused launch is for one graph, one block per superchunk");
   extern __shared__ double smem[];
-  __shared__ double part[kSuperChunks][rec_words(LMAX)];
+  __shared__ double part[kMaxSuperChunks][rec_words(LMAX)];
   const int nw = blockDim.x >> 6, wave = wave_id(), lane = threadIdx.x & 63;
   double *mb = smem + wave * kWaveLds;
   uint64_t *pl = reinterpret_cast<uint64_t *>(mb + kGroupTiles * 64);
   double *od = mb + kGroupTiles * 64 + 64;
   int *oa = reinterpret_cast<int *>(od + kOwnCap);
-  if constexpr (!PERSIST) {
+  if constexpr (FUSED) {
+    __shared__ FusedLds<LMAX> fl;
+    iter_superchunk_fused<LMAX>(g1, xcd_block(blockIdx.x, gridDim.x), t, part, smem, mb, od, oa, fl, nw, wave, lane);
+  } else if constexpr (!PERSIST) {
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     if constexpr (SINGLE) {
-      iter_superchunk<LMAX, false, true>(g1, blk, t, part, mb, pl, od, oa, nw, wave, lane);
+      iter_superchunk<LMAX, false, true>(g1, slot_c0(g1, blk), slot_c1(g1, blk), t, part, mb, pl, od, oa, nw, wave,
+                                         lane);
     } else {
       const GraphDev &G = graphs[block_graph[blk]];
-      iter_superchunk<LMAX, false>(G, blk - G.block0, t, part, mb, pl, od, oa, nw, wave, lane);
+      const int b = blk - G.block0;
+      iter_superchunk<LMAX, false>(G, slot_c0(G, b), slot_c1(G, b), t, part, mb, pl, od, oa, nw, wave, lane);
     }
   } else {
     for (int sc = blockIdx.x; sc < nsuper_total; sc += gridDim.x) {
       if constexpr (SINGLE) {
-        iter_superchunk<LMAX, false, true>(g1, sc, t, part, mb, pl, od, oa, nw, wave, lane);
+        iter_superchunk<LMAX, false, true>(g1, slot_c0(g1, sc), slot_c1(g1, sc), t, part, mb, pl, od, oa, nw, wave,
+                                           lane);
       } else {
         const GraphDev &G = graphs[block_graph[sc]];
-        iter_superchunk<LMAX, false>(G, sc - G.block0, t, part, mb, pl, od, oa, nw, wave, lane);
+        const int b = sc - G.block0;
+        iter_superchunk<LMAX, false>(G, slot_c0(G, b), slot_c1(G, b), t, part, mb, pl, od, oa, nw, wave, lane);
       }
       __syncthreads();  // part[] is reused by the next superchunk
     }
@@ -1373,18 +1634,19 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(LMAX <= 2 
 }
 
 // The superchunks that hold a LARGE packet: block i of a graph works on its
-// superchunk nblocks + i, packet by packet.
+// superchunk nslot + i, packet by packet.
 template <int LMAX>
 __global__ __launch_bounds__(1024) void k_iter_packets(const GraphDev *__restrict__ graphs, int B, int t) {
   extern __shared__ double smem[];
-  __shared__ double part[kSuperChunks][rec_words(LMAX)];
+  __shared__ double part[kMaxSuperChunks][rec_words(LMAX)];
   const int nw = blockDim.x >> 6, wave = wave_id(), lane = threadIdx.x & 63;
   double *mb = smem + wave * kWaveLds;
   uint64_t *pl = reinterpret_cast<uint64_t *>(mb + kGroupTiles * 64);
   double *od = mb + kGroupTiles * 64 + 64;
   int *oa = reinterpret_cast<int *>(od + kOwnCap);
   const GraphDev &G = graphs[find_graph(graphs, B, blockIdx.x, kGridPacket)];
-  iter_superchunk<LMAX, true>(G, G.nblocks + (blockIdx.x - G.pblock0), t, part, mb, pl, od, oa, nw, wave, lane);
+  const int i = blockIdx.x - G.pblock0;
+  iter_superchunk<LMAX, true>(G, packet_c0(G, i), packet_c1(G, i), t, part, mb, pl, od, oa, nw, wave, lane);
 }
 
 
@@ -1453,6 +1715,7 @@ hipError_t prof_pair(hipEvent_t *a, hipEvent_t *b) {
 }
 
 constexpr int kModeGraph = 1, kModePersistent = 2, kModeDirect = 3;
+constexpr int kFusedMaxLabels = 4;  // fused launches exist for LMAX = 2 and 4
 
 struct LaunchShape {
   int mode, waves_per_block, tiles_per_wave, blocks_per_cu;
@@ -1462,7 +1725,7 @@ struct LaunchShape {
 LaunchShape resolve_shape() {
   std::lock_guard<std::mutex> lk(g_launch_mu);
   LaunchShape s{g_launch.mode > 0 ? g_launch.mode : kModeGraph,
-                g_launch.waves_per_block > 0 ? g_launch.waves_per_block : 4,
+                g_launch.waves_per_block,  // 0: automatic (run_items)
                 g_launch.tiles_per_wave > 0 ? g_launch.tiles_per_wave : 1,
                 g_launch.blocks_per_cu > 0 ? g_launch.blocks_per_cu : 5, g_launch.mode == 0};
   return s;
@@ -1529,17 +1792,45 @@ pmrf_status check_item(const pmrf_em_item &it, int idx) {
 
 int64_t n_chunks(const pmrf_hoods *h) { return ((int64_t)h->tiles.size() + kChunkTiles - 1) / kChunkTiles; }
 int64_t vert_blocks(const pmrf_hoods *h) { return std::max<int64_t>(1, ((int64_t)h->n + kVertPerBlock - 1) / kVertPerBlock); }
-int64_t n_super(const pmrf_hoods *h) { return std::max<int64_t>(1, (n_chunks(h) + kSuperChunks - 1) / kSuperChunks); }
+int32_t superchunk_chunks(const pmrf_hoods *h) {
+  const int64_t nc = n_chunks(h);
+  return nc <= 4 * kFoldLanes ? 4 : nc <= 8 * kFoldLanes ? 8 : kMaxSuperChunks;
+}
+int64_t n_super(const pmrf_hoods *h) {
+  const int64_t sc = superchunk_chunks(h);
+  return std::max<int64_t>(1, (n_chunks(h) + sc - 1) / sc);
+}
 int64_t max_records(const pmrf_hoods *h) { return std::max<int64_t>(n_super(h), vert_blocks(h)); }
 
 // Superchunks of a graph that take the slot kernel: those before the first
 // LARGE packet (all of them when there is none), none when the window is
 // longer than kPreWindow; the rest take the packet kernel.
 int32_t slot_supers(const pmrf_hoods *h, const pmrf_em_params &params) {
-  const int64_t per_super = (int64_t)kChunkTiles * kSuperChunks;
+  const int64_t per_super = (int64_t)kChunkTiles * superchunk_chunks(h);
   int32_t nslot = h->slot_tiles == (int64_t)h->tiles.size() ? (int32_t)n_super(h) : (int32_t)(h->slot_tiles / per_super);
   if (params.conv_window > kPreWindow) nslot = 0;
   return nslot;
+}
+
+// How a graph's chunks are cut for one run: superchunks (records) of sc
+// chunks, which depend on the graph alone; slot-kernel blocks of bc chunks (a
+// single graph: one superchunk per block; a batch: 16 chunks per block, so
+// every block of the launch costs about the same and the blocks dealt to each
+// XCD carry equal work); packet-kernel blocks of one superchunk each.
+struct GraphSplit {
+  int32_t sc, bc, nsuper, nslot, slot_end, nblocks, pnblocks;
+};
+
+GraphSplit split_graph(const pmrf_hoods *h, const pmrf_em_params &params, int B) {
+  GraphSplit g;
+  g.sc = superchunk_chunks(h);
+  g.bc = B == 1 ? g.sc : kMaxSuperChunks;
+  g.nsuper = (int32_t)n_super(h);
+  g.nslot = slot_supers(h, params);
+  g.slot_end = (int32_t)std::min<int64_t>(n_chunks(h), (int64_t)g.nslot * g.sc);
+  g.nblocks = g.nslot == 0 ? 0 : std::max(1, (g.slot_end + g.bc - 1) / g.bc);  // an empty graph keeps one block
+  g.pnblocks = g.nsuper - g.nslot;
+  return g;
 }
 
 WsPlan plan_workspace(int B, const pmrf_em_item *items) {
@@ -1547,7 +1838,7 @@ WsPlan plan_workspace(int B, const pmrf_em_item *items) {
   int64_t off = 0;
   p.desc_off = off;
   off += align_up((int64_t)B * (int64_t)sizeof(GraphDev), 256);
-  for (int i = 0; i < B; ++i) p.slot_blocks += slot_supers(items[i].hoods, items[i].params);
+  for (int i = 0; i < B; ++i) p.slot_blocks += split_graph(items[i].hoods, items[i].params, B).nblocks;
   p.block_graph_off = off;
   off += align_up(std::max<int64_t>(1, p.slot_blocks) * 4, 256);
   for (int i = 0; i < B; ++i) {
@@ -1583,7 +1874,10 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
   if (!d_ws) return fail(PMRF_EINVAL, "workspace is NULL");
   if (ws_bytes < plan.total) return fail(PMRF_ENOMEM, "workspace smaller than the required size");
   if (reinterpret_cast<uintptr_t>(d_ws) % 256) return fail(PMRF_EINVAL, "workspace must be 256-byte aligned");
-  const LaunchShape shape = resolve_shape();
+  LaunchShape shape = resolve_shape();
+  // automatic block size: one wave per chunk of a superchunk for a single
+  // graph, four waves for a batch
+  if (shape.waves_per_block <= 0) shape.waves_per_block = B == 1 ? superchunk_chunks(items[0].hoods) : 4;
   const int threads = shape.waves_per_block * kWave;
   char *ws = static_cast<char *>(d_ws);
   std::vector<GraphDev> desc(B);
@@ -1633,12 +1927,16 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
     G.tie_eps = it.params.tie_eps;
     G.block0 = blocks_iter;
     G.nchunks = (int32_t)n_chunks(h);
-    G.nsuper = (int32_t)n_super(h);
-    const int32_t nslot = slot_supers(h, it.params);
-    G.nblocks = nslot;
+    const GraphSplit sp = split_graph(h, it.params, B);
+    G.nsuper = sp.nsuper;
+    G.sc = sp.sc;
+    G.bc = sp.bc;
+    G.nslot = sp.nslot;
+    G.slot_end = sp.slot_end;
+    G.nblocks = sp.nblocks;
     blocks_iter += G.nblocks;
     G.pblock0 = blocks_pk;
-    G.pnblocks = G.nsuper - nslot;
+    G.pnblocks = sp.pnblocks;
     blocks_pk += G.pnblocks;
     G.perm = reinterpret_cast<const int32_t *>(hb + h->layout.perm_off);
     G.vblock0 = blocks_vert;
@@ -1653,12 +1951,21 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
   bool any_init = false;
   for (int i = 0; i < B; ++i) any_init |= desc[i].init_from_labels != 0;
   const int lm = lmax_for(Lmax);
-  const size_t lds = (size_t)(kWaveLds * shape.waves_per_block) * 8;
+  // One launch per EM iteration for a single graph whose superchunks all take
+  // the slot kernel and whose records fit one fold pass per block (the blocks
+  // of iteration t fold the records of t - 1 themselves); otherwise a fold
+  // launch follows every iteration launch.  The fold order is the same either
+  // way, so this changes speed only.
+  const bool persist = shape.mode == kModePersistent;
+  const bool fused = B == 1 && blocks_pk == 0 && !persist && lm <= kFusedMaxLabels &&
+                     desc[0].nsuper <= kFoldLanes && desc[0].nslot == desc[0].nsuper && desc[0].nchunks >= 1 &&
+                     shape.waves_per_block >= kFoldLanes / 64;
+  size_t lds = (size_t)(kWaveLds * shape.waves_per_block) * 8;
+  if (fused) lds = std::max(lds, (size_t)rec_words(lm) * kFoldLanes * 8);
   const bool events = g_prof.on && !no_alloc;
   // grid of the iteration kernel: one block per superchunk, or in persistent
   // mode a machine-sized grid whose blocks walk the superchunks
   int grid_iter = blocks_iter;
-  const bool persist = shape.mode == kModePersistent;
   if (persist) {
     int dev = 0, cus = 0;
     HIP_TRY(hipGetDevice(&dev));
@@ -1688,12 +1995,7 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
       for (int pass = 0; pass < 2; ++pass) {
         hipLaunchKernelGGL(k_mstep_init, dim3(blocks_vert), dim3(256), 0, s, gd, B, pass);
         HIP_TRY(hipGetLastError());
-        switch (lm) {
-          case 2: hipLaunchKernelGGL(k_fin_init<2>, dim3(B), dim3(kFoldThreads), 0, s, gd, B, pass); break;
-          case 4: hipLaunchKernelGGL(k_fin_init<4>, dim3(B), dim3(kFoldThreads), 0, s, gd, B, pass); break;
-          case 8: hipLaunchKernelGGL(k_fin_init<8>, dim3(B), dim3(kFoldThreads), 0, s, gd, B, pass); break;
-          default: hipLaunchKernelGGL(k_fin_init<16>, dim3(B), dim3(kFoldThreads), 0, s, gd, B, pass); break;
-        }
+        hipLaunchKernelGGL(k_fin_init, dim3(B), dim3(kFoldThreads), 0, s, gd, B, pass);
         HIP_TRY(hipGetLastError());
       }
     }
@@ -1713,6 +2015,24 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
   } while (0)
 #define PMRF_LAUNCH_ITER(LM)                                                                                  \
   do {                                                                                                        \
+    if (fused && t > 0)                                                                                       \
+      PMRF_LAUNCH((k_iter<LM, false, true, true>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, desc[0], B, \
+                  blocks_iter, t);                                                                            \
+    else if (persist && B == 1)                                                                               \
+      PMRF_LAUNCH((k_iter<LM, true, true>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, desc[0], B,           \
+                  blocks_iter, t);                                                                            \
+    else if (persist)                                                                                         \
+      PMRF_LAUNCH((k_iter<LM, true, false>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, desc[0], B,          \
+                  blocks_iter, t);                                                                            \
+    else if (B == 1)                                                                                          \
+      PMRF_LAUNCH((k_iter<LM, false, true>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, desc[0], B,          \
+                  blocks_iter, t);                                                                            \
+    else                                                                                                      \
+      PMRF_LAUNCH((k_iter<LM, false, false>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, desc[0], B,         \
+                  blocks_iter, t);                                                                            \
+  } while (0)
+#define PMRF_LAUNCH_ITER_UNFUSED(LM)                                                                          \
+  do {                                                                                                        \
     if (persist && B == 1)                                                                                    \
       PMRF_LAUNCH((k_iter<LM, true, true>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, desc[0], B,           \
                   blocks_iter, t);                                                                            \
@@ -1731,8 +2051,8 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
         switch (lm) {
           case 2: PMRF_LAUNCH_ITER(2); break;
           case 4: PMRF_LAUNCH_ITER(4); break;
-          case 8: PMRF_LAUNCH_ITER(8); break;
-          default: PMRF_LAUNCH_ITER(16); break;
+          case 8: PMRF_LAUNCH_ITER_UNFUSED(8); break;
+          default: PMRF_LAUNCH_ITER_UNFUSED(16); break;
         }
         HIP_TRY(hipGetLastError());
       }
@@ -1745,24 +2065,19 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
         }
       }
 #undef PMRF_LAUNCH_ITER
+#undef PMRF_LAUNCH_ITER_UNFUSED
 #undef PMRF_LAUNCH_PK
 #undef PMRF_LAUNCH
       HIP_TRY(hipGetLastError());
-#define PMRF_LAUNCH_FOLD(LM)                                                                                \
-  do {                                                                                                      \
-    if (B == 1)                                                                                             \
-      hipLaunchKernelGGL((k_fold<LM, true>), dim3(B), dim3(kFoldThreads), 0, s, gd, desc[0], B, t + 1);      \
-    else                                                                                                    \
-      hipLaunchKernelGGL((k_fold<LM, false>), dim3(B), dim3(kFoldThreads), 0, s, gd, desc[0], B, t + 1);     \
-  } while (0)
-      switch (lm) {  // the parameter update of iteration t
-        case 2: PMRF_LAUNCH_FOLD(2); break;
-        case 4: PMRF_LAUNCH_FOLD(4); break;
-        case 8: PMRF_LAUNCH_FOLD(8); break;
-        default: PMRF_LAUNCH_FOLD(16); break;
+      // the parameter update of iteration t: here, or (fused) inside the next
+      // iteration launch and after the last one
+      if (!fused || t + 1 == max_iters) {
+        if (B == 1)
+          hipLaunchKernelGGL((k_fold<true>), dim3(B), dim3(kFoldThreads), 0, s, gd, desc[0], B, t + 1);
+        else
+          hipLaunchKernelGGL((k_fold<false>), dim3(B), dim3(kFoldThreads), 0, s, gd, desc[0], B, t + 1);
+        HIP_TRY(hipGetLastError());
       }
-#undef PMRF_LAUNCH_FOLD
-      HIP_TRY(hipGetLastError());
     }
     hipLaunchKernelGGL(k_final, dim3(blocks_vert), dim3(256), 0, s, gd, B);
     HIP_TRY(hipGetLastError());

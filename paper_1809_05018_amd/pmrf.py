@@ -312,10 +312,12 @@ def pmrf_profile_end():
 
 
 # Launch shapes the autotuner tries: (mode, waves_per_block, tiles_per_wave,
-# blocks_per_cu).  Graph replay with 2, 4 or 8 waves per block, the
-# persistent grid with 4 or 8 resident blocks per compute unit, and direct
-# launches.
-AUTOTUNE_SHAPES = ((1, 4, 0, 0), (1, 2, 0, 0), (1, 8, 0, 0), (2, 4, 0, 4), (2, 4, 0, 8), (3, 4, 0, 0))
+# blocks_per_cu).  Graph replay with the automatic block size (one wave per
+# chunk of a single graph's superchunks, 4 for a batch) and with 2, 4, 8 or 16
+# waves per block, the persistent grid with 4 or 8 resident blocks per compute
+# unit, and direct launches with the automatic and the 4-wave block.
+AUTOTUNE_SHAPES = ((1, 0, 0, 0), (1, 4, 0, 0), (1, 2, 0, 0), (1, 8, 0, 0), (1, 16, 0, 0), (2, 4, 0, 4),
+                   (2, 4, 0, 8), (3, 0, 0, 0), (3, 4, 0, 0))
 
 
 def autotune_launch(run, shapes=AUTOTUNE_SHAPES, reps=3, sync=None, clock=time.perf_counter):
