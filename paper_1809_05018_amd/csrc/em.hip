@@ -75,12 +75,10 @@ __device__ __forceinline__ gptr<T> gbl(T *p) {
 __host__ __device__ constexpr int rec_words(int L) { return 3 * L + 4; }
 constexpr int kRecMax = 3 * kMaxLabels + 4;
 
-// Chunks per superchunk (one block, one statistics record): 4, 8 or 16, the
-// smallest that keeps a graph's records at or below kFoldLanes (one record
-// per virtual thread of the fold, so a single graph's fold fits the iteration
-// launch).  Chosen from the graph alone (superchunk_chunks), so it is part of
-// the result's definition and never depends on the launch shape or the batch.
-constexpr int kMaxSuperChunks = 16;
+// Chunks per superchunk (one statistics record): superchunk_chunks_of keeps a
+// graph at or below kFoldLanes records where it can (one record per virtual
+// thread of the fold, so a single graph's fold fits the iteration launch); a
+// function of the graph alone, so part of the result's definition.
 constexpr int kGroupTiles = kChunkTiles;  // packets per neighbourhood-sum group (LDS buffer of 64 minima each)
 // Register budgets of the two-label iteration kernels, as resident waves per
 // SIMD: one graph (a single round of waves; the lower budget keeps every value
@@ -144,6 +142,7 @@ struct GraphDev {
   int32_t pblock0, pnblocks;  // packet-kernel blocks: superchunks [nslot, nsuper), one each
   int32_t vblock0, vnblocks;  // blocks of this graph in a vertex-parallel launch
   const int32_t *perm;        // processing index -> canonical neighbourhood
+  const int32_t *srange;      // member vertex range of superchunk s: [srange[2 s], srange[2 s + 1])
 };
 
 constexpr int kDescPerPack = 12;
@@ -279,7 +278,7 @@ struct LaneStats {
 // with its wave q mod nw.  The partials pass through LDS transposed (slot of
 // virtual thread v: 16 (v mod 16) + v / 16), so stage 2 reads consecutive
 // addresses across a row.
-constexpr int kFoldLanes = 256;    // virtual threads of stage 1
+constexpr int kFoldLanes = kMaxRecordsPerPass;  // virtual threads of stage 1 (256)
 constexpr int kFoldThreads = 256;  // block size of the fold kernels
 constexpr int kFoldGroup = 16;     // words folded per pass (LDS: 16 x 256 doubles)
 
@@ -989,6 +988,77 @@ __device__ __forceinline__ int load_theta(const Ctx &c, Theta<LMAX> &th) {
   return c.st->done;
 }
 
+// ------------------------------------------------------------- LDS staging
+// A slot-kernel block stages the intensities (double) and current labels
+// (byte) of its member vertex range [lo, lo + span) in LDS with coalesced
+// loads when the range holds at most kStageCap vertices (the neighbourhoods of
+// a run of consecutive cliques of an image graph cover a few rows of regions),
+// and its elements then read LDS instead of gathering from memory one
+// vertex per lane.  A wider range gathers from memory as before.  The range of
+// each superchunk comes with the graph's device layout.
+constexpr int kStageCap = 3072;
+constexpr int kStageDoubles = kStageCap + kStageCap / 8;  // LDS of the staged range, in doubles
+constexpr int kStagePerThread = 3;                         // entries a thread requests together
+
+struct Stage {
+  int lo, span;
+  bool on;  // uniform across the block
+};
+
+// The member range of chunks [c0, c1) (whole superchunks): scalar loads.
+__device__ __forceinline__ Stage block_stage(const GraphDev &G, int c0, int c1) {
+  const int sc = G.sc;
+  const int s0 = c0 / sc, s1 = max(s0 + 1, (c1 + sc - 1) / sc);
+  gptr<const int32_t> r = gbl(G.srange);
+  int lo = r[2 * s0], hi = r[2 * s0 + 1];
+  for (int sp = s0 + 1; sp < s1; ++sp) {
+    lo = min(lo, r[2 * sp]);
+    hi = max(hi, r[2 * sp + 1]);
+  }
+  Stage sg;
+  sg.lo = lo;
+  sg.span = hi - lo;
+  sg.on = sg.span > 0 && sg.span <= kStageCap;
+  return sg;
+}
+
+// Staging of entries [i0, i0 + blockDim.x * kStagePerThread): requested into
+// registers (every lane loads; lanes past the range repeat its last entry) ...
+struct StageIn {
+  double y[kStagePerThread];
+  int x[kStagePerThread];
+};
+__device__ __forceinline__ void stage_issue(gptr<const double> y, gptr<const int32_t> x, const Stage &sg, int i0,
+                                            StageIn &si) {
+#pragma unroll
+  for (int k = 0; k < kStagePerThread; ++k) {
+    const int i = min(i0 + k * (int)blockDim.x + (int)threadIdx.x, sg.span - 1);
+    si.y[k] = y[sg.lo + i];
+    si.x[k] = x[sg.lo + i];
+  }
+}
+// ... and written to LDS once they arrive.
+__device__ __forceinline__ void stage_commit(const Stage &sg, int i0, const StageIn &si, double *sy, uint8_t *sx) {
+#pragma unroll
+  for (int k = 0; k < kStagePerThread; ++k) {
+    const int i = i0 + k * (int)blockDim.x + (int)threadIdx.x;
+    if (i < sg.span) {
+      sy[i] = si.y[k];
+      sx[i] = (uint8_t)si.x[k];
+    }
+  }
+}
+// The whole range, first part already requested in si (the caller synchronises).
+__device__ __forceinline__ void stage_rest(gptr<const double> y, gptr<const int32_t> x, const Stage &sg, StageIn &si,
+                                           double *sy, uint8_t *sx) {
+  const int step = (int)blockDim.x * kStagePerThread;
+  stage_commit(sg, 0, si, sy, sx);
+  for (int i0 = step; i0 < sg.span; i0 += step) {
+    stage_issue(y, x, sg, i0, si);
+    stage_commit(sg, i0, si, sy, sx);
+  }
+}
+
 // A chunk's loads on the slot layout, requested by chunk_issue and consumed by
 // chunk_run.
 struct ChunkIn {
@@ -1034,16 +1104,25 @@ __device__ __forceinline__ void chunk_stream(const Ctx &c, int ck, ChunkIn &in, 
 // The label and intensity gathers of a chunk whose slot words chunk_stream
 // requested (each waits only for its own packet's slot words).
 template <int LMAX>
-__device__ __forceinline__ void chunk_gather(const Ctx &c, int ck, ChunkIn &in, int lane) {
+__device__ __forceinline__ void chunk_gather(const Ctx &c, int ck, ChunkIn &in, int lane, const Stage &sg,
+                                             const double *sy, const uint8_t *sx) {
   const int tb = ck * kChunkTiles;
   const unsigned ul = (unsigned)lane;
   const int flags = kPrefetchHi<LMAX> ? (int)hdr_field(in.hw, kDwFlags) : 0;
 #pragma unroll
   for (int i = 0; i < kChunkTiles; ++i) {
-    // an empty slot reads vertex 0; nothing of an empty slot is used
-    const unsigned vv = (uint32_t)in.v[i] != kSlotEmpty ? (uint32_t)in.v[i] & kSlotVidMask : 0u;
-    in.xv[i] = c.xr[vv];
-    in.yv[i] = c.y[vv];
+    // an empty slot reads vertex 0 (staged: the range's first entry); nothing
+    // of an empty slot is used
+    const bool valid = (uint32_t)in.v[i] != kSlotEmpty;
+    if (sg.on) {
+      const int li = valid ? (int)((uint32_t)in.v[i] & kSlotVidMask) - sg.lo : 0;
+      in.xv[i] = sx[li];
+      in.yv[i] = sy[li];
+    } else {
+      const unsigned vv = valid ? (uint32_t)in.v[i] & kSlotVidMask : 0u;
+      in.xv[i] = c.xr[vv];
+      in.yv[i] = c.y[vv];
+    }
     in.ah[i] = 0;
     if (kPrefetchHi<LMAX> && ((flags >> (kHdrMidShift + i)) & 1))
       in.ah[i] = (c.smask_hi + (size_t)tb * kWave)[i * kWave + ul];
@@ -1068,11 +1147,6 @@ __device__ __forceinline__ HoodPre load_pre(const Ctx &c, int h0, int hend, int 
   return pre;
 }
 
-template <int LMAX>
-__device__ __forceinline__ void chunk_issue(const Ctx &c, int ck, ChunkIn &in, int lane) {
-  chunk_stream<LMAX>(c, ck, in, lane);
-  chunk_gather<LMAX>(c, ck, in, lane);
-}
 
 // Second half: the offsets and window values of the chunk's first 64
 // neighbourhoods are requested, then the element passes, the owner list, the
@@ -1107,22 +1181,6 @@ __device__ __forceinline__ void chunk_run(const Ctx &c, int ck, const ChunkIn &i
   lean_hoods<LMAX>(c, h0, hend, gstart, pre, cs, mb, lane);
   wave_lds_sync();
   cs.store(row, mb, c.L, lane);  // the minima are no longer needed
-}
-
-// Chunk on the slot layout: chunk_issue, then chunk_run.  The slot kernel is
-// given only superchunks without LARGE packets and only windows of at most
-// kPreWindow (the host sends the others to the packet kernel).  Nothing is
-// written when skip is set (the run has ended or is done) or, with READ_DONE,
-// when the run state's done flag is set (read after the chunk's loads are
-// requested, so they need not wait for it).  th arrives with the chunk's loads
-// (requested before the kernel's first store).
-template <int LMAX, bool READ_DONE>
-__device__ __forceinline__ void chunk_slots(const Ctx &c, int ck, bool skip, const Theta<LMAX> &th, double *row,
-                                            double *mb, double *od, int *oa, int lane) {
-  ChunkIn in;
-  chunk_issue<LMAX>(c, ck, in, lane);
-  if (skip || (READ_DONE && c.st->done != 0)) return;
-  chunk_run<LMAX>(c, ck, in, th, row, mb, od, oa, lane);
 }
 
 // One statistics chunk: packets [ck * kChunkTiles, min(ntiles, (ck + 1) * kChunkTiles)).
@@ -1459,15 +1517,24 @@ __device__ __forceinline__ void iter_superchunk(const GraphDev &G, int c0, int c
     // single graph: the slot path's descriptor fields (kernel arguments)
     // arrive in one batch of scalar loads, before the first branch
     // (otherwise each branch waits for the fields it tests before the next
-    // ones are even requested); the run state's done flag is read inside
-    // the chunk, after the chunk's loads are requested.  (A batch looks its
-    // descriptor up in memory; pinning it there costs registers.)
+    // ones are even requested).  (A batch looks its descriptor up in memory;
+    // pinning it there costs registers.)
     if constexpr (SINGLE)
       asm volatile("" ::"s"(c.chdr), "s"(c.svid), "s"(c.smask), "s"(c.st), "s"(c.hood_ptr), "s"(c.y), "s"(c.xr),
                    "s"(c.xw), "s"(c.ring), "s"(c.H), "s"(c.W), "s"(c.L), "s"(c.ntiles), "s"(c.nchunks), "s"(nw));
-    const bool skip = SINGLE ? ended : (done_flag != 0 || ended);
-    for (int ck = c0 + wave; ck < c1; ck += nw)
-      chunk_slots<LMAX, SINGLE>(c, ck, skip, th, part[ck - c0], mb, od, oa, lane);
+    // (no staging here: a barrier at the start of every block and the
+    // staged range's LDS cost more than the gathers they save where blocks
+    // run in many rounds; the fused single-graph launch stages)
+    const Stage sg{0, 0, false};
+    // nothing is written once the run has ended or is done (the run state's
+    // done flag is read with the parameters, before the chunk's loads wait)
+    const bool skip = ended || done_flag != 0;
+    for (int ck = c0 + wave; ck < c1; ck += nw) {
+      ChunkIn in;
+      chunk_stream<LMAX>(c, ck, in, lane);
+      chunk_gather<LMAX>(c, ck, in, lane, sg, nullptr, nullptr);
+      if (!skip) chunk_run<LMAX>(c, ck, in, th, part[ck - c0], mb, od, oa, lane);
+    }
   } else {
     if (!(done_flag != 0 || ended))
       for (int ck = c0 + wave; ck < c1; ck += nw) chunk_packets<LMAX>(c, ck, th, part[ck - c0], mb, pl, lane);
@@ -1518,9 +1585,9 @@ struct FusedLds {
 // buffers, unused until the fold is over).
 template <int LMAX>
 __device__ __forceinline__ void iter_superchunk_fused(const GraphDev &G, int b, int t,
-                                                      double (*part)[rec_words(LMAX)], double *scr, double *mb,
-                                                      double *od, int *oa, FusedLds<LMAX> &fl, int nw, int wave,
-                                                      int lane) {
+                                                      double (*part)[rec_words(LMAX)], double *sy, uint8_t *sx,
+                                                      double *scr, double *mb, double *od, int *oa,
+                                                      FusedLds<LMAX> &fl, int nw, int wave, int lane) {
   // one superchunk per block (bc == sc, every superchunk on the slot kernel)
   constexpr int WORDS = rec_words(LMAX);
   static_assert(WORDS <= kFoldGroup, "the fused fold takes one pass of words");
@@ -1543,17 +1610,21 @@ __device__ __forceinline__ void iter_superchunk_fused(const GraphDev &G, int b, 
   const Ctx c = make_ctx(G, t);
   const int c0 = slot_c0(G, b), c1 = slot_c1(G, b);
   const int ck0 = c0 + wave;
+  const Stage sg = block_stage(G, c0, c1);
   // requested unconditionally (a wave without a chunk of its own requests the
   // superchunk's last one and drops it), so no branch joins the loads in
   // flight during the fold
   ChunkIn in;
   const int ckl = min(ck0, c1 - 1);
   chunk_stream<LMAX>(c, ckl, in, lane);
+  StageIn si;
+  if (sg.on) stage_issue(c.y, c.xr, sg, 0, si);
   if (wave < kFoldLanes / 64) {
     const int v = wave * 64 + lane;
 #pragma unroll
     for (int j = 0; j < WORDS; ++j) scr[fold_slot(j, v)] = rv[j];  // words >= L's are zero and never read
   }
+  if (sg.on) stage_rest(c.y, c.xr, sg, si, sy, sx);
   __syncthreads();
   if (wave == 0) {
     fold_stage2(scr, words, fl.tot, 1, 0, lane);
@@ -1580,9 +1651,13 @@ __device__ __forceinline__ void iter_superchunk_fused(const GraphDev &G, int b, 
     th.lg[l] = uniform_f64(fl.lg[l]);
   }
   const bool stop = __builtin_amdgcn_readfirstlane(fl.stop) != 0;
-  chunk_gather<LMAX>(c, ckl, in, lane);
+  chunk_gather<LMAX>(c, ckl, in, lane, sg, sy, sx);
   if (!stop && ck0 < c1) chunk_run<LMAX>(c, ck0, in, th, part[ck0 - c0], mb, od, oa, lane);
-  for (int ck = ck0 + nw; ck < c1; ck += nw) chunk_slots<LMAX, false>(c, ck, stop, th, part[ck - c0], mb, od, oa, lane);
+  for (int ck = ck0 + nw; ck < c1; ck += nw) {
+    chunk_stream<LMAX>(c, ck, in, lane);
+    chunk_gather<LMAX>(c, ck, in, lane, sg, sy, sx);
+    if (!stop) chunk_run<LMAX>(c, ck, in, th, part[ck - c0], mb, od, oa, lane);
+  }
   __syncthreads();
   if (!stop) store_records<LMAX>(G, c0, c1, t, part);
 }
@@ -1598,21 +1673,27 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(LMAX <= 2 
     const GraphDev *__restrict__ graphs, const int32_t *__restrict__ block_graph, const GraphDev g1, int B,
     int nsuper_total, int t) {
   static_assert(!FUSED || (SINGLE && !PERSIST), "the fused launch is for one graph, one block per superchunk");
+  // dynamic LDS: one region of kWaveLds doubles per wave, after (fused
+  // launch) the staged range (kStageCap doubles, then kStageCap bytes)
   extern __shared__ double smem[];
   __shared__ double part[kMaxSuperChunks][rec_words(LMAX)];
   const int nw = blockDim.x >> 6, wave = wave_id(), lane = threadIdx.x & 63;
-  double *mb = smem + wave * kWaveLds;
+  double *sy = smem;
+  uint8_t *sx = reinterpret_cast<uint8_t *>(smem + kStageCap);
+  double *wbase = FUSED ? smem + kStageDoubles : smem;
+  double *mb = wbase + wave * kWaveLds;
   uint64_t *pl = reinterpret_cast<uint64_t *>(mb + kGroupTiles * 64);
   double *od = mb + kGroupTiles * 64 + 64;
   int *oa = reinterpret_cast<int *>(od + kOwnCap);
   if constexpr (FUSED) {
     __shared__ FusedLds<LMAX> fl;
-    iter_superchunk_fused<LMAX>(g1, xcd_block(blockIdx.x, gridDim.x), t, part, smem, mb, od, oa, fl, nw, wave, lane);
+    iter_superchunk_fused<LMAX>(g1, xcd_block(blockIdx.x, gridDim.x), t, part, sy, sx, wbase, mb, od, oa, fl, nw,
+                                wave, lane);
   } else if constexpr (!PERSIST) {
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     if constexpr (SINGLE) {
-      iter_superchunk<LMAX, false, true>(g1, slot_c0(g1, blk), slot_c1(g1, blk), t, part, mb, pl, od, oa, nw, wave,
-                                         lane);
+      iter_superchunk<LMAX, false, true>(g1, slot_c0(g1, blk), slot_c1(g1, blk), t, part, mb, pl, od, oa, nw,
+                                         wave, lane);
     } else {
       const GraphDev &G = graphs[block_graph[blk]];
       const int b = blk - G.block0;
@@ -1621,8 +1702,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(LMAX <= 2 
   } else {
     for (int sc = blockIdx.x; sc < nsuper_total; sc += gridDim.x) {
       if constexpr (SINGLE) {
-        iter_superchunk<LMAX, false, true>(g1, slot_c0(g1, sc), slot_c1(g1, sc), t, part, mb, pl, od, oa, nw, wave,
-                                           lane);
+        iter_superchunk<LMAX, false, true>(g1, slot_c0(g1, sc), slot_c1(g1, sc), t, part, mb, pl, od, oa, nw,
+                                           wave, lane);
       } else {
         const GraphDev &G = graphs[block_graph[sc]];
         const int b = sc - G.block0;
@@ -1792,10 +1873,7 @@ pmrf_status check_item(const pmrf_em_item &it, int idx) {
 
 int64_t n_chunks(const pmrf_hoods *h) { return ((int64_t)h->tiles.size() + kChunkTiles - 1) / kChunkTiles; }
 int64_t vert_blocks(const pmrf_hoods *h) { return std::max<int64_t>(1, ((int64_t)h->n + kVertPerBlock - 1) / kVertPerBlock); }
-int32_t superchunk_chunks(const pmrf_hoods *h) {
-  const int64_t nc = n_chunks(h);
-  return nc <= 4 * kFoldLanes ? 4 : nc <= 8 * kFoldLanes ? 8 : kMaxSuperChunks;
-}
+int32_t superchunk_chunks(const pmrf_hoods *h) { return superchunk_chunks_of(n_chunks(h)); }
 int64_t n_super(const pmrf_hoods *h) {
   const int64_t sc = superchunk_chunks(h);
   return std::max<int64_t>(1, (n_chunks(h) + sc - 1) / sc);
@@ -1939,6 +2017,7 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
     G.pnblocks = sp.pnblocks;
     blocks_pk += G.pnblocks;
     G.perm = reinterpret_cast<const int32_t *>(hb + h->layout.perm_off);
+    G.srange = reinterpret_cast<const int32_t *>(hb + h->layout.srange_off);
     G.vblock0 = blocks_vert;
     G.vnblocks = (int32_t)vert_blocks(h);
     blocks_vert += G.vnblocks;
@@ -1960,8 +2039,11 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
   const bool fused = B == 1 && blocks_pk == 0 && !persist && lm <= kFusedMaxLabels &&
                      desc[0].nsuper <= kFoldLanes && desc[0].nslot == desc[0].nsuper && desc[0].nchunks >= 1 &&
                      shape.waves_per_block >= kFoldLanes / 64;
-  size_t lds = (size_t)(kWaveLds * shape.waves_per_block) * 8;
-  if (fused) lds = std::max(lds, (size_t)rec_words(lm) * kFoldLanes * 8);
+  // dynamic LDS of the slot kernel: the staged range, then the waves' regions
+  // (which hold the fused fold's partials before any chunk is computed); of
+  // the packet kernel: the waves' regions
+  const size_t lds_pk = (size_t)(kWaveLds * shape.waves_per_block) * 8;
+  const size_t lds_fused = (size_t)kStageDoubles * 8 + std::max(lds_pk, (size_t)rec_words(lm) * kFoldLanes * 8);
   const bool events = g_prof.on && !no_alloc;
   // grid of the iteration kernel: one block per superchunk, or in persistent
   // mode a machine-sized grid whose blocks walk the superchunks
@@ -2006,47 +2088,48 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
       hipEvent_t slot_start = ev0, slot_stop = blocks_pk > 0 ? nullptr : ev1;
       hipEvent_t pk_start = blocks_iter > 0 ? nullptr : ev0, pk_stop = ev1;
 // plain launches unless the iteration is being timed (graph capture never is)
-#define PMRF_LAUNCH(KERNEL, GRID, START, STOP, ...)                                                          \
+#define PMRF_LAUNCH(KERNEL, GRID, LDS, START, STOP, ...)                                                     \
   do {                                                                                                        \
     if ((START) || (STOP))                                                                                    \
-      hipExtLaunchKernelGGL(KERNEL, GRID, dim3(threads), lds, s, START, STOP, 0, __VA_ARGS__);                \
+      hipExtLaunchKernelGGL(KERNEL, GRID, dim3(threads), LDS, s, START, STOP, 0, __VA_ARGS__);                \
     else                                                                                                      \
-      hipLaunchKernelGGL(KERNEL, GRID, dim3(threads), lds, s, __VA_ARGS__);                                   \
+      hipLaunchKernelGGL(KERNEL, GRID, dim3(threads), LDS, s, __VA_ARGS__);                                   \
   } while (0)
+#define PMRF_LAUNCH_LDS(KERNEL, GRID, ...) PMRF_LAUNCH(KERNEL, GRID, lds_pk, __VA_ARGS__)
 #define PMRF_LAUNCH_ITER(LM)                                                                                  \
   do {                                                                                                        \
     if (fused && t > 0)                                                                                       \
-      PMRF_LAUNCH((k_iter<LM, false, true, true>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, desc[0], B, \
-                  blocks_iter, t);                                                                            \
+      PMRF_LAUNCH((k_iter<LM, false, true, true>), dim3(grid_iter), lds_fused, slot_start, slot_stop, gd, block_graph, \
+                  desc[0], B, blocks_iter, t);                                                                \
     else if (persist && B == 1)                                                                               \
-      PMRF_LAUNCH((k_iter<LM, true, true>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, desc[0], B,           \
+      PMRF_LAUNCH_LDS((k_iter<LM, true, true>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, desc[0], B,           \
                   blocks_iter, t);                                                                            \
     else if (persist)                                                                                         \
-      PMRF_LAUNCH((k_iter<LM, true, false>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, desc[0], B,          \
+      PMRF_LAUNCH_LDS((k_iter<LM, true, false>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, desc[0], B,          \
                   blocks_iter, t);                                                                            \
     else if (B == 1)                                                                                          \
-      PMRF_LAUNCH((k_iter<LM, false, true>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, desc[0], B,          \
+      PMRF_LAUNCH_LDS((k_iter<LM, false, true>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, desc[0], B,          \
                   blocks_iter, t);                                                                            \
     else                                                                                                      \
-      PMRF_LAUNCH((k_iter<LM, false, false>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, desc[0], B,         \
+      PMRF_LAUNCH_LDS((k_iter<LM, false, false>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, desc[0], B,         \
                   blocks_iter, t);                                                                            \
   } while (0)
 #define PMRF_LAUNCH_ITER_UNFUSED(LM)                                                                          \
   do {                                                                                                        \
     if (persist && B == 1)                                                                                    \
-      PMRF_LAUNCH((k_iter<LM, true, true>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, desc[0], B,           \
+      PMRF_LAUNCH_LDS((k_iter<LM, true, true>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, desc[0], B,           \
                   blocks_iter, t);                                                                            \
     else if (persist)                                                                                         \
-      PMRF_LAUNCH((k_iter<LM, true, false>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, desc[0], B,          \
+      PMRF_LAUNCH_LDS((k_iter<LM, true, false>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, desc[0], B,          \
                   blocks_iter, t);                                                                            \
     else if (B == 1)                                                                                          \
-      PMRF_LAUNCH((k_iter<LM, false, true>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, desc[0], B,          \
+      PMRF_LAUNCH_LDS((k_iter<LM, false, true>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, desc[0], B,          \
                   blocks_iter, t);                                                                            \
     else                                                                                                      \
-      PMRF_LAUNCH((k_iter<LM, false, false>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, desc[0], B,         \
+      PMRF_LAUNCH_LDS((k_iter<LM, false, false>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, desc[0], B,         \
                   blocks_iter, t);                                                                            \
   } while (0)
-#define PMRF_LAUNCH_PK(LM) PMRF_LAUNCH(k_iter_packets<LM>, dim3(blocks_pk), pk_start, pk_stop, gd, B, t)
+#define PMRF_LAUNCH_PK(LM) PMRF_LAUNCH(k_iter_packets<LM>, dim3(blocks_pk), lds_pk, pk_start, pk_stop, gd, B, t)
       if (blocks_iter > 0) {
         switch (lm) {
           case 2: PMRF_LAUNCH_ITER(2); break;
@@ -2067,6 +2150,7 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
 #undef PMRF_LAUNCH_ITER
 #undef PMRF_LAUNCH_ITER_UNFUSED
 #undef PMRF_LAUNCH_PK
+#undef PMRF_LAUNCH_LDS
 #undef PMRF_LAUNCH
       HIP_TRY(hipGetLastError());
       // the parameter update of iteration t: here, or (fused) inside the next
@@ -2102,7 +2186,7 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
   put(&grid_iter, sizeof grid_iter);
   put(&blocks_vert, sizeof blocks_vert);
   put(&threads, sizeof threads);
-  put(&lds, sizeof lds);
+  put(&lds_pk, sizeof lds_pk);
   put(&any_init, sizeof any_init);
   put(&d_desc, sizeof d_desc);
   put(desc.data(), desc.size() * sizeof(GraphDev));

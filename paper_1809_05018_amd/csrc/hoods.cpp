@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cstring>
 #include <new>
 
@@ -286,12 +287,14 @@ extern "C" pmrf_status pmrf_build_neighborhoods(int32_t n, const int32_t *row_pt
     const int64_t nchunks = (ntiles + kChunkTiles - 1) / kChunkTiles;
     bool any_mid = false;
     for (const TileDesc &t : hd->tiles) any_mid |= t.kind == kMid;
-    // padded to whole chunks (empty slots), so a chunk's loads need no bounds
-    const size_t slots = (size_t)(nchunks * kChunkTiles) * kWave;
+    // padded to whole chunks (empty slots), so a chunk's loads need no bounds,
+    // and to at least one chunk (an empty graph's one block reads chunk 0)
+    const int64_t chunks_alloc = std::max<int64_t>(1, nchunks);
+    const size_t slots = (size_t)(chunks_alloc * kChunkTiles) * kWave;
     hd->svid.assign(slots, (int32_t)kSlotEmpty);
     hd->smask.assign(slots, 0u);
     hd->smask_hi.assign(any_mid ? slots : 0, 0u);
-    hd->chdr.assign((size_t)nchunks, ChunkHdr{});
+    hd->chdr.assign((size_t)chunks_alloc, ChunkHdr{});
     for (int64_t ti = 0; ti < ntiles; ++ti) {
       const TileDesc &t = hd->tiles[ti];
       if (t.kind == kLarge) continue;
@@ -319,17 +322,39 @@ extern "C" pmrf_status pmrf_build_neighborhoods(int32_t n, const int32_t *row_pt
         c.elem_off[i] = (uint16_t)std::min<int64_t>(t.elem_start - c.elem_start, 0xffff);
       }
     }
+    // member vertex range of each superchunk's slot-layout packets
+    {
+      const int64_t sc = superchunk_chunks_of(nchunks);
+      const int64_t nsuper = std::max<int64_t>(1, (nchunks + sc - 1) / sc);
+      hd->srange.assign((size_t)(2 * nsuper), 0);
+      for (int64_t sp = 0; sp < nsuper; ++sp) {
+        int32_t lo = INT32_MAX, hi = INT32_MIN;
+        const size_t s0 = (size_t)(sp * sc * kChunkTiles) * kWave;
+        const size_t s1 = std::min(hd->svid.size(), (size_t)((sp + 1) * sc * kChunkTiles) * kWave);
+        for (size_t k = s0; k < s1; ++k) {
+          const uint32_t w = (uint32_t)hd->svid[k];
+          if (w == kSlotEmpty) continue;
+          const int32_t v = (int32_t)(w & kSlotVidMask);
+          lo = std::min(lo, v);
+          hi = std::max(hi, v + 1);
+        }
+        if (lo > hi) lo = hi = 0;
+        hd->srange[2 * sp] = lo;
+        hd->srange[2 * sp + 1] = hi;
+      }
+    }
     DeviceLayout &L = hd->layout;
     L.tiles_off = 0;
     L.hptr_off = align_up(ntiles * (int64_t)sizeof(TileDesc), 256);
     L.vid_off = L.hptr_off + align_up((hd->H + 1) * 4, 256);
     L.mask_off = L.vid_off + align_up(hd->M * 4, 256);
     L.chdr_off = L.mask_off + align_up((int64_t)hd->mask.size() * 4, 256);
-    L.svid_off = L.chdr_off + align_up(nchunks * (int64_t)sizeof(ChunkHdr), 256);
+    L.svid_off = L.chdr_off + align_up((int64_t)hd->chdr.size() * (int64_t)sizeof(ChunkHdr), 256);
     L.smask_off = L.svid_off + align_up((int64_t)hd->svid.size() * 4, 256);
     L.smaskhi_off = L.smask_off + align_up((int64_t)hd->smask.size() * 4, 256);
     L.perm_off = L.smaskhi_off + align_up((int64_t)hd->smask_hi.size() * 4, 256);
-    L.total = L.perm_off + align_up(hd->H * 4, 256);
+    L.srange_off = L.perm_off + align_up(hd->H * 4, 256);
+    L.total = L.srange_off + align_up((int64_t)hd->srange.size() * 4, 256);
     if (L.total == 0) L.total = 256;
   } catch (const std::bad_alloc &) {
     delete hd;
@@ -392,6 +417,8 @@ extern "C" pmrf_status pmrf_hoods_upload(const pmrf_hoods *h, void *d_buf, int64
     e = hipMemcpyAsync(base + h->layout.smask_off, h->smask.data(), h->smask.size() * 4, hipMemcpyHostToDevice, s);
   if (e == hipSuccess && !h->perm.empty())
     e = hipMemcpyAsync(base + h->layout.perm_off, h->perm.data(), h->perm.size() * 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && !h->srange.empty())
+    e = hipMemcpyAsync(base + h->layout.srange_off, h->srange.data(), h->srange.size() * 4, hipMemcpyHostToDevice, s);
   if (e == hipSuccess && !h->smask_hi.empty())
     e = hipMemcpyAsync(base + h->layout.smaskhi_off, h->smask_hi.data(), h->smask_hi.size() * 4,
                        hipMemcpyHostToDevice, s);

@@ -62,11 +62,21 @@ constexpr uint32_t kSlotVidMask = (1u << kSlotJShift) - 1u;
 constexpr int32_t kMaxSlotVertices = (1 << kSlotJShift) - 1;
 constexpr int kHdrMidShift = 8;
 
+// Chunks per superchunk (one statistics record): 4, 8 or 16, the smallest
+// that keeps a graph at or below kMaxRecordsPerPass records.  A function of
+// the graph alone, so it belongs to the result's definition.
+constexpr int kMaxRecordsPerPass = 256;
+constexpr int kMaxSuperChunks = 16;
+inline int32_t superchunk_chunks_of(int64_t nchunks) {
+  return nchunks <= 4 * kMaxRecordsPerPass ? 4 : nchunks <= 8 * kMaxRecordsPerPass ? 8 : kMaxSuperChunks;
+}
+
 // Offsets (bytes) of the arrays inside the uploaded device buffer.
 struct DeviceLayout {
   int64_t tiles_off, hptr_off, vid_off, mask_off;
   int64_t chdr_off, svid_off, smask_off, smaskhi_off;  // slot layout
   int64_t perm_off;                                     // processing index -> canonical neighbourhood
+  int64_t srange_off;                                   // member vertex range of each superchunk
   int64_t total;
 };
 
@@ -96,6 +106,9 @@ struct pmrf_hoods {
   std::vector<pmrf::ChunkHdr> chdr;               // one per chunk of packets
   std::vector<int32_t> svid;                      // slot layout: member id (-1: unused slot)
   std::vector<uint32_t> smask, smask_hi;          // slot layout: adjacency words 0 and 1 (the latter only if MID packets exist)
+  // per superchunk s: [srange[2 s], srange[2 s + 1]) holds the member vertices
+  // of its slot-layout packets (empty range where it has none)
+  std::vector<int32_t> srange;
   pmrf::DeviceLayout layout{};
 };
 
