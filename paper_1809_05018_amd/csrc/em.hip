@@ -98,6 +98,17 @@ struct LabelTheta {
   double mu, sigma, w, lg;
 };
 
+// Per vertex, in the workspace: its intensity and its label in the two label
+// buffers (iteration t reads x[t & 1] and writes x[(t + 1) & 1]), so that one
+// 16-byte gather brings both values an element needs (one cache line per
+// vertex instead of one per array).
+struct VertexRec {
+  double y;
+  int32_t x[2];
+};
+static_assert(sizeof(VertexRec) == 16, "VertexRec layout");
+typedef int32_t v4i __attribute__((ext_vector_type(4)));
+
 struct GraphState {
   LabelTheta th[2][kMaxLabels];  // parameters of iteration t in th[t & 1]
   int32_t done;                // 1: no further iterations (early exit or error)
@@ -121,8 +132,8 @@ struct GraphDev {
   const uint32_t *smask, *smask_hi;
   const int32_t *hood_ptr;  // element offset of each neighbourhood, H+1 entries
   const double *y;
-  int32_t *x0;   // caller labels (even iterations read here)
-  int32_t *x1;   // workspace labels (odd iterations read here)
+  int32_t *x0;    // caller labels: read at the start, written at the end
+  VertexRec *vr;  // workspace: intensities and both label buffers
   double *ring;  // (W+1) x H neighbourhood sums
   double *thist;
   GraphState *st;
@@ -431,14 +442,22 @@ struct Ctx {
   gptr<const int32_t> svid;
   gptr<const uint32_t> smask, smask_hi;
   gptr<const int32_t> hood_ptr;
-  gptr<const double> y;
-  gptr<const int32_t> xr;
-  gptr<int32_t> xw;
+  gptr<const VertexRec> vr;  // intensities and labels
+  gptr<int32_t> xw;          // labels written this iteration: xw[4 v] (x[(t + 1) & 1] of vertex v)
+  int par;                   // label buffer read this iteration (t & 1)
   gptr<double> ring;
   gptr<const GraphState> st;
   int H, W, L, P, t, ntiles, nchunks;
   double beta, tol, tie_eps;
 };
+
+// Label (read buffer) and intensity of vertex v: one 16-byte load.
+__device__ __forceinline__ void vrec_load(const Ctx &c, unsigned v, int &x, double &y) {
+  const v4i q = *(gptr<const v4i>)(c.vr + v);
+  y = __longlong_as_double(((long long)q.y << 32) | (unsigned)q.x);
+  x = c.par ? q.w : q.z;
+}
+__device__ __forceinline__ void vrec_store_label(const Ctx &c, int v, int a) { c.xw[4 * (size_t)v] = a; }
 
 __device__ __forceinline__ TileDesc load_tile(gptr<const TileDesc> p) {
   TileDesc td;
@@ -521,8 +540,7 @@ __device__ __forceinline__ Stream load_stream(const Ctx &c, const TileDesc &td, 
 __device__ __forceinline__ Gather load_gather(const Ctx &c, const TileDesc &td, const Stream &st, int lane) {
   Gather r{0, 0.0};
   if (td.kind != kLarge && lane < td.nelem) {
-    r.xv = c.xr[st.v];
-    r.yv = c.y[st.v];
+    vrec_load(c, (unsigned)st.v, r.xv, r.yv);
   }
   return r;
 }
@@ -565,7 +583,7 @@ __device__ __forceinline__ void elem_pass(const Ctx &c, const TileDesc &td, cons
   int a;
   element_energy<LMAX>(th, c.L, c.beta, yv, deg, cnt, m, a, gap, dsel);
   if (owner) {
-    c.xw[v] = a;
+    vrec_store_label(c, v, a);
     ls.add_owner(a, dsel);
     if (gap < c.tie_eps) ls.ties += 1;
   }
@@ -629,7 +647,8 @@ __device__ void do_large(const Ctx &c, const TileDesc &td, const Theta<LMAX> &th
     int xv = 0;
     const bool valid = jj < s;
     if (valid) {
-      xv = c.xr[c.vid[td.elem_start + jj]];
+      double unused;
+      vrec_load(c, (unsigned)c.vid[td.elem_start + jj], xv, unused);
       if ((unsigned)xv >= (unsigned)c.L) ls.err |= 1;
     }
 #pragma unroll
@@ -653,7 +672,8 @@ __device__ void do_large(const Ctx &c, const TileDesc &td, const Theta<LMAX> &th
     bool owner = false;
     if (valid) {
       v = c.vid[td.elem_start + jj];
-      yv = c.y[v];
+      int unused;
+      vrec_load(c, (unsigned)v, unused, yv);
       gptr<const uint32_t> mw = c.mask + td.mask_start + (size_t)jj * W;
       for (int wi = 0; wi < W; ++wi) {
         uint32_t word = mw[wi];
@@ -680,7 +700,7 @@ __device__ void do_large(const Ctx &c, const TileDesc &td, const Theta<LMAX> &th
     int a;
     element_energy<LMAX>(th, c.L, c.beta, yv, deg, cnt, m, a, gap, dsel);
     if (owner) {
-      c.xw[v] = a;
+      vrec_store_label(c, v, a);
       ls.add_owner(a, dsel);
       if (gap < c.tie_eps) ls.ties += 1;
     }
@@ -909,7 +929,7 @@ __device__ __forceinline__ void slot_elem(const Ctx &c, int eoff, bool mid, int 
     const int idx = ocount + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(ob >> 32),
                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)ob, 0u));
     if (owner) {
-      c.xw[v] = a;
+      vrec_store_label(c, v, a);
       od[idx] = dsel;
       oa[idx] = a;
     }
@@ -1028,13 +1048,11 @@ struct StageIn {
   double y[kStagePerThread];
   int x[kStagePerThread];
 };
-__device__ __forceinline__ void stage_issue(gptr<const double> y, gptr<const int32_t> x, const Stage &sg, int i0,
-                                            StageIn &si) {
+__device__ __forceinline__ void stage_issue(const Ctx &c, const Stage &sg, int i0, StageIn &si) {
 #pragma unroll
   for (int k = 0; k < kStagePerThread; ++k) {
     const int i = min(i0 + k * (int)blockDim.x + (int)threadIdx.x, sg.span - 1);
-    si.y[k] = y[sg.lo + i];
-    si.x[k] = x[sg.lo + i];
+    vrec_load(c, (unsigned)(sg.lo + i), si.x[k], si.y[k]);
   }
 }
 // ... and written to LDS once they arrive.
@@ -1049,12 +1067,11 @@ __device__ __forceinline__ void stage_commit(const Stage &sg, int i0, const Stag
   }
 }
 // The whole range, first part already requested in si (the caller synchronises).
-__device__ __forceinline__ void stage_rest(gptr<const double> y, gptr<const int32_t> x, const Stage &sg, StageIn &si,
-                                           double *sy, uint8_t *sx) {
+__device__ __forceinline__ void stage_rest(const Ctx &c, const Stage &sg, StageIn &si, double *sy, uint8_t *sx) {
   const int step = (int)blockDim.x * kStagePerThread;
   stage_commit(sg, 0, si, sy, sx);
   for (int i0 = step; i0 < sg.span; i0 += step) {
-    stage_issue(y, x, sg, i0, si);
+    stage_issue(c, sg, i0, si);
     stage_commit(sg, i0, si, sy, sx);
   }
 }
@@ -1120,8 +1137,7 @@ __device__ __forceinline__ void chunk_gather(const Ctx &c, int ck, ChunkIn &in, 
       in.yv[i] = sy[li];
     } else {
       const unsigned vv = valid ? (uint32_t)in.v[i] & kSlotVidMask : 0u;
-      in.xv[i] = c.xr[vv];
-      in.yv[i] = c.y[vv];
+      vrec_load(c, vv, in.xv[i], in.yv[i]);
     }
     in.ah[i] = 0;
     if (kPrefetchHi<LMAX> && ((flags >> (kHdrMidShift + i)) & 1))
@@ -1262,6 +1278,21 @@ __global__ void k_setup(const GraphDev *graphs, int B) {
     return;
   }
   for (int l = 0; l < G.L; ++l) set_label_theta(st->th[0], l, st->th[0][l].mu, st->th[0][l].sigma);
+}
+
+// The workspace vertex records from the caller's intensities and starting
+// labels (label buffer 0), once per run.
+__global__ void k_vr_init(const GraphDev *graphs, int B) {
+  const GraphDev &G = graphs[find_graph(graphs, B, blockIdx.x, kGridVertex)];
+  const int b = blockIdx.x - G.vblock0;
+  const int stride = G.vnblocks * blockDim.x;
+  for (int v = b * blockDim.x + threadIdx.x; v < G.n; v += stride) {
+    VertexRec r;
+    r.y = G.y[v];
+    r.x[0] = G.x0[v];
+    r.x[1] = 0;
+    G.vr[v] = r;
+  }
 }
 
 // Graph of every slot-kernel block, written once per run (batches only):
@@ -1459,9 +1490,9 @@ __device__ __forceinline__ Ctx make_ctx(const GraphDev &G, int t) {
   c.smask_hi = gbl(G.smask_hi);
   c.st = gbl((const GraphState *)G.st);
   c.hood_ptr = gbl(G.hood_ptr);
-  c.y = gbl(G.y);
-  c.xr = gbl((const int32_t *)((t & 1) ? G.x1 : G.x0));
-  c.xw = gbl((t & 1) ? G.x0 : G.x1);
+  c.vr = gbl((const VertexRec *)G.vr);
+  c.par = t & 1;
+  c.xw = gbl(reinterpret_cast<int32_t *>(G.vr)) + 2 + ((t + 1) & 1);
   c.ring = gbl(G.ring);
   c.H = G.H;
   c.W = G.W;
@@ -1520,8 +1551,8 @@ __device__ __forceinline__ void iter_superchunk(const GraphDev &G, int c0, int c
     // ones are even requested).  (A batch looks its descriptor up in memory;
     // pinning it there costs registers.)
     if constexpr (SINGLE)
-      asm volatile("" ::"s"(c.chdr), "s"(c.svid), "s"(c.smask), "s"(c.st), "s"(c.hood_ptr), "s"(c.y), "s"(c.xr),
-                   "s"(c.xw), "s"(c.ring), "s"(c.H), "s"(c.W), "s"(c.L), "s"(c.ntiles), "s"(c.nchunks), "s"(nw));
+      asm volatile("" ::"s"(c.chdr), "s"(c.svid), "s"(c.smask), "s"(c.st), "s"(c.hood_ptr), "s"(c.vr), "s"(c.xw),
+                   "s"(c.ring), "s"(c.H), "s"(c.W), "s"(c.L), "s"(c.ntiles), "s"(c.nchunks), "s"(nw));
     // (no staging here: a barrier at the start of every block and the
     // staged range's LDS cost more than the gathers they save where blocks
     // run in many rounds; the fused single-graph launch stages)
@@ -1618,13 +1649,13 @@ __device__ __forceinline__ void iter_superchunk_fused(const GraphDev &G, int b, 
   const int ckl = min(ck0, c1 - 1);
   chunk_stream<LMAX>(c, ckl, in, lane);
   StageIn si;
-  if (sg.on) stage_issue(c.y, c.xr, sg, 0, si);
+  if (sg.on) stage_issue(c, sg, 0, si);
   if (wave < kFoldLanes / 64) {
     const int v = wave * 64 + lane;
 #pragma unroll
     for (int j = 0; j < WORDS; ++j) scr[fold_slot(j, v)] = rv[j];  // words >= L's are zero and never read
   }
-  if (sg.on) stage_rest(c.y, c.xr, sg, si, sy, sx);
+  if (sg.on) stage_rest(c, sg, si, sy, sx);
   __syncthreads();
   if (wave == 0) {
     fold_stage2(scr, words, fl.tot, 1, 0, lane);
@@ -1739,8 +1770,7 @@ __global__ void k_final(const GraphDev *graphs, int B) {
   const int b = blockIdx.x - G.vblock0;
   const int iters = st->iters;
   const int stride = G.vnblocks * blockDim.x;
-  if (iters & 1)  // final labels sit in the workspace buffer
-    for (int v = b * blockDim.x + threadIdx.x; v < G.n; v += stride) G.x0[v] = G.x1[v];
+  for (int v = b * blockDim.x + threadIdx.x; v < G.n; v += stride) G.x0[v] = G.vr[v].x[iters & 1];
   if (G.out_S && iters > 0) {
     const double *src = G.ring + (size_t)((iters - 1) % (G.W + 1)) * G.H;
     for (int h = b * blockDim.x + threadIdx.x; h < G.H; h += stride) G.out_S[G.perm[h]] = src[h];
@@ -1842,7 +1872,7 @@ hipStream_t capture_stream(int dev) {
 struct WsPlan {
   int64_t desc_off = 0;
   int64_t block_graph_off = 0, slot_blocks = 0;  // int32 graph of every slot-kernel block
-  std::vector<int64_t> state_off, x1_off, ring_off, thist_off, rec_off;
+  std::vector<int64_t> state_off, vr_off, ring_off, thist_off, rec_off;
   int64_t total = 0;
 };
 
@@ -1923,8 +1953,8 @@ WsPlan plan_workspace(int B, const pmrf_em_item *items) {
     const pmrf_hoods *h = items[i].hoods;
     p.state_off.push_back(off);
     off += align_up(sizeof(GraphState), 256);
-    p.x1_off.push_back(off);
-    off += align_up((int64_t)h->n * 4, 256);
+    p.vr_off.push_back(off);
+    off += align_up((int64_t)h->n * (int64_t)sizeof(VertexRec), 256);
     p.ring_off.push_back(off);
     off += align_up((int64_t)(items[i].params.conv_window + 1) * h->H * 8, 256);
     p.thist_off.push_back(off);
@@ -1975,7 +2005,7 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
     G.hood_ptr = reinterpret_cast<const int32_t *>(hb + h->layout.hptr_off);
     G.y = it.d_y;
     G.x0 = it.d_labels;
-    G.x1 = reinterpret_cast<int32_t *>(ws + plan.x1_off[i]);
+    G.vr = reinterpret_cast<VertexRec *>(ws + plan.vr_off[i]);
     G.ring = reinterpret_cast<double *>(ws + plan.ring_off[i]);
     G.thist = reinterpret_cast<double *>(ws + plan.thist_off[i]);
     G.st = reinterpret_cast<GraphState *>(ws + plan.state_off[i]);
@@ -2068,6 +2098,8 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
     }
     const GraphDev *gd = d_desc;
     hipLaunchKernelGGL(k_setup, dim3((B + 63) / 64), dim3(64), 0, s, gd, B);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_vr_init, dim3(blocks_vert), dim3(256), 0, s, gd, B);
     HIP_TRY(hipGetLastError());
     if (B > 1 && blocks_iter > 0) {
       hipLaunchKernelGGL(k_block_graph, dim3(B), dim3(256), 0, s, gd, block_graph);
