@@ -35,6 +35,8 @@ def _bind(lib):
     P = POINTER
     lib.or_build.restype = c_void_p
     lib.or_build.argtypes = [c_int, P(c_int), P(c_int)]
+    lib.or_build_k.restype = c_void_p
+    lib.or_build_k.argtypes = [c_int, P(c_int), P(c_int), c_int]
     lib.or_free.argtypes = [c_void_p]
     lib.or_info.argtypes = [c_void_p, P(c_int64)]
     lib.or_get_cliques.argtypes = [c_void_p, P(c_int64), P(c_int)]
@@ -47,13 +49,13 @@ def _bind(lib):
     lib.or_mstep.argtypes = [c_int, P(c_double), c_int, P(c_int), P(c_double), P(c_double), c_double,
                              P(c_double), P(c_double)]
     lib.or_em_step.restype = c_int
-    lib.or_em_step.argtypes = [c_void_p, P(c_double), c_int, c_double, P(c_int), P(c_double), P(c_double),
+    lib.or_em_step.argtypes = [c_void_p, P(c_double), c_int, c_double, c_int, P(c_int), P(c_double), P(c_double),
                                c_double, c_double, P(c_int), P(c_double), P(c_double), P(c_double),
                                P(c_double), P(c_int64), P(c_double), P(c_int), P(c_double)]
     lib.or_hood_converged.restype = c_int
     lib.or_hood_converged.argtypes = [c_int, c_double, P(c_double)]
     lib.or_em_run.restype = c_int
-    lib.or_em_run.argtypes = [c_void_p, P(c_double), c_int, c_double, c_int, c_int, c_double, c_int,
+    lib.or_em_run.argtypes = [c_void_p, P(c_double), c_int, c_double, c_int, c_int, c_int, c_double, c_int,
                               c_double, c_double, c_int, P(c_int), P(c_double), P(c_double), P(c_double),
                               P(c_double), P(c_int64), P(c_int64), P(c_int64)]
     return lib
@@ -83,14 +85,20 @@ def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
-class OracleGraph:
-    """Neighbourhood structure built by the oracle from a CSR graph."""
+# Scatter rules of the label update ("Update Output Labels"): which element's
+# write stands for a vertex that several neighbourhoods hold.
+RULE_OWNER, RULE_LAST, RULE_MIN = 0, 1, 2
 
-    def __init__(self, n, row_ptr, col_idx, lib=None):
+
+class OracleGraph:
+    """Neighbourhood structure built by the oracle from a CSR graph (k-neighbourhoods)."""
+
+    def __init__(self, n, row_ptr, col_idx, lib=None, k=1):
         self.lib = lib or load()
         self.row_ptr = _i32(row_ptr)
         self.col_idx = _i32(col_idx) if len(col_idx) else np.zeros(1, np.int32)
-        self.h = self.lib.or_build(int(n), _p(self.row_ptr, c_int), _p(self.col_idx, c_int))
+        self.k = int(k)
+        self.h = self.lib.or_build_k(int(n), _p(self.row_ptr, c_int), _p(self.col_idx, c_int), self.k)
         if not self.h:
             raise ValueError("oracle: invalid CSR graph")
         info = np.zeros(6, np.int64)
@@ -125,7 +133,7 @@ class OracleGraph:
         self.lib.or_get_owner(self.h, _p(own, c_int64))
         return own[: self.n]
 
-    def em_step(self, y, L, beta, x, mu, sigma, sigma_min=1e-3, tie_eps=1e-9, per_element=False):
+    def em_step(self, y, L, beta, x, mu, sigma, sigma_min=1e-3, tie_eps=1e-9, per_element=False, rule=RULE_OWNER):
         y, x, mu, sigma = _f64(y), _i32(x), _f64(mu), _f64(sigma)
         xo = np.zeros(max(1, self.n), np.int32)
         muo, so = np.zeros(L), np.zeros(L)
@@ -138,7 +146,7 @@ class OracleGraph:
         gap = np.zeros(M) if per_element else None
         nul_d = ctypes.cast(None, POINTER(c_double))
         nul_i = ctypes.cast(None, POINTER(c_int))
-        rc = self.lib.or_em_step(self.h, _p(y, c_double), int(L), float(beta), _p(x, c_int), _p(mu, c_double),
+        rc = self.lib.or_em_step(self.h, _p(y, c_double), int(L), float(beta), int(rule), _p(x, c_int), _p(mu, c_double),
                                  _p(sigma, c_double), float(sigma_min), float(tie_eps), _p(xo, c_int),
                                  _p(muo, c_double), _p(so, c_double), _p(S, c_double), _p(T, c_double),
                                  _p(nt, c_int64), _p(m, c_double) if per_element else nul_d,
@@ -153,7 +161,7 @@ class OracleGraph:
         return out
 
     def em_run(self, y, L, beta, x0, mu0, sigma0, iters, window=3, tol=1e-4, early_exit=False,
-               sigma_min=1e-3, tie_eps=1e-9, init_from_labels=False):
+               sigma_min=1e-3, tie_eps=1e-9, init_from_labels=False, rule=RULE_OWNER):
         y = _f64(y)
         x = _i32(x0).copy()
         if x.size == 0:
@@ -164,7 +172,7 @@ class OracleGraph:
         nt = np.zeros(max(1, iters), np.int64)
         nc = np.zeros(max(1, iters), np.int64)
         summ = np.zeros(4, np.int64)
-        rc = self.lib.or_em_run(self.h, _p(y, c_double), int(L), float(beta), int(iters), int(window), float(tol),
+        rc = self.lib.or_em_run(self.h, _p(y, c_double), int(L), float(beta), int(rule), int(iters), int(window), float(tol),
                                 int(bool(early_exit)), float(sigma_min), float(tie_eps), int(bool(init_from_labels)),
                                 _p(x, c_int), _p(mu, c_double), _p(sigma, c_double), _p(trace, c_double),
                                 _p(S, c_double), _p(nt, c_int64), _p(nc, c_int64), _p(summ, c_int64))

@@ -11,15 +11,16 @@
  * written.  Each function names the passage of the paper it follows; where the
  * paper is silent or garbled the reading taken is stated at the function.
  *
- *   or_build        maximal cliques (Sec. 3.2.1), 1-neighbourhoods (Sec. 3.1 and
- *                   the four construction steps of Sec. 3.2.2), in-hood adjacency,
- *                   owner element per vertex
+ *   or_build_k      maximal cliques (Sec. 3.2.1), k-neighbourhoods (Sec. 3.1; for
+ *                   k = 1 the four construction steps of Sec. 3.2.2), in-hood
+ *                   adjacency, owner element per vertex (or_build: k = 1)
  *   or_replicate    replication of the neighbourhood array by label (Sec. 3.2.2,
  *                   "Replicate Neighborhoods By Label" and its worked example)
  *   or_gather       gathered per-replica labels and intensities (same example)
  *   or_mstep        parameter update (Sec. 3.2.2, "Update Parameters")
  *   or_em_step      one EM iteration: energies, per-vertex minimum, neighbourhood
- *                   sums, label update, parameter update (Alg. 2, EM loop)
+ *                   sums, label update under a scatter rule, parameter update
+ *                   (Alg. 2, EM loop)
  *   or_hood_converged  convergence test over the last W sums (Sec. 3.2.2,
  *                   "MAP Convergence Check" / "EM Convergence Check")
  *   or_em_run       the fixed-count EM loop with convergence bookkeeping
@@ -37,7 +38,7 @@ typedef struct {
   int H;
   i64 *clq_ptr;
   int *clq_vid;
-  /* 1-neighbourhoods hood_h = sorted(C_h u N(C_h)); M elements in total */
+  /* k-neighbourhoods: hood_h = sorted(C_h u {u within k edges of C_h}); M elements in total */
   i64 *hood_ptr;
   int *hood_vid;
   i64 M;
@@ -159,9 +160,10 @@ static int cmp_clique(const void *x, const void *y) {
 
 void or_free(or_graph *g);
 
-/* Returns NULL if the CSR is not a simple undirected graph with sorted rows. */
-or_graph *or_build(int n, const int *row_ptr, const int *col_idx) {
-  if (n < 0 || !row_ptr) return NULL;
+/* Returns NULL if the CSR is not a simple undirected graph with sorted rows,
+   or k < 1. */
+or_graph *or_build_k(int n, const int *row_ptr, const int *col_idx, int k) {
+  if (n < 0 || !row_ptr || k < 1) return NULL;
   if (row_ptr[0] != 0) return NULL;
   for (int v = 0; v < n; ++v) {
     if (row_ptr[v + 1] < row_ptr[v]) return NULL;
@@ -219,26 +221,45 @@ or_graph *or_build(int n, const int *row_ptr, const int *col_idx) {
   }
   free(order); free(cl.members.a); free(cl.ptr.a);
 
-  /* B2: hood_h = ascending, duplicate-free C_h u N(C_h) */
+  /* B2: hood_h = the clique's members and every vertex within k edges of one
+     of them (Sec. 3.1), ascending: a breadth-first search of depth k from the
+     members, each vertex taken once (mark[u] = h + 1 once u is in hood h) */
   ivec hv = {0};
+  ivec front = {0};
+  int *mark = (int *)calloc((size_t)(n > 0 ? n : 1), sizeof(int));
   g->hood_ptr = (i64 *)malloc((size_t)(H + 1) * sizeof(i64));
   g->hood_ptr[0] = 0;
   g->max_hood = 0;
   for (i64 h = 0; h < H; ++h) {
     i64 start = hv.n;
-    for (i64 k = g->clq_ptr[h]; k < g->clq_ptr[h + 1]; ++k) {
-      int c = g->clq_vid[k];
+    front.n = 0;
+    for (i64 q = g->clq_ptr[h]; q < g->clq_ptr[h + 1]; ++q) {
+      int c = g->clq_vid[q];
+      mark[c] = (int)h + 1;
       iv_push(&hv, c);
-      for (int q = row_ptr[c]; q < row_ptr[c + 1]; ++q) iv_push(&hv, col_idx[q]);
+      iv_push(&front, c);
+    }
+    i64 fb = 0;
+    for (int depth = 1; depth <= k; ++depth) {
+      i64 fe = front.n;
+      for (i64 f = fb; f < fe; ++f) {
+        int u = front.a[f];
+        for (int q = row_ptr[u]; q < row_ptr[u + 1]; ++q) {
+          int w = col_idx[q];
+          if (mark[w] == (int)h + 1) continue;
+          mark[w] = (int)h + 1;
+          iv_push(&hv, w);
+          iv_push(&front, w);
+        }
+      }
+      fb = fe;
     }
     qsort(hv.a + start, (size_t)(hv.n - start), sizeof(int), cmp_int);
-    i64 w = start;
-    for (i64 k = start; k < hv.n; ++k)
-      if (k == start || hv.a[k] != hv.a[w - 1]) hv.a[w++] = hv.a[k];
-    hv.n = w;
     g->hood_ptr[h + 1] = hv.n;
     if (hv.n - start > g->max_hood) g->max_hood = (int)(hv.n - start);
   }
+  free(mark);
+  free(front.a);
   g->M = hv.n;
   g->hood_vid = hv.a ? hv.a : (int *)malloc(sizeof(int));
 
@@ -271,6 +292,8 @@ or_graph *or_build(int n, const int *row_ptr, const int *col_idx) {
   }
   return g;
 }
+
+or_graph *or_build(int n, const int *row_ptr, const int *col_idx) { return or_build_k(n, row_ptr, col_idx, 1); }
 
 void or_free(or_graph *g) {
   if (!g) return;
@@ -378,20 +401,30 @@ int or_mstep(int n, const double *y, int L, const int *x, const double *mu_in, c
  *  gap(h,j) = second smallest E - m  ("Compute Minimum Vertex and Label Energies")
  *  S_h = sum over j ascending of m(h,j); T = sum over h ascending of S_h
  *                                      ("Compute Neighborhood Energy Sums")
- *  x_out[v] = a(owner(v))              ("Update Output Labels"; the owner rule
- *                                       resolves the scatter's write conflicts)
- *  near_ties = #{v : gap(owner(v)) < tie_eps}
+ *  x_out[v] = a(e_v)                   ("Update Output Labels": every element
+ *                                       scatters its argmin to its vertex; the
+ *                                       rule picks the element e_v whose write
+ *                                       stands, a reading of the paper's
+ *                                       write conflicts)
+ *     rule 0 (owner): e_v = owner(v), v's element in the first clique holding v
+ *     rule 1 (last):  e_v = the last element holding v in the hood-major array
+ *                     (the outcome of a serial Scatter)
+ *     rule 2 (min):   e_v = the element holding v with the smallest m, the
+ *                     first such element on ties
+ *  near_ties = #{v : gap(e_v) < tie_eps, or (rule 2) another element e of v
+ *               has m(e) - m(e_v) < tie_eps and a(e) != a(e_v)}
  *  (mu_out, sigma_out) = or_mstep(x_out) ("Update Parameters")
  *
  * m, a, gap may be NULL; otherwise they receive the per-element values.
  */
-int or_em_step(const or_graph *g, const double *y, int L, double beta, const int *x_in,
+int or_em_step(const or_graph *g, const double *y, int L, double beta, int rule, const int *x_in,
                const double *mu_in, const double *sigma_in, double sigma_min, double tie_eps,
                int *x_out, double *mu_out, double *sigma_out, double *S, double *T, i64 *near_ties,
                double *m_out, int *a_out, double *gap_out) {
-  if (L < 2 || L > 16) return -1;
+  if (L < 2 || L > 16 || rule < 0 || rule > 2) return -1;
   double E[16];
   double *gap_elem = (double *)malloc((size_t)(g->M > 0 ? g->M : 1) * sizeof(double));
+  double *m_elem = (double *)malloc((size_t)(g->M > 0 ? g->M : 1) * sizeof(double));
   int *a_elem = (int *)malloc((size_t)(g->M > 0 ? g->M : 1) * sizeof(int));
   double total = 0.0;
   for (int h = 0; h < g->H; ++h) {
@@ -416,6 +449,7 @@ int or_em_step(const or_graph *g, const double *y, int L, double beta, const int
       for (int l = 0; l < L; ++l)
         if (l != a && E[l] < second) second = E[l];
       a_elem[e] = a;
+      m_elem[e] = m;
       gap_elem[e] = second - m;
       if (m_out) m_out[e] = m;
       if (a_out) a_out[e] = a;
@@ -426,14 +460,34 @@ int or_em_step(const or_graph *g, const double *y, int L, double beta, const int
     total = total + sh;
   }
   *T = total;
-  i64 ties = 0;
+  /* the element whose write stands, per vertex */
+  i64 *pick = (i64 *)malloc((size_t)(g->n > 0 ? g->n : 1) * sizeof(i64));
+  for (int v = 0; v < g->n; ++v) pick[v] = rule == 0 ? g->owner[v] : -1;
+  if (rule == 1)
+    for (i64 e = 0; e < g->M; ++e) pick[g->hood_vid[e]] = e;
+  if (rule == 2)
+    for (i64 e = 0; e < g->M; ++e) {
+      int v = g->hood_vid[e];
+      if (pick[v] < 0 || m_elem[e] < m_elem[pick[v]]) pick[v] = e;
+    }
+  char *tie = (char *)calloc((size_t)(g->n > 0 ? g->n : 1), 1);
   for (int v = 0; v < g->n; ++v) {
-    i64 e = g->owner[v];
-    x_out[v] = a_elem[e];
-    if (gap_elem[e] < tie_eps) ties++;
+    x_out[v] = a_elem[pick[v]];
+    if (gap_elem[pick[v]] < tie_eps) tie[v] = 1;
   }
+  if (rule == 2)
+    for (i64 e = 0; e < g->M; ++e) {
+      int v = g->hood_vid[e];
+      i64 c = pick[v];
+      if (e != c && m_elem[e] - m_elem[c] < tie_eps && a_elem[e] != a_elem[c]) tie[v] = 1;
+    }
+  i64 ties = 0;
+  for (int v = 0; v < g->n; ++v) ties += tie[v];
   *near_ties = ties;
+  free(tie);
+  free(pick);
   free(gap_elem);
+  free(m_elem);
   free(a_elem);
   return or_mstep(g->n, y, L, x_out, mu_in, sigma_in, sigma_min, mu_out, sigma_out);
 }
@@ -453,7 +507,7 @@ int or_hood_converged(int W, double tol, const double *hist) {
 }
 
 /*
- * The EM loop (Alg. 2): a fixed number of iterations T (Sec. 3.2.2, last
+ * The EM loop (Alg. 2) under scatter rule `rule` (or_em_step): a fixed number of iterations T (Sec. 3.2.2, last
  * paragraph), each one or_em_step.  Per iteration it records the energy total
  * T_t (computed with the incoming state), the near-tie count and the number of
  * neighbourhoods not yet converged.  summary = {iterations run, first iteration
@@ -462,11 +516,11 @@ int or_hood_converged(int W, double tol, const double *hist) {
  * loop stops after the iteration at which every neighbourhood converged.  With
  * init_from_labels the starting parameters are or_mstep of the starting labels.
  */
-int or_em_run(const or_graph *g, const double *y, int L, double beta, int iters, int W, double tol,
+int or_em_run(const or_graph *g, const double *y, int L, double beta, int rule, int iters, int W, double tol,
               int early_exit, double sigma_min, double tie_eps, int init_from_labels, int *x,
               double *mu, double *sigma, double *trace, double *S_last, i64 *near_ties,
               i64 *nonconv, i64 *summary) {
-  if (L < 2 || L > 16 || iters < 0 || W < 1) return -1;
+  if (L < 2 || L > 16 || iters < 0 || W < 1 || rule < 0 || rule > 2) return -1;
   int n = g->n, H = g->H;
   if (init_from_labels) {
     double m2[16], s2[16];
@@ -484,7 +538,7 @@ int or_em_run(const or_graph *g, const double *y, int L, double beta, int iters,
   for (int t = 0; t < iters; ++t) {
     double Tt;
     i64 ties;
-    or_em_step(g, y, L, beta, x, mu, sigma, sigma_min, tie_eps, xn, mu2, s2, S, &Tt, &ties,
+    or_em_step(g, y, L, beta, rule, x, mu, sigma, sigma_min, tie_eps, xn, mu2, s2, S, &Tt, &ties,
                NULL, NULL, NULL);
     trace[t] = Tt;
     Thist[t] = Tt;

@@ -9,6 +9,10 @@ What pins what:
   brute force over all vertex subsets     maximal cliques, canonical order
   closed forms on K_n, paths, stars,      neighbourhoods = clique + 1-ring
   cycles, empty graphs
+  reachability by adjacency-matrix        k-neighbourhoods (k = 2, 3) and their
+  powers, paths and stars at k = 2        in-neighbourhood adjacency
+  serial Scatter simulation, argmin over  the scatter rules of the label update
+  occurrences, a hand-worked path, beta=0 (owner, last neighbourhood, minimum)
   adjacency-matrix recomputation          in-hood adjacency, owner rule
   scipy.stats.norm.logpdf                 the Gaussian data term
   per-vertex synchronous ICM on the CSR   label update through neighbourhoods
@@ -391,6 +395,121 @@ def check_convergence(lib):
     assert early["iters"] == want + 1 and np.array_equal(early["x"], run["x"])
 
 
+def check_k_hoods(lib):
+    """k-neighbourhoods (Sec. 3.1): clique plus every vertex within k edges of a
+    member, by reachability through powers of (I + A); closed forms on paths
+    and stars; the owner rule still sees every neighbour, so at k = 2 the labels
+    equal synchronous ICM on the graph."""
+    graphs = list(random_small_graphs(40))
+    for k in (2, 3):
+        for n, rp, ci in graphs:
+            og = oracle.OracleGraph(n, rp, ci, lib=lib, k=k)
+            og1 = oracle.OracleGraph(n, rp, ci, lib=lib)
+            cl, hl = oracle_lists(og)
+            assert cl == oracle_lists(og1)[0]  # the cliques do not depend on k
+            A = adj_matrix(n, rp, ci)
+            R = np.eye(n, dtype=np.int64)
+            step = (np.eye(n, dtype=np.int64) + A.astype(np.int64))
+            for _ in range(k):
+                R = np.minimum(R @ step, 1)
+            hp, hv = og.hoods()
+            ap, aloc = og.adjacency()
+            for h, (c, hood) in enumerate(zip(cl, hl)):
+                want = sorted(set(np.nonzero(R[list(c)].any(axis=0))[0].tolist()))
+                assert list(hood) == want, (k, h, hood, want)
+                for j, v in enumerate(hood):
+                    e = hp[h] + j
+                    assert aloc[ap[e]:ap[e + 1]].tolist() == [jj for jj, u in enumerate(hood) if A[v, u]], (k, h, j)
+    for n in range(3, 9):  # path, k = 2: hood(edge i, i+1) = {i-2 .. i+3}
+        rp, ci = csr(n, [(i, i + 1) for i in range(n - 1)])
+        og = oracle.OracleGraph(n, rp, ci, lib=lib, k=2)
+        _, hl = oracle_lists(og)
+        assert hl == [tuple(range(max(0, i - 2), min(n - 1, i + 3) + 1)) for i in range(n - 1)], (n, hl)
+    rp, ci = csr(7, [(0, i) for i in range(1, 7)] + [(1, 2)])  # star with one chord, k = 2: every hood = V
+    og = oracle.OracleGraph(7, rp, ci, lib=lib, k=2)
+    assert all(h == tuple(range(7)) for h in oracle_lists(og)[1])
+    g = synth.workload_small()
+    og = oracle.OracleGraph(g.n, g.row_ptr, g.col_idx, lib=lib, k=2)
+    rng = np.random.default_rng(13)
+    for L, beta in ((2, 0.5), (3, 0.8)):
+        mu, sigma = _random_theta(rng, L)
+        x = rng.integers(0, L, g.n).astype(np.int32)
+        out = og.em_step(g.y, L, beta, x, mu, sigma)
+        want, gap = icm_step(g.n, g.row_ptr, g.col_idx, g.y, L, beta, x, mu, sigma)
+        clear = gap > 1e-9
+        assert np.array_equal(out["x"][clear], want[clear])
+
+
+def check_scatter_rules(lib):
+    """Scatter rules of "Update Output Labels": the last write of a serial
+    Scatter over the hood-major array, the minimum over a vertex's
+    occurrences (first on ties), and a hand-worked path where the three rules
+    part; at beta = 0 all occurrences of a vertex agree, so the rules do."""
+    R = oracle
+    # hand-worked: path 0-1-2-3, cliques {0,1} {1,2} {2,3}, hoods {0,1,2} {0,1,2,3} {1,2,3}.
+    # Vertex 1: the first two hoods hold both its neighbours (energies d_l + beta each,
+    # one disagreeing neighbour per label: x_0 = 1, x_2 = 0); the third holds only
+    # vertex 2 (energies d_0 and d_1 + beta).  With d_0 - d_1 = 0.1 < beta = 0.5:
+    # owner -> label 1; last hood -> 0; minimum (d_0 < d_1 + beta) -> 0.
+    rp, ci = csr(4, [(0, 1), (1, 2), (2, 3)])
+    og = oracle.OracleGraph(4, rp, ci, lib=lib)
+    y = np.array([0.0, 5.01, 10.0, 10.0])
+    x = np.array([1, 0, 0, 1], np.int32)
+    got = {rule: int(og.em_step(y, 2, 0.5, x, [0.0, 10.0], [1.0, 1.0], rule=rule)["x"][1])
+           for rule in (R.RULE_OWNER, R.RULE_LAST, R.RULE_MIN)}
+    assert got == {R.RULE_OWNER: 1, R.RULE_LAST: 0, R.RULE_MIN: 0}, got
+    # exact tie across occurrences: y_1 = 5.25 gives d_0 = 13.78125, d_1 = 11.28125
+    # (exact in binary), beta = 2.5: every occurrence of vertex 1 has minimum
+    # 13.78125, the first two at label 1, the third (a tie inside it, lowest
+    # label) at label 0; the minimum rule takes the first occurrence
+    y = np.array([0.0, 5.25, 10.0, 10.0])
+    out = {rule: og.em_step(y, 2, 2.5, x, [0.0, 10.0], [1.0, 1.0], per_element=True, rule=rule)
+           for rule in (R.RULE_OWNER, R.RULE_LAST, R.RULE_MIN)}
+    hp, hv = og.hoods()
+    occ = np.nonzero(hv == 1)[0]
+    assert np.all(out[R.RULE_MIN]["m"][occ] == 13.78125) and list(out[R.RULE_MIN]["a"][occ]) == [1, 1, 0]
+    assert [int(out[r]["x"][1]) for r in (R.RULE_OWNER, R.RULE_LAST, R.RULE_MIN)] == [1, 0, 1]
+    rng = np.random.default_rng(29)
+    cases = [(n, rp, ci) for n, rp, ci in random_small_graphs(30)]
+    g = synth.workload_small()
+    cases.append((g.n, g.row_ptr, g.col_idx))
+    for n, rp, ci in cases:
+        og = oracle.OracleGraph(n, rp, ci, lib=lib)
+        hp, hv = og.hoods()
+        yv = rng.uniform(0, 255, n)
+        for L, beta in ((2, 0.0), (2, 0.7), (3, 1.5)):
+            mu, sigma = _random_theta(rng, L)
+            x = rng.integers(0, L, n).astype(np.int32)
+            outs = {rule: og.em_step(yv, L, beta, x, mu, sigma, per_element=True, rule=rule)
+                    for rule in (R.RULE_OWNER, R.RULE_LAST, R.RULE_MIN)}
+            m, a = outs[R.RULE_OWNER]["m"], outs[R.RULE_OWNER]["a"]
+            for o in outs.values():  # the rule changes only the label update
+                assert np.array_equal(o["m"], m) and np.array_equal(o["S"], outs[R.RULE_OWNER]["S"])
+            sim = x.copy()  # a serial Scatter over the hood-major array
+            for e in range(len(hv)):
+                sim[hv[e]] = a[e]
+            assert np.array_equal(outs[R.RULE_LAST]["x"], sim)
+            owner = og.owner()
+            for v in range(n):
+                occ = np.nonzero(hv == v)[0]
+                best = occ[np.argmin(m[occ])]
+                assert outs[R.RULE_MIN]["x"][v] == a[best], (v, occ)
+                assert m[best] <= m[owner[v]] and m[best] <= m[occ[-1]]
+            if beta == 0.0:
+                for rule in (R.RULE_LAST, R.RULE_MIN):
+                    assert np.array_equal(outs[rule]["x"], outs[R.RULE_OWNER]["x"])
+                    assert outs[rule]["near_ties"] == outs[R.RULE_OWNER]["near_ties"]
+    # minimum rule, near tie between occurrences: vertex 1 at gap 0.1 in every
+    # hood, but its minimum differs by 1e-12 between the two kinds of hoods with
+    # different labels (d_0 - d_1 = beta - 1e-12)
+    d = 0.5 - 1e-12
+    y1 = (d + 50.0) / 10.0  # (y^2 - (y - 10)^2) / 2 = 10 y - 50 = d
+    out = oracle.OracleGraph(4, *csr(4, [(0, 1), (1, 2), (2, 3)]), lib=lib).em_step(
+        np.array([0.0, y1, 10.0, 10.0]), 2, 0.5, np.array([1, 0, 0, 1], np.int32), [0.0, 10.0], [1.0, 1.0],
+        rule=R.RULE_MIN)
+    assert out["near_ties"] >= 1
+
+
 ALL_CHECKS = [
     check_worked_example,
     check_cliques_bruteforce,
@@ -404,4 +523,6 @@ ALL_CHECKS = [
     check_cem,
     check_udata_monotone,
     check_convergence,
+    check_k_hoods,
+    check_scatter_rules,
 ]

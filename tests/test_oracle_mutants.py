@@ -22,8 +22,13 @@ MUTANTS = {
     "hood_sum_wrong_term": ("sh = sh + m;", "sh = sh + E[0];"),
     "total_not_summed": ("total = total + sh;", "total = sh;"),
     "owner_last_clique": ("if (g->owner[v] >= 0) continue;", ""),
-    "hood_one_member_ring": ("for (int q = row_ptr[c]; q < row_ptr[c + 1]; ++q) iv_push(&hv, col_idx[q]);",
-                             "if (k == g->clq_ptr[h]) for (int q = row_ptr[c]; q < row_ptr[c + 1]; ++q) iv_push(&hv, col_idx[q]);"),
+    "hood_one_member_ring": ("for (i64 f = fb; f < fe; ++f) {", "for (i64 f = fb; f < fb + 1 && f < fe; ++f) {"),
+    "hood_ring_too_deep": ("for (int depth = 1; depth <= k; ++depth) {", "for (int depth = 0; depth <= k; ++depth) {"),
+    "last_rule_first_write": ("for (i64 e = 0; e < g->M; ++e) pick[g->hood_vid[e]] = e;",
+                              "for (i64 e = g->M - 1; e >= 0; --e) pick[g->hood_vid[e]] = e;"),
+    "min_rule_last_on_ties": ("if (pick[v] < 0 || m_elem[e] < m_elem[pick[v]]) pick[v] = e;",
+                              "if (pick[v] < 0 || m_elem[e] <= m_elem[pick[v]]) pick[v] = e;"),
+    "min_rule_ties_ignore_labels": ("&& a_elem[e] != a_elem[c]) tie[v] = 1;", ") tie[v] = 1;"),
     "adjacency_whole_hood": ("if (is_neighbor(g, v, g->hood_vid[o + jj])) iv_push(&al, (int)jj);",
                              "if (jj != j) iv_push(&al, (int)jj);"),
     "sample_std": ("double sigma = sqrt(ss / (double)cnt);", "double sigma = sqrt(ss / (double)(cnt > 1 ? cnt - 1 : 1));"),
