@@ -146,11 +146,28 @@ typedef struct {
   int32_t init_from_labels; /* 1: first replace (mu, sigma) by the parameter update of the starting labels */
   double sigma_min;         /* floor of sigma, > 0 (default 1e-3) */
   double tie_eps;           /* a label decision with energy gap below this is counted as a near tie (1e-9) */
+  int32_t scatter_rule;     /* PMRF_SCATTER_*: which neighbourhood's label decision stands for a vertex */
 } pmrf_em_params;
+
+/* Scatter rules of the label update ("Update Output Labels": every element
+ * (h, v) scatters its arg-minimum to vertex v; the paper leaves the write
+ * conflicts between the ~20 neighbourhoods holding a vertex open).
+ *  OWNER: the element in the first clique (canonical order) holding v; it sees
+ *         every graph neighbour of v, so the update is synchronous ICM on the
+ *         graph (default).
+ *  LAST:  the element in the last neighbourhood (canonical order) holding v,
+ *         the outcome of a serial Scatter over the neighbourhood-major array.
+ *  MIN:   the element of v with the smallest minimum energy, the first in
+ *         canonical order on ties; a near tie also counts another element of
+ *         v within tie_eps of that minimum at a different label.  Runs a
+ *         per-vertex pass after each iteration's energies. */
+#define PMRF_SCATTER_OWNER 0
+#define PMRF_SCATTER_LAST 1
+#define PMRF_SCATTER_MIN 2
 
 /* Fill p with the defaults: L = 2, beta = 0.5, max_iters = 20, conv_window = 3,
  * conv_tol = 1e-4, early_exit = 0, init_from_labels = 0, sigma_min = 1e-3,
- * tie_eps = 1e-9. */
+ * tie_eps = 1e-9, scatter_rule = PMRF_SCATTER_OWNER. */
 void pmrf_em_params_default(pmrf_em_params *p);
 
 /* counters[] layout (int64, device) */

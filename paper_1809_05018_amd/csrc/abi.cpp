@@ -17,7 +17,7 @@ void clear_error() { g_last_error.clear(); }
 
 extern "C" const char *pmrf_last_error(void) { return g_last_error.c_str(); }
 
-extern "C" int32_t pmrf_abi_version(void) { return 1; }
+extern "C" int32_t pmrf_abi_version(void) { return 2; }
 
 extern "C" void pmrf_em_params_default(pmrf_em_params *p) {
   if (!p) return;
@@ -30,4 +30,5 @@ extern "C" void pmrf_em_params_default(pmrf_em_params *p) {
   p->init_from_labels = 0;
   p->sigma_min = 1e-3;
   p->tie_eps = 1e-9;
+  p->scatter_rule = PMRF_SCATTER_OWNER;
 }

@@ -154,6 +154,12 @@ struct GraphDev {
   int32_t vblock0, vnblocks;  // blocks of this graph in a vertex-parallel launch
   const int32_t *perm;        // processing index -> canonical neighbourhood
   const int32_t *srange;      // member vertex range of superchunk s: [srange[2 s], srange[2 s + 1])
+  int32_t rule;               // scatter rule (PMRF_SCATTER_*)
+  int32_t nrec;               // statistics records per iteration: superchunks, then (rule MIN) vertex blocks
+  const uint64_t *lastbits;   // rule LAST: element holds its vertex's last occurrence
+  const int32_t *occ_ptr, *occ;  // rule MIN: each vertex's elements in canonical order
+  double *em, *eg;            // rule MIN: per element (processing order) minimum energy and gap
+  int32_t *ea;                //           and arg-minimum label
 };
 
 constexpr int kDescPerPack = 12;
@@ -448,8 +454,26 @@ struct Ctx {
   gptr<double> ring;
   gptr<const GraphState> st;
   int H, W, L, P, t, ntiles, nchunks;
+  int rule;
+  gptr<const uint64_t> lastbits;
+  gptr<double> em, eg;
+  gptr<int32_t> ea;
   double beta, tol, tie_eps;
 };
+
+constexpr int kRuleOwner = PMRF_SCATTER_OWNER, kRuleLast = PMRF_SCATTER_LAST, kRuleMin = PMRF_SCATTER_MIN;
+
+// Whether element e (processing order) decides its vertex's label, for the
+// rules other than the owner's (whose flag is the element's own adjacency bit).
+__device__ __forceinline__ bool decides(const Ctx &c, int e) {
+  return c.rule == kRuleLast && ((c.lastbits[e >> 6] >> (e & 63)) & 1);
+}
+// Rule MIN: the element's minimum energy, arg-minimum and gap, for the vertex pass.
+__device__ __forceinline__ void record_elem(const Ctx &c, int e, double m, int a, double gap) {
+  c.em[e] = m;
+  c.ea[e] = a;
+  c.eg[e] = gap;
+}
 
 // Label (read buffer) and intensity of vertex v: one 16-byte load.
 __device__ __forceinline__ void vrec_load(const Ctx &c, unsigned v, int &x, double &y) {
@@ -564,7 +588,7 @@ __device__ __forceinline__ void elem_pass(const Ctx &c, const TileDesc &td, cons
   const uint64_t below = (2ull << lane) - 1ull;  // lanes 0..lane
   const int base = 63 - __clzll(td.start_mask & below);
   const uint64_t self = 1ull << (lane - base);
-  const bool owner = valid && (am & self);
+  const bool owner = valid && (c.rule == kRuleOwner ? (am & self) != 0 : decides(c, e));
   const uint64_t nbr = am & ~self;
   const int deg = __popcll(nbr);
   int cnt[LMAX];
@@ -587,6 +611,7 @@ __device__ __forceinline__ void elem_pass(const Ctx &c, const TileDesc &td, cons
     ls.add_owner(a, dsel);
     if (gap < c.tie_eps) ls.ties += 1;
   }
+  if (c.rule == kRuleMin && valid) record_elem(c, e, m, a, gap);
   if (valid) mb[e - gstart] = m;
 }
 
@@ -679,7 +704,7 @@ __device__ void do_large(const Ctx &c, const TileDesc &td, const Theta<LMAX> &th
         uint32_t word = mw[wi];
         if (wi == (jj >> 5)) {
           const uint32_t selfb = 1u << (jj & 31);
-          owner = (word & selfb) != 0;
+          owner = c.rule == kRuleOwner ? (word & selfb) != 0 : decides(c, td.elem_start + jj);
           word &= ~selfb;
         }
         deg += __popc(word);
@@ -704,6 +729,7 @@ __device__ void do_large(const Ctx &c, const TileDesc &td, const Theta<LMAX> &th
       ls.add_owner(a, dsel);
       if (gap < c.tie_eps) ls.ties += 1;
     }
+    if (c.rule == kRuleMin && valid) record_elem(c, td.elem_start + jj, m, a, gap);
     mb[lane] = valid ? m : 0.0;
     wave_lds_sync();
     if (lane == 0) {
@@ -843,7 +869,7 @@ constexpr bool kPrefetchHi = LMAX >= 4;
 // element relative to the chunk; am: the element's first adjacency word; the
 // second word of a MID packet is prefetched (ah) or read here.
 template <int LMAX>
-__device__ __forceinline__ void slot_elem(const Ctx &c, int eoff, bool mid, int ti, uint32_t sv, uint32_t am,
+__device__ __forceinline__ void slot_elem(const Ctx &c, int e0, int eoff, bool mid, int ti, uint32_t sv, uint32_t am,
                                           uint32_t ah, int xv, double yv, const Theta<LMAX> &th,
                                           ChunkStats<LMAX> &cs, double *mb, double *od, int *oa, int &ocount,
                                           int lane) {
@@ -907,7 +933,8 @@ __device__ __forceinline__ void slot_elem(const Ctx &c, int eoff, bool mid, int 
       }
     }
   }
-  const bool owner = own != 0;  // empty slots have no adjacency bits
+  // empty slots have no adjacency bits; e0 + lane is the element's index
+  const bool owner = c.rule == kRuleOwner ? own != 0 : valid && decides(c, e0 + lane);
   double m, gap, dsel;
   int a;
   if constexpr (LMAX == 2) {
@@ -924,6 +951,7 @@ __device__ __forceinline__ void slot_elem(const Ctx &c, int eoff, bool mid, int 
   } else {
     element_energy<LMAX>(th, c.L, c.beta, yv, deg, cnt, m, a, gap, dsel);
   }
+  if (c.rule == kRuleMin && valid) record_elem(c, e0 + lane, m, a, gap);
   const uint64_t ob = __ballot(owner);
   if (ob) {
     const int idx = ocount + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(ob >> 32),
@@ -1189,8 +1217,8 @@ __device__ __forceinline__ void chunk_run(const Ctx &c, int ck, const ChunkIn &i
         wave_lds_sync();
       }
       const int eoff = (int)((hdr_field(in.hw, kDwOff + i / 2) >> (16 * (i & 1))) & 0xffffu);
-      slot_elem<LMAX>(c, eoff, (flags >> (kHdrMidShift + i)) & 1, tb + i, (uint32_t)in.v[i], in.am[i], in.ah[i],
-                      in.xv[i], in.yv[i], th, cs, mb, od, oa, ocount, lane);
+      slot_elem<LMAX>(c, gstart + eoff, eoff, (flags >> (kHdrMidShift + i)) & 1, tb + i, (uint32_t)in.v[i], in.am[i],
+                      in.ah[i], in.xv[i], in.yv[i], th, cs, mb, od, oa, ocount, lane);
     }
   wave_lds_sync();
   cs.take_owners(od, oa, ocount, lane);
@@ -1346,6 +1374,70 @@ __global__ __launch_bounds__(256) void k_mstep_init(const GraphDev *graphs, int 
   }
 }
 
+// Scatter rule MIN, after iteration t's element kernels: vertex v takes the
+// label of its element with the smallest minimum energy, the first in
+// canonical neighbourhood order on ties (elements listed in that order); a
+// near tie is a gap below tie_eps at that element or another element of v
+// within tie_eps of the minimum at a different label.  The new label goes to
+// label buffer (t + 1) & 1, and the vertex's share of the parameter update
+// (y - mu_a of iteration t) and its near tie to the record of its vertex
+// block (records nsuper + block; thread i takes vertices i, i + 256, ... in
+// order, the four waves add in order).
+template <int LMAX>
+__global__ __launch_bounds__(256) void k_decide(const GraphDev *graphs, int B, int t) {
+  __shared__ double part[4][kRecMax];
+  const GraphDev &G = graphs[find_graph(graphs, B, blockIdx.x, kGridVertex)];
+  if (G.rule != kRuleMin) return;
+  gptr<const GraphState> st = gbl((const GraphState *)G.st);
+  if (t >= G.max_iters || st->done) return;
+  const int L = G.L, words = rec_words(L);
+  const int b = blockIdx.x - G.vblock0;
+  const int v0 = b * kVertPerBlock, v1 = min(G.n, v0 + kVertPerBlock);
+  gptr<const int32_t> optr = gbl(G.occ_ptr), occ = gbl(G.occ), ea = gbl((const int32_t *)G.ea);
+  gptr<const double> em = gbl((const double *)G.em), eg = gbl((const double *)G.eg);
+  gptr<VertexRec> vr = gbl(G.vr);
+  double mu[LMAX];
+#pragma unroll
+  for (int l = 0; l < LMAX; ++l) mu[l] = l < L ? st->th[t & 1][l].mu : 0.0;
+  LaneStats<LMAX> ls;
+  ls.clear();
+  for (int v = v0 + threadIdx.x; v < v1; v += blockDim.x) {
+    const int o0 = optr[v], o1 = optr[v + 1];
+    int best = occ[o0];
+    double mbest = em[best];
+    for (int o = o0 + 1; o < o1; ++o) {
+      const int e = occ[o];
+      const double m = em[e];
+      if (m < mbest) {
+        mbest = m;
+        best = e;
+      }
+    }
+    const int a = ea[best];
+    bool tie = eg[best] < G.tie_eps;
+    for (int o = o0; o < o1; ++o) {
+      const int e = occ[o];
+      if (e != best && em[e] - mbest < G.tie_eps && ea[e] != a) tie = true;
+    }
+    vr[v].x[(t + 1) & 1] = a;
+    double cm = 0.0;
+#pragma unroll
+    for (int l = 0; l < LMAX; ++l)
+      if (l == a) cm = mu[l];
+    ls.add_owner(a, vr[v].y - cm);
+    if (tie) ls.ties += 1;
+  }
+  const int wave = wave_id(), lane = threadIdx.x & 63;
+  ls.store(&part[wave][0], 1, L, lane);
+  __syncthreads();
+  if (threadIdx.x < words) {
+    const int w = threadIdx.x;
+    double acc = 0.0;
+    for (int k = 0; k < 4; ++k) acc = acc + part[k][w];
+    gbl(G.rec)[(size_t)(t & 1) * G.rec_stride + (size_t)w * G.nrec + G.nsuper + b] = acc;
+  }
+}
+
 // LDS of the parameter update.
 struct FoldLds {
   double tot[kRecMax];
@@ -1461,7 +1553,7 @@ __device__ __forceinline__ void fold_iteration(const GraphDev &G, int t, FoldLds
   // a graph whose run has ended (tp >= max_iters, in a batch of mixed run
   // lengths) folds but stores nothing; testing it after the fold lets every
   // load above be requested at once
-  fold_all(gbl((const double *)G.rec) + (size_t)(tp & 1) * G.rec_stride, G.nsuper, rec_words(G.L), sh.scr, sh.tot,
+  fold_all(gbl((const double *)G.rec) + (size_t)(tp & 1) * G.rec_stride, G.nrec, rec_words(G.L), sh.scr, sh.tot,
            nw, wave, lane);
   if (tp >= G.max_iters || wave != 0) return;
   (void)finish_iteration(G, t, sh.tot, p, true, lane);
@@ -1479,6 +1571,9 @@ __global__ __launch_bounds__(kFoldThreads) void k_fold(const GraphDev *graphs, c
 }
 
 // Registers of one iteration launch for a graph.
+// ANY: the graph's scatter rule is read from its descriptor; otherwise the
+// launch is compiled for the owner rule (every rule test folds away).
+template <bool ANY = false>
 __device__ __forceinline__ Ctx make_ctx(const GraphDev &G, int t) {
   Ctx c;
   c.tiles = gbl(G.tiles);
@@ -1504,6 +1599,11 @@ __device__ __forceinline__ Ctx make_ctx(const GraphDev &G, int t) {
   c.beta = G.beta;
   c.tol = G.tol;
   c.tie_eps = G.tie_eps;
+  c.rule = ANY ? G.rule : kRuleOwner;
+  c.lastbits = gbl(G.lastbits);
+  c.em = gbl(G.em);
+  c.eg = gbl(G.eg);
+  c.ea = gbl(G.ea);
   return c;
 }
 
@@ -1521,7 +1621,7 @@ __device__ __forceinline__ void store_records(const GraphDev &G, int c0, int c1,
     const int k1 = min((r + 1) * sc, c1 - c0);
     double out = 0.0;
     for (int k = r * sc; k < k1; ++k) out = out + part[k][w];
-    rec[(size_t)w * G.nsuper + s0 + r] = out;
+    rec[(size_t)w * G.nrec + s0 + r] = out;
   }
 }
 
@@ -1533,7 +1633,7 @@ __device__ __forceinline__ void store_records(const GraphDev &G, int c0, int c1,
 // superchunk holds a LARGE packet (or the window is longer than kPreWindow)
 // and goes packet by packet over the element arrays; otherwise every chunk
 // takes the slot layout.
-template <int LMAX, bool PACKET, bool SINGLE = false>
+template <int LMAX, bool PACKET, bool SINGLE = false, bool ANY = false>
 __device__ __forceinline__ void iter_superchunk(const GraphDev &G, int c0, int c1, int t,
                                                 double (*part)[rec_words(LMAX)], double *mb, uint64_t *pl, double *od,
                                                 int *oa, int nw, int wave, int lane) {
@@ -1541,7 +1641,7 @@ __device__ __forceinline__ void iter_superchunk(const GraphDev &G, int c0, int c
   // writes nothing; the test joins the run state's done flag instead of
   // returning first, so the chunk's loads need not wait for it (they only read).
   const bool ended = t >= G.max_iters;
-  const Ctx c = make_ctx(G, t);
+  const Ctx c = make_ctx<ANY>(G, t);
   Theta<LMAX> th;
   const int done_flag = load_theta<LMAX>(c, th);  // scalar loads, waited for with the chunk's
   if constexpr (!PACKET) {
@@ -1622,7 +1722,7 @@ __device__ __forceinline__ void iter_superchunk_fused(const GraphDev &G, int b, 
   // one superchunk per block (bc == sc, every superchunk on the slot kernel)
   constexpr int WORDS = rec_words(LMAX);
   static_assert(WORDS <= kFoldGroup, "the fused fold takes one pass of words");
-  const int tp = t - 1, R = G.nsuper, words = rec_words(G.L);
+  const int tp = t - 1, R = G.nrec, words = rec_words(G.L);
   gptr<GraphState> st = gbl(G.st);
   const bool writer = b == 0;
   // this wave's virtual fold thread: at most one record
@@ -1699,7 +1799,7 @@ __device__ __forceinline__ void iter_superchunk_fused(const GraphDev &G, int b, 
 // without a dependent load); otherwise each block looks its graph up in
 // graphs[0 .. B).  FUSED (single graph, t >= 1, not persistent): the launch
 // also does the parameter update of iteration t - 1 (iter_superchunk_fused).
-template <int LMAX, bool PERSIST, bool SINGLE, bool FUSED = false>
+template <int LMAX, bool PERSIST, bool SINGLE, bool FUSED = false, bool ANY = false>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(LMAX <= 2 ? (SINGLE ? PMRF_ITER_WAVES_PER_EU : PMRF_BATCH_WAVES_PER_EU) : 1, 8))) void k_iter(
     const GraphDev *__restrict__ graphs, const int32_t *__restrict__ block_graph, const GraphDev g1, int B,
     int nsuper_total, int t) {
@@ -1723,12 +1823,13 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(LMAX <= 2 
   } else if constexpr (!PERSIST) {
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     if constexpr (SINGLE) {
-      iter_superchunk<LMAX, false, true>(g1, slot_c0(g1, blk), slot_c1(g1, blk), t, part, mb, pl, od, oa, nw,
+      iter_superchunk<LMAX, false, true, ANY>(g1, slot_c0(g1, blk), slot_c1(g1, blk), t, part, mb, pl, od, oa, nw,
                                          wave, lane);
     } else {
       const GraphDev &G = graphs[block_graph[blk]];
       const int b = blk - G.block0;
-      iter_superchunk<LMAX, false>(G, slot_c0(G, b), slot_c1(G, b), t, part, mb, pl, od, oa, nw, wave, lane);
+      iter_superchunk<LMAX, false, false, ANY>(G, slot_c0(G, b), slot_c1(G, b), t, part, mb, pl, od, oa, nw, wave,
+                                               lane);
     }
   } else {
     for (int sc = blockIdx.x; sc < nsuper_total; sc += gridDim.x) {
@@ -1747,7 +1848,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(LMAX <= 2 
 
 // The superchunks that hold a LARGE packet: block i of a graph works on its
 // superchunk nslot + i, packet by packet.
-template <int LMAX>
+template <int LMAX, bool ANY = false>
 __global__ __launch_bounds__(1024) void k_iter_packets(const GraphDev *__restrict__ graphs, int B, int t) {
   extern __shared__ double smem[];
   __shared__ double part[kMaxSuperChunks][rec_words(LMAX)];
@@ -1758,7 +1859,8 @@ __global__ __launch_bounds__(1024) void k_iter_packets(const GraphDev *__restric
   int *oa = reinterpret_cast<int *>(od + kOwnCap);
   const GraphDev &G = graphs[find_graph(graphs, B, blockIdx.x, kGridPacket)];
   const int i = blockIdx.x - G.pblock0;
-  iter_superchunk<LMAX, true>(G, packet_c0(G, i), packet_c1(G, i), t, part, mb, pl, od, oa, nw, wave, lane);
+  iter_superchunk<LMAX, true, false, ANY>(G, packet_c0(G, i), packet_c1(G, i), t, part, mb, pl, od, oa, nw, wave,
+                                          lane);
 }
 
 
@@ -1872,7 +1974,7 @@ hipStream_t capture_stream(int dev) {
 struct WsPlan {
   int64_t desc_off = 0;
   int64_t block_graph_off = 0, slot_blocks = 0;  // int32 graph of every slot-kernel block
-  std::vector<int64_t> state_off, vr_off, ring_off, thist_off, rec_off;
+  std::vector<int64_t> state_off, vr_off, ring_off, thist_off, rec_off, elem_off;
   int64_t total = 0;
 };
 
@@ -1888,6 +1990,8 @@ pmrf_status check_params(const pmrf_em_params *p) {
   if (!(p->tie_eps >= 0.0)) return fail(PMRF_EINVAL, "tie_eps must be >= 0");
   if (p->early_exit != 0 && p->early_exit != 1) return fail(PMRF_EINVAL, "early_exit must be 0 or 1");
   if (p->init_from_labels != 0 && p->init_from_labels != 1) return fail(PMRF_EINVAL, "init_from_labels must be 0 or 1");
+  if (p->scatter_rule < PMRF_SCATTER_OWNER || p->scatter_rule > PMRF_SCATTER_MIN)
+    return fail(PMRF_EINVAL, "scatter_rule must be 0 (owner), 1 (last) or 2 (min)");
   return PMRF_OK;
 }
 
@@ -1908,7 +2012,14 @@ int64_t n_super(const pmrf_hoods *h) {
   const int64_t sc = superchunk_chunks(h);
   return std::max<int64_t>(1, (n_chunks(h) + sc - 1) / sc);
 }
-int64_t max_records(const pmrf_hoods *h) { return std::max<int64_t>(n_super(h), vert_blocks(h)); }
+// Statistics records per iteration: one per superchunk, and under rule MIN
+// one more per vertex block (the vertex pass adds the parameter update's sums).
+int64_t n_records(const pmrf_hoods *h, const pmrf_em_params &p) {
+  return n_super(h) + (p.scatter_rule == PMRF_SCATTER_MIN ? vert_blocks(h) : 0);
+}
+int64_t max_records(const pmrf_hoods *h, const pmrf_em_params &p) {
+  return std::max<int64_t>(n_records(h, p), vert_blocks(h));
+}
 
 // Superchunks of a graph that take the slot kernel: those before the first
 // LARGE packet (all of them when there is none), none when the window is
@@ -1960,7 +2071,9 @@ WsPlan plan_workspace(int B, const pmrf_em_item *items) {
     p.thist_off.push_back(off);
     off += align_up((int64_t)std::max(1, items[i].params.max_iters) * 8, 256);
     p.rec_off.push_back(off);
-    off += align_up(2 * max_records(h) * rec_words(items[i].params.L) * 8, 256);  // two record buffers
+    off += align_up(2 * max_records(h, items[i].params) * rec_words(items[i].params.L) * 8, 256);  // two record buffers
+    p.elem_off.push_back(off);  // rule MIN: per element minimum, gap (doubles) and label (int32)
+    if (items[i].params.scatter_rule == PMRF_SCATTER_MIN) off += align_up(std::max<int64_t>(1, h->M) * 20, 256);
   }
   p.total = std::max<int64_t>(off, 256);
   return p;
@@ -2019,7 +2132,21 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
     G.out_stats = it.d_iter_stats;
     G.out_ctr = it.d_counters;
     G.M = h->M;
-    G.rec_stride = max_records(h) * rec_words(it.params.L);
+    G.rec_stride = max_records(h, it.params) * rec_words(it.params.L);
+    G.nrec = (int32_t)n_records(h, it.params);
+    G.rule = it.params.scatter_rule;
+    G.lastbits = reinterpret_cast<const uint64_t *>(hb + h->layout.lastbits_off);
+    G.occ_ptr = reinterpret_cast<const int32_t *>(hb + h->layout.occptr_off);
+    G.occ = reinterpret_cast<const int32_t *>(hb + h->layout.occ_off);
+    if (G.rule == PMRF_SCATTER_MIN) {
+      const int64_t Mp = std::max<int64_t>(1, h->M);
+      G.em = reinterpret_cast<double *>(ws + plan.elem_off[i]);
+      G.eg = G.em + Mp;
+      G.ea = reinterpret_cast<int32_t *>(G.eg + Mp);
+    } else {
+      G.em = G.eg = nullptr;
+      G.ea = nullptr;
+    }
     G.n = h->n;
     G.H = (int32_t)h->H;
     G.ntiles = (int32_t)h->tiles.size();
@@ -2057,16 +2184,22 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
   GraphDev *d_desc = reinterpret_cast<GraphDev *>(ws + plan.desc_off);
   int32_t *block_graph = reinterpret_cast<int32_t *>(ws + plan.block_graph_off);
   if (blocks_iter != plan.slot_blocks) return fail(PMRF_EDEVICE, "internal: slot block count differs from the plan");
-  bool any_init = false;
-  for (int i = 0; i < B; ++i) any_init |= desc[i].init_from_labels != 0;
+  bool any_init = false, any_min = false, any_rule = false;
+  for (int i = 0; i < B; ++i) {
+    any_init |= desc[i].init_from_labels != 0;
+    any_min |= desc[i].rule == PMRF_SCATTER_MIN;
+    any_rule |= desc[i].rule != PMRF_SCATTER_OWNER;
+  }
   const int lm = lmax_for(Lmax);
   // One launch per EM iteration for a single graph whose superchunks all take
   // the slot kernel and whose records fit one fold pass per block (the blocks
   // of iteration t fold the records of t - 1 themselves); otherwise a fold
   // launch follows every iteration launch.  The fold order is the same either
   // way, so this changes speed only.
-  const bool persist = shape.mode == kModePersistent;
-  const bool fused = B == 1 && blocks_pk == 0 && !persist && lm <= kFusedMaxLabels &&
+  // runs with a scatter rule other than the owner's use the launches compiled
+  // for any rule: one block per superchunk group, a fold launch per iteration
+  const bool persist = shape.mode == kModePersistent && !any_rule;
+  const bool fused = B == 1 && blocks_pk == 0 && !persist && lm <= kFusedMaxLabels && !any_rule &&
                      desc[0].nsuper <= kFoldLanes && desc[0].nslot == desc[0].nsuper && desc[0].nchunks >= 1 &&
                      shape.waves_per_block >= kFoldLanes / 64;
   // dynamic LDS of the slot kernel: the staged range, then the waves' regions
@@ -2130,7 +2263,13 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
 #define PMRF_LAUNCH_LDS(KERNEL, GRID, ...) PMRF_LAUNCH(KERNEL, GRID, lds_pk, __VA_ARGS__)
 #define PMRF_LAUNCH_ITER(LM)                                                                                  \
   do {                                                                                                        \
-    if (fused && t > 0)                                                                                       \
+    if (any_rule && B == 1)                                                                                   \
+      PMRF_LAUNCH_LDS((k_iter<LM, false, true, false, true>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, \
+                      desc[0], B, blocks_iter, t);                                                            \
+    else if (any_rule)                                                                                        \
+      PMRF_LAUNCH_LDS((k_iter<LM, false, false, false, true>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, \
+                      desc[0], B, blocks_iter, t);                                                            \
+    else if (fused && t > 0)                                                                                  \
       PMRF_LAUNCH((k_iter<LM, false, true, true>), dim3(grid_iter), lds_fused, slot_start, slot_stop, gd, block_graph, \
                   desc[0], B, blocks_iter, t);                                                                \
     else if (persist && B == 1)                                                                               \
@@ -2148,7 +2287,13 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
   } while (0)
 #define PMRF_LAUNCH_ITER_UNFUSED(LM)                                                                          \
   do {                                                                                                        \
-    if (persist && B == 1)                                                                                    \
+    if (any_rule && B == 1)                                                                                   \
+      PMRF_LAUNCH_LDS((k_iter<LM, false, true, false, true>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, \
+                      desc[0], B, blocks_iter, t);                                                            \
+    else if (any_rule)                                                                                        \
+      PMRF_LAUNCH_LDS((k_iter<LM, false, false, false, true>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, \
+                      desc[0], B, blocks_iter, t);                                                            \
+    else if (persist && B == 1)                                                                               \
       PMRF_LAUNCH_LDS((k_iter<LM, true, true>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, desc[0], B,           \
                   blocks_iter, t);                                                                            \
     else if (persist)                                                                                         \
@@ -2161,7 +2306,13 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
       PMRF_LAUNCH_LDS((k_iter<LM, false, false>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, desc[0], B,         \
                   blocks_iter, t);                                                                            \
   } while (0)
-#define PMRF_LAUNCH_PK(LM) PMRF_LAUNCH(k_iter_packets<LM>, dim3(blocks_pk), lds_pk, pk_start, pk_stop, gd, B, t)
+#define PMRF_LAUNCH_PK(LM)                                                                                      \
+  do {                                                                                                          \
+    if (any_rule)                                                                                               \
+      PMRF_LAUNCH((k_iter_packets<LM, true>), dim3(blocks_pk), lds_pk, pk_start, pk_stop, gd, B, t);           \
+    else                                                                                                        \
+      PMRF_LAUNCH((k_iter_packets<LM, false>), dim3(blocks_pk), lds_pk, pk_start, pk_stop, gd, B, t);          \
+  } while (0)
       if (blocks_iter > 0) {
         switch (lm) {
           case 2: PMRF_LAUNCH_ITER(2); break;
@@ -2185,6 +2336,16 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
 #undef PMRF_LAUNCH_LDS
 #undef PMRF_LAUNCH
       HIP_TRY(hipGetLastError());
+      // rule MIN: the vertex pass decides the labels of iteration t
+      if (any_min) {
+        switch (lm) {
+          case 2: hipLaunchKernelGGL(k_decide<2>, dim3(blocks_vert), dim3(256), 0, s, gd, B, t); break;
+          case 4: hipLaunchKernelGGL(k_decide<4>, dim3(blocks_vert), dim3(256), 0, s, gd, B, t); break;
+          case 8: hipLaunchKernelGGL(k_decide<8>, dim3(blocks_vert), dim3(256), 0, s, gd, B, t); break;
+          default: hipLaunchKernelGGL(k_decide<16>, dim3(blocks_vert), dim3(256), 0, s, gd, B, t); break;
+        }
+        HIP_TRY(hipGetLastError());
+      }
       // the parameter update of iteration t: here, or (fused) inside the next
       // iteration launch and after the last one
       if (!fused || t + 1 == max_iters) {

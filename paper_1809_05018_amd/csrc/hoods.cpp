@@ -153,7 +153,8 @@ extern "C" pmrf_status pmrf_build_neighborhoods(int32_t n, const int32_t *row_pt
                                                 pmrf_hoods **out) {
   clear_error();
   if (!out) return fail(PMRF_EINVAL, "out is NULL");
-  if (k != 1) return fail(PMRF_EUNSUPPORTED, "only k = 1 neighbourhoods are supported");
+  if (k < 1) return fail(PMRF_EINVAL, "k must be >= 1");
+  if (k > kMaxHoodRadius) return fail(PMRF_EUNSUPPORTED, "k above " + std::to_string(kMaxHoodRadius) + " is not supported");
   pmrf_status st = validate_csr(n, row_ptr, col_idx);
   if (st != PMRF_OK) return st;
   if (n > kMaxSlotVertices)
@@ -180,23 +181,36 @@ extern "C" pmrf_status pmrf_build_neighborhoods(int32_t n, const int32_t *row_pt
       hd->clique_vid.insert(hd->clique_vid.end(), cv + cp[a], cv + cp[a + 1]);
       hd->clique_ptr.push_back((int64_t)hd->clique_vid.size());
     }
-    // neighbourhood = clique u 1-ring, ascending, without repeats
+    // k-neighbourhood = the clique and every vertex within k edges of a member
+    // (rings added one hop at a time from the previous ring), ascending, each
+    // vertex once; the search stops early once a neighbourhood outgrows the
+    // supported size
     std::vector<int64_t> stamp(n, -1);
+    hd->k = k;
     hd->hood_ptr.assign(1, 0);
     for (int64_t h = 0; h < H; ++h) {
       size_t start = hd->hood_vid.size();
       for (int64_t q = hd->clique_ptr[h]; q < hd->clique_ptr[h + 1]; ++q) {
         int32_t c = hd->clique_vid[q];
         if (stamp[c] != h) { stamp[c] = h; hd->hood_vid.push_back(c); }
-        for (int32_t e = row_ptr[c]; e < row_ptr[c + 1]; ++e) {
-          int32_t u = col_idx[e];
-          if (stamp[u] != h) { stamp[u] = h; hd->hood_vid.push_back(u); }
+      }
+      size_t ring0 = start, ring1 = hd->hood_vid.size();
+      for (int32_t depth = 1; depth <= k && ring1 - start <= (size_t)kMaxHood; ++depth) {
+        for (size_t f = ring0; f < ring1; ++f) {
+          const int32_t c = hd->hood_vid[f];
+          for (int32_t e = row_ptr[c]; e < row_ptr[c + 1]; ++e) {
+            int32_t u = col_idx[e];
+            if (stamp[u] != h) { stamp[u] = h; hd->hood_vid.push_back(u); }
+          }
         }
+        ring0 = ring1;
+        ring1 = hd->hood_vid.size();
       }
       std::sort(hd->hood_vid.begin() + start, hd->hood_vid.end());
       int64_t s = (int64_t)(hd->hood_vid.size() - start);
-      hd->max_hood = std::max<int32_t>(hd->max_hood, (int32_t)s);
+      hd->max_hood = std::max<int32_t>(hd->max_hood, (int32_t)std::min<int64_t>(s, INT32_MAX));
       hd->hood_ptr.push_back((int64_t)hd->hood_vid.size());
+      if (hd->max_hood > kMaxHood) break;
     }
     hd->M = (int64_t)hd->hood_vid.size();
     if (hd->max_hood > kMaxHood) {
@@ -233,6 +247,27 @@ extern "C" pmrf_status pmrf_build_neighborhoods(int32_t n, const int32_t *row_pt
       hd->dev_vid.insert(hd->dev_vid.end(), hd->hood_vid.begin() + hd->hood_ptr[h],
                          hd->hood_vid.begin() + hd->hood_ptr[h + 1]);
       hd->hood_ptr32.push_back((int32_t)hd->dev_vid.size());
+    }
+    // the elements of each vertex (processing-order indices) in canonical
+    // neighbourhood order, and the element in its last canonical neighbourhood
+    {
+      std::vector<int32_t> inv(H);
+      for (int64_t hp = 0; hp < H; ++hp) inv[hd->perm[hp]] = (int32_t)hp;
+      hd->occ_ptr.assign((size_t)n + 1, 0);
+      for (int64_t e = 0; e < hd->M; ++e) hd->occ_ptr[hd->hood_vid[e] + 1]++;
+      for (int32_t v = 0; v < n; ++v) hd->occ_ptr[v + 1] += hd->occ_ptr[v];
+      hd->occ.assign((size_t)std::max<int64_t>(1, hd->M), 0);
+      std::vector<int32_t> fill(hd->occ_ptr.begin(), hd->occ_ptr.end() - 1);
+      hd->lastbits.assign((size_t)(hd->M / 64 + 2), 0ull);
+      for (int64_t h = 0; h < H; ++h) {
+        const int64_t pe = hd->hood_ptr32[inv[h]];
+        for (int64_t e = hd->hood_ptr[h]; e < hd->hood_ptr[h + 1]; ++e)
+          hd->occ[fill[hd->hood_vid[e]]++] = (int32_t)(pe + (e - hd->hood_ptr[h]));
+      }
+      for (int32_t v = 0; v < n; ++v) {
+        const int32_t e = hd->occ[hd->occ_ptr[v + 1] - 1];
+        hd->lastbits[e >> 6] |= 1ull << (e & 63);
+      }
     }
     // work packets and adjacency words, in processing order
     std::vector<int32_t> loc(n, -1);
@@ -354,7 +389,10 @@ extern "C" pmrf_status pmrf_build_neighborhoods(int32_t n, const int32_t *row_pt
     L.smaskhi_off = L.smask_off + align_up((int64_t)hd->smask.size() * 4, 256);
     L.perm_off = L.smaskhi_off + align_up((int64_t)hd->smask_hi.size() * 4, 256);
     L.srange_off = L.perm_off + align_up(hd->H * 4, 256);
-    L.total = L.srange_off + align_up((int64_t)hd->srange.size() * 4, 256);
+    L.lastbits_off = L.srange_off + align_up((int64_t)hd->srange.size() * 4, 256);
+    L.occptr_off = L.lastbits_off + align_up((int64_t)hd->lastbits.size() * 8, 256);
+    L.occ_off = L.occptr_off + align_up((int64_t)hd->occ_ptr.size() * 4, 256);
+    L.total = L.occ_off + align_up((int64_t)hd->occ.size() * 4, 256);
     if (L.total == 0) L.total = 256;
   } catch (const std::bad_alloc &) {
     delete hd;
@@ -417,6 +455,13 @@ extern "C" pmrf_status pmrf_hoods_upload(const pmrf_hoods *h, void *d_buf, int64
     e = hipMemcpyAsync(base + h->layout.smask_off, h->smask.data(), h->smask.size() * 4, hipMemcpyHostToDevice, s);
   if (e == hipSuccess && !h->perm.empty())
     e = hipMemcpyAsync(base + h->layout.perm_off, h->perm.data(), h->perm.size() * 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && !h->lastbits.empty())
+    e = hipMemcpyAsync(base + h->layout.lastbits_off, h->lastbits.data(), h->lastbits.size() * 8, hipMemcpyHostToDevice,
+                       s);
+  if (e == hipSuccess && !h->occ_ptr.empty())
+    e = hipMemcpyAsync(base + h->layout.occptr_off, h->occ_ptr.data(), h->occ_ptr.size() * 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && !h->occ.empty())
+    e = hipMemcpyAsync(base + h->layout.occ_off, h->occ.data(), h->occ.size() * 4, hipMemcpyHostToDevice, s);
   if (e == hipSuccess && !h->srange.empty())
     e = hipMemcpyAsync(base + h->layout.srange_off, h->srange.data(), h->srange.size() * 4, hipMemcpyHostToDevice, s);
   if (e == hipSuccess && !h->smask_hi.empty())

@@ -13,6 +13,7 @@ namespace pmrf {
 constexpr int kWave = 64;
 constexpr int kMaxLabels = 16;
 constexpr int kMaxHood = 1024;
+constexpr int kMaxHoodRadius = 8;  // k of the k-neighbourhoods
 constexpr int kMaxWindow = 8;
 
 // Work packet kinds.  A SMALL tile packs whole neighbourhoods of at most 32
@@ -77,6 +78,8 @@ struct DeviceLayout {
   int64_t chdr_off, svid_off, smask_off, smaskhi_off;  // slot layout
   int64_t perm_off;                                     // processing index -> canonical neighbourhood
   int64_t srange_off;                                   // member vertex range of each superchunk
+  int64_t lastbits_off;                                 // element holds the last occurrence of its vertex
+  int64_t occptr_off, occ_off;                          // each vertex's elements, canonical hood order
   int64_t total;
 };
 
@@ -87,6 +90,7 @@ inline int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 // Host object behind the opaque pmrf_hoods handle.
 struct pmrf_hoods {
   int32_t n = 0;
+  int32_t k = 1;  // neighbourhood radius
   int64_t H = 0, M = 0, A = 0;
   int32_t max_hood = 0;
   std::vector<int64_t> clique_ptr;
@@ -109,6 +113,12 @@ struct pmrf_hoods {
   // per superchunk s: [srange[2 s], srange[2 s + 1]) holds the member vertices
   // of its slot-layout packets (empty range where it has none)
   std::vector<int32_t> srange;
+  // scatter rules other than the owner's: bit e of lastbits is set when
+  // element e (processing order) holds its vertex in the vertex's last
+  // neighbourhood in canonical order; occ[occ_ptr[v] .. occ_ptr[v + 1]) are
+  // the elements holding v, in canonical neighbourhood order
+  std::vector<uint64_t> lastbits;
+  std::vector<int32_t> occ_ptr, occ;
   pmrf::DeviceLayout layout{};
 };
 

@@ -56,7 +56,7 @@ class HoodsInfo(Structure):
 class EmParams(Structure):
     _fields_ = [("L", c_int32), ("beta", c_double), ("max_iters", c_int32), ("conv_window", c_int32),
                 ("conv_tol", c_double), ("early_exit", c_int32), ("init_from_labels", c_int32),
-                ("sigma_min", c_double), ("tie_eps", c_double)]
+                ("sigma_min", c_double), ("tie_eps", c_double), ("scatter_rule", c_int32)]
 
 
 class EmItem(Structure):
@@ -73,6 +73,10 @@ class Launch(Structure):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run paper_1809_05018_amd/build_lib.py (or __graft_entry__.build())")
+    # torch first: the library's HIP calls must go to the HIP runtime that torch
+    # loads (and allocates device memory with), whatever order callers import in
+    import torch  # noqa: F401
+
     lib = ctypes.CDLL(LIB_PATH)
     P = POINTER
     lib.pmrf_last_error.restype = c_char_p
@@ -125,13 +129,17 @@ def _p(a, ct):
     return a.ctypes.data_as(POINTER(ct))
 
 
+SCATTER_OWNER, SCATTER_LAST, SCATTER_MIN = 0, 1, 2
+
+
 def pmrf_em_params(L=2, beta=0.5, max_iters=20, conv_window=3, conv_tol=1e-4, early_exit=False,
-                   init_from_labels=False, sigma_min=1e-3, tie_eps=1e-9) -> EmParams:
+                   init_from_labels=False, sigma_min=1e-3, tie_eps=1e-9, scatter_rule=SCATTER_OWNER) -> EmParams:
     p = EmParams()
     lib.pmrf_em_params_default(ctypes.byref(p))
     p.L, p.beta, p.max_iters, p.conv_window, p.conv_tol = int(L), float(beta), int(max_iters), int(conv_window), float(conv_tol)
     p.early_exit, p.init_from_labels = int(bool(early_exit)), int(bool(init_from_labels))
     p.sigma_min, p.tie_eps = float(sigma_min), float(tie_eps)
+    p.scatter_rule = int(scatter_rule)
     return p
 
 

@@ -30,12 +30,12 @@ def test_exports_every_declared_symbol():
     for name in names:
         assert hasattr(lib, name), name
     assert set(names) == set(pmrf.EXPORTED)
-    assert pmrf.lib.pmrf_abi_version() == 1
+    assert pmrf.lib.pmrf_abi_version() == 2
 
 
-def compare_with_oracle(n, rp, ci):
-    h = pmrf.pmrf_build_neighborhoods(n, rp, ci)
-    og = oracle.OracleGraph(n, rp, ci)
+def compare_with_oracle(n, rp, ci, k=1):
+    h = pmrf.pmrf_build_neighborhoods(n, rp, ci, k)
+    og = oracle.OracleGraph(n, rp, ci, k=k)
     ex = h.export()
     ocp, ocv = og.cliques()
     ohp, ohv = og.hoods()
@@ -60,6 +60,16 @@ def test_builder_matches_oracle_workloads():
     assert h.max_hood > 64  # exercises the multi-chunk packet layout
 
 
+def test_builder_k_neighbourhoods_match_oracle():
+    for k in (2, 3):
+        for n, rp, ci in pins.random_small_graphs(count=40):
+            compare_with_oracle(n, rp, ci, k)
+    g = synth.workload_small()
+    h1 = compare_with_oracle(g.n, g.row_ptr, g.col_idx)
+    h2 = compare_with_oracle(g.n, g.row_ptr, g.col_idx, 2)
+    assert h2.M > 2 * h1.M and 32 < h2.max_hood <= 64  # two rings of an image graph: MID packets
+
+
 def test_builder_edge_cases():
     h = pmrf.pmrf_build_neighborhoods(0, np.zeros(1, np.int32), np.zeros(0, np.int32))
     assert (h.n, h.H, h.M) == (0, 0, 0) and h.device_bytes >= 256
@@ -81,7 +91,7 @@ def test_neighbourhood_limit():
     assert e.value.code == pmrf.PMRF_EUNSUPPORTED
 
 
-@pytest.mark.parametrize("case", ["asym", "selfloop", "unsorted", "range", "rowptr", "k2"])
+@pytest.mark.parametrize("case", ["asym", "selfloop", "unsorted", "range", "rowptr", "k0", "k9"])
 def test_validation_errors(case):
     rp, ci = pins.csr(4, [(0, 1), (1, 2), (2, 3)])
     rp, ci = rp.copy(), ci.copy()
@@ -98,8 +108,10 @@ def test_validation_errors(case):
         ci[-1] = 7
     elif case == "rowptr":
         rp[2] = rp[1] - 1
-    elif case == "k2":
-        k = 2
+    elif case == "k0":
+        k = 0
+    elif case == "k9":
+        k = 9
     with pytest.raises(pmrf.PmrfError) as e:
         pmrf.pmrf_build_neighborhoods(4, rp, ci, k)
     assert e.value.code in (pmrf.PMRF_EINVAL, pmrf.PMRF_EUNSUPPORTED)
