@@ -135,7 +135,15 @@ class GpuExecutor:
         if self.ws is None or self.ws.numel() != need:
             self.ws = None  # release before allocating: the footprint is the exact need
             self.ws = torch.empty(need, dtype=torch.uint8, device=self.device)
-        pm.pmrf_em_batch(items, self.ws)
+        # the active set, its trace offsets and its starting flags change from
+        # step to step, so a HIP graph of one step would rarely be replayed:
+        # steps launch their kernels directly (launch mode 3)
+        prev = pm.pmrf_get_launch()
+        pm.pmrf_set_launch(**dict(prev, mode=3))
+        try:
+            pm.pmrf_em_batch(items, self.ws)
+        finally:
+            pm.pmrf_set_launch(**prev)
         # one copy back for every request's counters (it waits for the batch)
         c = torch.stack([slot["prob"].counters for _, slot in active]).cpu().numpy()
         out = []

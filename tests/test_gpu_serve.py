@@ -4,7 +4,9 @@ import numpy as np
 import pytest
 import torch
 
+import oracle
 from paper_1809_05018_amd import pmrf, serve, synth
+from tests.gpu_helpers import compare_runs
 
 pytestmark = pytest.mark.gpu
 
@@ -23,7 +25,11 @@ def test_serving_mix_equals_solo():
     ex = serve.GpuExecutor("cuda")
     sizes = [ex.footprint(r, ex.build(r)) for r in reqs]
     srv = serve.Server(ex, hbm_budget=int(sum(sizes) * 0.5), iters_per_step=10)
+    before = pmrf.pmrf_launch_stats()
     stats = srv.run(reqs)
+    after = pmrf.pmrf_launch_stats()
+    assert after["captures"] == before["captures"] and after["replays"] == before["replays"]  # no graph per step
+    assert after["direct"] - before["direct"] == stats.steps
     assert stats.requests == count and max(srv.footprint_log) <= srv.budget
     assert stats.max_active > 1  # work really overlapped
     for r in reqs:
@@ -32,6 +38,26 @@ def test_serving_mix_equals_solo():
                                                             init_from_labels=True))
         for k in ("x", "mu", "sigma", "S", "trace"):
             assert np.array_equal(np.asarray(r.result[k]), np.asarray(solo[k])), (r.rid, k)
+    # the served results against the oracle: the smallest requests whose
+    # oracle run has no near tie (so every label is decided), all their
+    # iterations from the same start
+    compared = 0
+    for r in sorted(reqs, key=lambda q: q.n):
+        og = oracle.OracleGraph(r.n, r.row_ptr, r.col_idx)
+        ref = og.em_run(r.y, r.L, r.beta, serve.threshold_start(r.y, r.L), np.zeros(r.L), np.ones(r.L), r.iters,
+                        init_from_labels=True)
+        if ref["total_near_ties"]:
+            continue
+        got = dict(r.result, status=0, iters=r.done_iters)
+        # the per-call bookkeeping restarts in each batched call, so only the
+        # quantities of the whole run are compared
+        for key in ("near_ties", "nonconv", "map_conv_iter", "em_conv_iter", "total_near_ties"):
+            got[key] = ref[key]
+        compare_runs(got, ref, f"served request {r.rid} (n={r.n}, L={r.L})")
+        compared += 1
+        if compared == 3:
+            break
+    assert compared == 3
 
 
 def solo_schedule(r, k):
