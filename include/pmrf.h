@@ -82,13 +82,33 @@ typedef struct {
 /* Build the neighbourhoods of an undirected graph given as CSR (host).
  * row_ptr[n+1] (row_ptr[0] = 0, non-decreasing) and col_idx[row_ptr[n]]
  * with each row strictly ascending, no self loops, every edge present in both
- * directions.  k is the neighbourhood radius; only k = 1 is supported.
+ * directions.  k is the neighbourhood radius, 1..8 (the paper uses k = 1):
+ * a neighbourhood holds its clique and every vertex within k edges of it.
  * n = 0 is allowed (empty problem).  *out receives a new host object.
- * Errors: PMRF_EINVAL (malformed CSR, NULL pointers), PMRF_EUNSUPPORTED
- * (k != 1, a neighbourhood above 1024 members, n above 2^26 - 1 = 67108863
- * vertices), PMRF_ENOMEM. */
+ * Errors: PMRF_EINVAL (malformed CSR, NULL pointers, k < 1), PMRF_EUNSUPPORTED
+ * (k > 8, a neighbourhood above 1024 members, n above 2^26 - 1 = 67108863
+ * vertices, 2^30 or more neighbourhood elements), PMRF_ENOMEM. */
 pmrf_status pmrf_build_neighborhoods(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, int32_t k,
                                      pmrf_hoods **out);
+
+/* The same construction on the device (Alg. 2, "enumerate maximal cliques"
+ * and "construct k-neighborhoods", as data-parallel passes: Sec. 3.2.2 Find /
+ * Count / Get Neighbors and Remove Duplicate Neighbors).  d_row_ptr[n+1] and
+ * d_col_idx[d_row_ptr[n]] are device arrays on the current device with the
+ * CSR rules above (checked on the device).  Work is enqueued on hip_stream
+ * (NULL: the null stream); the call synchronises that stream several times
+ * to size its arrays and returns when the structure is complete.  The result
+ * equals pmrf_build_neighborhoods' in every exported array and in the layout
+ * pmrf_hoods_upload writes, byte for byte; its layout and canonical arrays
+ * stay in device memory owned by the object (hipMalloc; released by
+ * pmrf_hoods_free), and pmrf_hoods_upload copies device to device.  The
+ * caller keeps ownership of the CSR, which is not needed afterwards.
+ * Errors: as pmrf_build_neighborhoods, plus PMRF_EUNSUPPORTED when one
+ * neighbourhood gathers more than 8192 candidate entries (its members'
+ * rows, duplicates included) or a clique level would exceed 2^30 member
+ * entries, and PMRF_EDEVICE / PMRF_ENOMEM for HIP failures. */
+pmrf_status pmrf_build_neighborhoods_device(int32_t n, const int32_t *d_row_ptr, const int32_t *d_col_idx, int32_t k,
+                                            void *hip_stream, pmrf_hoods **out);
 
 pmrf_status pmrf_hoods_get_info(const pmrf_hoods *hoods, pmrf_hoods_info *info);
 

@@ -10,7 +10,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpmrf.so")
-SOURCES = ["em.hip", "image.hip", "hoods.cpp", "abi.cpp"]
+SOURCES = ["em.hip", "image.hip", "build.hip", "hoods.cpp", "abi.cpp"]
 
 
 def hipcc() -> str:

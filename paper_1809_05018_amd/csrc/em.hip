@@ -2005,7 +2005,7 @@ pmrf_status check_item(const pmrf_em_item &it, int idx) {
   return PMRF_OK;
 }
 
-int64_t n_chunks(const pmrf_hoods *h) { return ((int64_t)h->tiles.size() + kChunkTiles - 1) / kChunkTiles; }
+int64_t n_chunks(const pmrf_hoods *h) { return (h->ntiles + kChunkTiles - 1) / kChunkTiles; }
 int64_t vert_blocks(const pmrf_hoods *h) { return std::max<int64_t>(1, ((int64_t)h->n + kVertPerBlock - 1) / kVertPerBlock); }
 int32_t superchunk_chunks(const pmrf_hoods *h) { return superchunk_chunks_of(n_chunks(h)); }
 int64_t n_super(const pmrf_hoods *h) {
@@ -2026,7 +2026,7 @@ int64_t max_records(const pmrf_hoods *h, const pmrf_em_params &p) {
 // longer than kPreWindow; the rest take the packet kernel.
 int32_t slot_supers(const pmrf_hoods *h, const pmrf_em_params &params) {
   const int64_t per_super = (int64_t)kChunkTiles * superchunk_chunks(h);
-  int32_t nslot = h->slot_tiles == (int64_t)h->tiles.size() ? (int32_t)n_super(h) : (int32_t)(h->slot_tiles / per_super);
+  int32_t nslot = h->slot_tiles == h->ntiles ? (int32_t)n_super(h) : (int32_t)(h->slot_tiles / per_super);
   if (params.conv_window > kPreWindow) nslot = 0;
   return nslot;
 }
@@ -2149,7 +2149,7 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
     }
     G.n = h->n;
     G.H = (int32_t)h->H;
-    G.ntiles = (int32_t)h->tiles.size();
+    G.ntiles = (int32_t)h->ntiles;
     G.L = it.params.L;
     G.P = it.params.L <= 2 ? 1 : it.params.L <= 4 ? 2 : it.params.L <= 8 ? 3 : 4;
     G.W = it.params.conv_window;

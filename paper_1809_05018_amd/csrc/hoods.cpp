@@ -378,22 +378,20 @@ extern "C" pmrf_status pmrf_build_neighborhoods(int32_t n, const int32_t *row_pt
         hd->srange[2 * sp + 1] = hi;
       }
     }
-    DeviceLayout &L = hd->layout;
-    L.tiles_off = 0;
-    L.hptr_off = align_up(ntiles * (int64_t)sizeof(TileDesc), 256);
-    L.vid_off = L.hptr_off + align_up((hd->H + 1) * 4, 256);
-    L.mask_off = L.vid_off + align_up(hd->M * 4, 256);
-    L.chdr_off = L.mask_off + align_up((int64_t)hd->mask.size() * 4, 256);
-    L.svid_off = L.chdr_off + align_up((int64_t)hd->chdr.size() * (int64_t)sizeof(ChunkHdr), 256);
-    L.smask_off = L.svid_off + align_up((int64_t)hd->svid.size() * 4, 256);
-    L.smaskhi_off = L.smask_off + align_up((int64_t)hd->smask.size() * 4, 256);
-    L.perm_off = L.smaskhi_off + align_up((int64_t)hd->smask_hi.size() * 4, 256);
-    L.srange_off = L.perm_off + align_up(hd->H * 4, 256);
-    L.lastbits_off = L.srange_off + align_up((int64_t)hd->srange.size() * 4, 256);
-    L.occptr_off = L.lastbits_off + align_up((int64_t)hd->lastbits.size() * 8, 256);
-    L.occ_off = L.occptr_off + align_up((int64_t)hd->occ_ptr.size() * 4, 256);
-    L.total = L.occ_off + align_up((int64_t)hd->occ.size() * 4, 256);
-    if (L.total == 0) L.total = 256;
+    LayoutSizes z{};
+    z.ntiles = ntiles;
+    z.H = hd->H;
+    z.M = hd->M;
+    z.mask_words = (int64_t)hd->mask.size();
+    z.nchdr = (int64_t)hd->chdr.size();
+    z.slots = (int64_t)hd->svid.size();
+    z.slots_hi = (int64_t)hd->smask_hi.size();
+    z.nsrange = (int64_t)hd->srange.size();
+    z.nlastbits = (int64_t)hd->lastbits.size();
+    z.nocc_ptr = (int64_t)hd->occ_ptr.size();
+    z.nocc = (int64_t)hd->occ.size();
+    hd->layout = layout_of(z);
+    hd->ntiles = ntiles;
   } catch (const std::bad_alloc &) {
     delete hd;
     return fail(PMRF_ENOMEM, "host allocation failed while building neighbourhoods");
@@ -410,15 +408,55 @@ extern "C" pmrf_status pmrf_hoods_get_info(const pmrf_hoods *h, pmrf_hoods_info 
   info->M = h->M;
   info->A = h->A;
   info->max_hood = h->max_hood;
-  info->tiles = (int64_t)h->tiles.size();
+  info->tiles = h->ntiles;
   info->device_bytes = h->layout.total;
   return PMRF_OK;
 }
+
+pmrf_hoods::~pmrf_hoods() {
+  for (void *p : {dev_layout, dev_clique_ptr, dev_clique_vid, dev_hood_ptr, dev_hood_vid, dev_owner})
+    if (p) (void)hipFree(p);
+}
+
+namespace {
+
+// int32 device array -> host int64 (or int32) array
+hipError_t fetch_widened(int64_t *dst, const void *src, int64_t count) {
+  if (count <= 0 || !dst) return hipSuccess;
+  std::vector<int32_t> tmp((size_t)count);
+  hipError_t e = hipMemcpy(tmp.data(), src, (size_t)count * 4, hipMemcpyDeviceToHost);
+  for (int64_t i = 0; i < count; ++i) dst[i] = tmp[(size_t)i];
+  return e;
+}
+
+hipError_t fetch(int32_t *dst, const void *src, int64_t count) {
+  if (count <= 0 || !dst) return hipSuccess;
+  return hipMemcpy(dst, src, (size_t)count * 4, hipMemcpyDeviceToHost);
+}
+
+// exports of a neighbourhood structure built on the device
+pmrf_status export_device(const pmrf_hoods *h, int64_t *hood_ptr, int32_t *hood_vid, int64_t *clique_ptr,
+                          int32_t *clique_vid, int64_t *owner) {
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return fail(PMRF_EDEVICE, "no current HIP device");
+  if (cur != h->device && hipSetDevice(h->device) != hipSuccess) return fail(PMRF_EDEVICE, "hipSetDevice failed");
+  hipError_t e = fetch_widened(hood_ptr, h->dev_hood_ptr, h->H + 1);
+  if (e == hipSuccess) e = fetch(hood_vid, h->dev_hood_vid, h->M);
+  if (e == hipSuccess) e = fetch_widened(clique_ptr, h->dev_clique_ptr, h->H + 1);
+  if (e == hipSuccess) e = fetch(clique_vid, h->dev_clique_vid, h->dev_clique_total);
+  if (e == hipSuccess) e = fetch_widened(owner, h->dev_owner, h->n);
+  if (cur != h->device) (void)hipSetDevice(cur);
+  if (e != hipSuccess) return fail(PMRF_EDEVICE, std::string("hipMemcpy: ") + hipGetErrorString(e));
+  return PMRF_OK;
+}
+
+}  // namespace
 
 extern "C" pmrf_status pmrf_hoods_export(const pmrf_hoods *h, int64_t *hood_ptr, int32_t *hood_vid,
                                          int64_t *clique_ptr, int32_t *clique_vid, int64_t *owner) {
   clear_error();
   if (!h) return fail(PMRF_EINVAL, "hoods is NULL");
+  if (h->on_device) return export_device(h, hood_ptr, hood_vid, clique_ptr, clique_vid, owner);
   if (hood_ptr) std::memcpy(hood_ptr, h->hood_ptr.data(), h->hood_ptr.size() * sizeof(int64_t));
   if (hood_vid && h->M) std::memcpy(hood_vid, h->hood_vid.data(), (size_t)h->M * sizeof(int32_t));
   if (clique_ptr) std::memcpy(clique_ptr, h->clique_ptr.data(), h->clique_ptr.size() * sizeof(int64_t));
@@ -436,6 +474,11 @@ extern "C" pmrf_status pmrf_hoods_upload(const pmrf_hoods *h, void *d_buf, int64
   hipStream_t s = static_cast<hipStream_t>(stream);
   char *base = static_cast<char *>(d_buf);
   hipError_t e = hipSuccess;
+  if (h->on_device) {
+    e = hipMemcpyAsync(base, h->dev_layout, (size_t)h->layout.total, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return fail(PMRF_EDEVICE, std::string("hipMemcpyAsync: ") + hipGetErrorString(e));
+    return PMRF_OK;
+  }
   if (!h->tiles.empty())
     e = hipMemcpyAsync(base + h->layout.tiles_off, h->tiles.data(), h->tiles.size() * sizeof(TileDesc),
                        hipMemcpyHostToDevice, s);
@@ -495,7 +538,12 @@ extern "C" pmrf_status pmrf_replicate_indices(const pmrf_hoods *h, int32_t L, in
     clear_error();
     return fail(PMRF_EINVAL, "hoods is NULL");
   }
-  return pmrf_replicate_hood_array(h->H, h->hood_ptr.data(), L, test_label, old_index, hood_id);
+  if (!h->on_device) return pmrf_replicate_hood_array(h->H, h->hood_ptr.data(), L, test_label, old_index, hood_id);
+  std::vector<int64_t> hp((size_t)h->H + 1);
+  clear_error();
+  pmrf_status st = export_device(h, hp.data(), nullptr, nullptr, nullptr, nullptr);
+  if (st != PMRF_OK) return st;
+  return pmrf_replicate_hood_array(h->H, hp.data(), L, test_label, old_index, hood_id);
 }
 
 extern "C" void pmrf_hoods_free(pmrf_hoods *h) { delete h; }

@@ -85,10 +85,38 @@ struct DeviceLayout {
 
 inline int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
+// Entry counts of the device arrays; both builders place them with layout_of.
+struct LayoutSizes {
+  int64_t ntiles, H, M, mask_words, nchdr, slots, slots_hi, nsrange, nlastbits, nocc_ptr, nocc;
+};
+
+inline DeviceLayout layout_of(const LayoutSizes &z) {
+  DeviceLayout L{};
+  L.tiles_off = 0;
+  L.hptr_off = align_up(z.ntiles * (int64_t)sizeof(TileDesc), 256);
+  L.vid_off = L.hptr_off + align_up((z.H + 1) * 4, 256);
+  L.mask_off = L.vid_off + align_up(z.M * 4, 256);
+  L.chdr_off = L.mask_off + align_up(z.mask_words * 4, 256);
+  L.svid_off = L.chdr_off + align_up(z.nchdr * (int64_t)sizeof(ChunkHdr), 256);
+  L.smask_off = L.svid_off + align_up(z.slots * 4, 256);
+  L.smaskhi_off = L.smask_off + align_up(z.slots * 4, 256);
+  L.perm_off = L.smaskhi_off + align_up(z.slots_hi * 4, 256);
+  L.srange_off = L.perm_off + align_up(z.H * 4, 256);
+  L.lastbits_off = L.srange_off + align_up(z.nsrange * 4, 256);
+  L.occptr_off = L.lastbits_off + align_up(z.nlastbits * 8, 256);
+  L.occ_off = L.occptr_off + align_up(z.nocc_ptr * 4, 256);
+  L.total = L.occ_off + align_up(z.nocc * 4, 256);
+  if (L.total == 0) L.total = 256;
+  return L;
+}
+
 }  // namespace pmrf
 
-// Host object behind the opaque pmrf_hoods handle.
+// Host object behind the opaque pmrf_hoods handle.  The host builder fills
+// the vectors below; the device builder leaves them empty and keeps the
+// layout and the canonical arrays in device memory it owns (dev_*).
 struct pmrf_hoods {
+  ~pmrf_hoods();
   int32_t n = 0;
   int32_t k = 1;  // neighbourhood radius
   int64_t H = 0, M = 0, A = 0;
@@ -119,7 +147,17 @@ struct pmrf_hoods {
   // the elements holding v, in canonical neighbourhood order
   std::vector<uint64_t> lastbits;
   std::vector<int32_t> occ_ptr, occ;
+  int64_t ntiles = 0;  // packets of the layout
   pmrf::DeviceLayout layout{};
+  // built on the device: the layout (layout.total bytes) and the canonical
+  // arrays as int32 (clique_ptr and hood_ptr H + 1, clique members, hood
+  // members M, owner n), all on device `device`
+  bool on_device = false;
+  int device = -1;
+  void *dev_layout = nullptr;
+  void *dev_clique_ptr = nullptr, *dev_clique_vid = nullptr, *dev_hood_ptr = nullptr, *dev_hood_vid = nullptr,
+       *dev_owner = nullptr;
+  int64_t dev_clique_total = 0;
 };
 
 namespace pmrf {

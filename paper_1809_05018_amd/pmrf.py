@@ -38,7 +38,7 @@ EXPORTED = (
     "pmrf_em_batch_workspace_bytes", "pmrf_em_batch", "pmrf_set_launch", "pmrf_get_launch",
     "pmrf_profile_begin", "pmrf_profile_end", "pmrf_image_graph_workspace_bytes", "pmrf_image_graph",
     "pmrf_labels_to_pixels", "pmrf_confusion", "pmrf_volume_graph_workspace_bytes", "pmrf_volume_graph",
-    "pmrf_launch_stats", "pmrf_em_run_noalloc",
+    "pmrf_launch_stats", "pmrf_em_run_noalloc", "pmrf_build_neighborhoods_device",
 )
 
 
@@ -82,6 +82,7 @@ def _load():
     lib.pmrf_last_error.restype = c_char_p
     lib.pmrf_abi_version.restype = c_int32
     lib.pmrf_build_neighborhoods.argtypes = [c_int32, P(c_int32), P(c_int32), c_int32, P(c_void_p)]
+    lib.pmrf_build_neighborhoods_device.argtypes = [c_int32, c_void_p, c_void_p, c_int32, c_void_p, P(c_void_p)]
     lib.pmrf_hoods_get_info.argtypes = [c_void_p, P(HoodsInfo)]
     lib.pmrf_hoods_export.argtypes = [c_void_p, P(c_int64), P(c_int32), P(c_int64), P(c_int32), P(c_int64)]
     lib.pmrf_hoods_upload.argtypes = [c_void_p, c_void_p, c_int64, c_void_p]
@@ -201,6 +202,25 @@ def pmrf_build_neighborhoods(n, row_ptr, col_idx, k=1) -> Hoods:
         ci = np.zeros(1, np.int32)
     out = c_void_p()
     _check(lib.pmrf_build_neighborhoods(int(n), _p(rp, c_int32), _p(ci, c_int32), int(k), ctypes.byref(out)))
+    return Hoods(out.value)
+
+
+def pmrf_build_neighborhoods_device(n, row_ptr, col_idx, k=1, stream=None) -> Hoods:
+    """Same structure built on the device from a CSR held in device memory
+    (int32 tensors row_ptr[n + 1] and col_idx[row_ptr[n]]); numpy arrays are
+    copied to the current device first.  Returns after the build has finished."""
+    import torch
+
+    dev = torch.device("cuda", torch.cuda.current_device())
+    rp = torch.as_tensor(np.asarray(row_ptr, dtype=np.int32) if not torch.is_tensor(row_ptr) else row_ptr,
+                         dtype=torch.int32, device=dev).contiguous()
+    ci = torch.as_tensor(np.asarray(col_idx, dtype=np.int32) if not torch.is_tensor(col_idx) else col_idx,
+                         dtype=torch.int32, device=dev).contiguous()
+    if ci.numel() == 0:
+        ci = torch.zeros(1, dtype=torch.int32, device=dev)
+    out = c_void_p()
+    _check(lib.pmrf_build_neighborhoods_device(int(n), rp.data_ptr(), ci.data_ptr(), int(k), _stream(stream, dev),
+                                               ctypes.byref(out)))
     return Hoods(out.value)
 
 

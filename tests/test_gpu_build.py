@@ -1,0 +1,146 @@
+"""Neighbourhood construction on the device (Alg. 2, maximal cliques and
+k-neighbourhoods; Sec. 3.2.2 Find / Count / Get Neighbors, Remove Duplicate
+Neighbors): cliques, neighbourhoods, owners and adjacency element by element
+against the oracle, and the whole packed layout byte for byte against the host
+builder's (needs the GPU)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1809_05018_amd import pmrf, synth
+from tests import pins
+from tests.gpu_helpers import compare_runs, init_state
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def device():
+    assert torch.cuda.is_available(), "gpu tests need a HIP device"
+    return "cuda"
+
+
+def layout_bytes(h):
+    buf = torch.zeros(max(256, h.device_bytes), dtype=torch.uint8, device="cuda")
+    pmrf.lib.pmrf_hoods_upload(h.handle, pmrf.c_void_p(buf.data_ptr()), buf.numel(),
+                               pmrf.c_void_p(torch.cuda.current_stream().cuda_stream))
+    torch.cuda.synchronize()
+    return buf.cpu().numpy()
+
+
+def check_graph(n, rp, ci, k=1, what=""):
+    d = pmrf.pmrf_build_neighborhoods_device(n, rp, ci, k)
+    og = oracle.OracleGraph(n, rp, ci, k=k)
+    assert (d.n, d.H, d.M, d.A, d.max_hood) == (og.n, og.H, og.M, og.A, og.max_hood), what
+    ex = d.export()
+    ocp, ocv = og.cliques()
+    ohp, ohv = og.hoods()
+    assert np.array_equal(ex["clique_ptr"], ocp) and np.array_equal(ex["clique_vid"], ocv), what + " cliques"
+    assert np.array_equal(ex["hood_ptr"], ohp) and np.array_equal(ex["hood_vid"], ohv), what + " hoods"
+    assert np.array_equal(ex["owner"], og.owner()), what + " owners"
+    h = pmrf.pmrf_build_neighborhoods(n, rp, ci, k)
+    assert (d.tiles, d.device_bytes) == (h.tiles, h.device_bytes), what
+    a, b = layout_bytes(d), layout_bytes(h)
+    diff = np.flatnonzero(a != b)
+    assert diff.size == 0, f"{what}: layouts differ at bytes {diff[:8]} of {a.size}"
+    return d
+
+
+def test_small_random_graphs():
+    for n, rp, ci in pins.random_small_graphs(count=60):
+        check_graph(n, rp, ci, 1, f"random n={n}")
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_small_random_graphs_k(k):
+    for n, rp, ci in pins.random_small_graphs(count=30):
+        check_graph(n, rp, ci, k, f"random n={n} k={k}")
+
+
+def edge_graphs():
+    yield "empty", 0, np.zeros(1, np.int32), np.zeros(0, np.int32)
+    yield "isolated", 5, *pins.csr(5, [])
+    yield "one edge", 2, *pins.csr(2, [(0, 1)])
+    yield "path", 6, *pins.csr(6, [(i, i + 1) for i in range(5)])
+    yield "K8", 8, *pins.csr(8, [(i, j) for i in range(8) for j in range(i + 1, 8)])
+    yield "star", 40, *pins.csr(40, [(0, j) for j in range(1, 40)])
+    yield "two K4 and loose vertices", 11, *pins.csr(11, [(i, j) for i in range(4) for j in range(i + 1, 4)]
+                                                      + [(i, j) for i in range(5, 9) for j in range(i + 1, 9)])
+    # a hub of 1023 leaves: the largest neighbourhood the layout allows
+    yield "hub 1023", 1024, *pins.csr(1024, [(0, j) for j in range(1, 1024)])
+
+
+@pytest.mark.parametrize("case", list(range(8)))
+def test_edge_graphs(case):
+    name, n, rp, ci = list(edge_graphs())[case]
+    check_graph(n, rp, ci, 1, name)
+
+
+def test_image_and_powerlaw_workloads():
+    g = synth.workload_small()
+    d = check_graph(g.n, g.row_ptr, g.col_idx, 1, "slice 20k")
+    assert d.max_hood <= 32
+    check_graph(g.n, g.row_ptr, g.col_idx, 2, "slice 20k k=2")
+    p = synth.powerlaw_graph(41, 4000, phases=4, dmax=60)
+    d = check_graph(p.n, p.row_ptr, p.col_idx, 1, "power-law 4000")
+    assert d.max_hood > 64  # LARGE packets
+    q = synth.powerlaw_graph(17, 1500, phases=3, dmax=30)
+    check_graph(q.n, q.row_ptr, q.col_idx, 2, "power-law 1500 k=2")
+
+
+def test_large_slice_workload():
+    g = synth.workload_large()
+    d = pmrf.pmrf_build_neighborhoods_device(g.n, g.row_ptr, g.col_idx)
+    h = pmrf.pmrf_build_neighborhoods(g.n, g.row_ptr, g.col_idx)
+    assert (d.H, d.M, d.A, d.max_hood, d.tiles) == (h.H, h.M, h.A, h.max_hood, h.tiles)
+    a, b = layout_bytes(d), layout_bytes(h)
+    assert np.array_equal(a, b)
+    ex, eh = d.export(), h.export()
+    for key in ex:
+        assert np.array_equal(ex[key], eh[key]), key
+    # owners and a sample of neighbourhoods against the oracle
+    og = oracle.OracleGraph(g.n, g.row_ptr, g.col_idx)
+    ohp, ohv = og.hoods()
+    assert np.array_equal(ex["owner"], og.owner())
+    assert np.array_equal(ex["hood_ptr"], ohp) and np.array_equal(ex["hood_vid"], ohv)
+
+
+def test_em_on_device_built_neighbourhoods():
+    g = synth.workload_small()
+    L, beta, iters = 2, 0.5, 8
+    x0, mu0, s0 = init_state(g, L)
+    hoods = pmrf.pmrf_build_neighborhoods_device(g.n, g.row_ptr, g.col_idx)
+    prob = pmrf.Problem(g.n, g.row_ptr, g.col_idx, g.y, L, "cuda", hoods=hoods)
+    params = pmrf.pmrf_em_params(L=L, beta=beta, max_iters=iters)
+    prob.set_state(x0, mu0, s0)
+    prob.run(params)
+    got = prob.results(params)
+    ref = oracle.OracleGraph(g.n, g.row_ptr, g.col_idx).em_run(g.y, L, beta, x0, mu0, s0, iters)
+    compare_runs(got, ref, "EM on device-built neighbourhoods", check_labels=ref["total_near_ties"] == 0)
+
+
+def test_device_checks_the_csr():
+    def code(n, rp, ci, k=1):
+        with pytest.raises(pmrf.PmrfError) as e:
+            pmrf.pmrf_build_neighborhoods_device(n, rp, ci, k)
+        return e.value.code
+
+    rp, ci = pins.csr(4, [(0, 1), (1, 2), (2, 3)])
+    assert code(4, rp, ci, 0) == pmrf.PMRF_EINVAL
+    assert code(4, rp, ci, 9) == pmrf.PMRF_EUNSUPPORTED
+    bad = rp.copy()
+    bad[0] = 1
+    assert code(4, bad, ci) == pmrf.PMRF_EINVAL  # row_ptr[0] != 0
+    bad = rp.copy()
+    bad[2] = bad[3] + 1
+    assert code(4, bad, np.concatenate([ci, ci])) == pmrf.PMRF_EINVAL  # decreasing row_ptr
+    assert code(4, rp, np.where(ci == 3, 7, ci)) == pmrf.PMRF_EINVAL  # id out of range
+    assert code(4, rp, np.where(ci == 2, 1, ci)) == pmrf.PMRF_EINVAL  # self loop at 1
+    swapped = ci.copy()
+    swapped[rp[1]], swapped[rp[1] + 1] = swapped[rp[1] + 1], swapped[rp[1]]
+    assert code(4, rp, swapped) == pmrf.PMRF_EINVAL  # row 1 not ascending
+    one_way_rp = np.array([0, 1, 1], np.int32)
+    assert code(2, one_way_rp, np.array([1], np.int32)) == pmrf.PMRF_EINVAL  # missing reverse edge
+    hub_rp, hub_ci = pins.csr(1100, [(0, j) for j in range(1, 1100)])
+    assert code(1100, hub_rp, hub_ci) == pmrf.PMRF_EUNSUPPORTED  # a neighbourhood of 1100 members
