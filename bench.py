@@ -199,7 +199,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true",
                     help="default workload only: skip the 64-slice batched-vs-plain leg")
     ap.add_argument("--workload", default="slice2048_100k",
-                    choices=["slice2048_100k", "batch64", "powerlaw16", "serving", "image2048", "volume256"],
+                    choices=["slice2048_100k", "batch64", "powerlaw16", "serving", "image2048", "volume256",
+                             "build"],
                     help="default: the single 100k-region slice, followed by the 64-slice batched leg; "
                          "the others print their own JSON line")
     ap.add_argument("--requests", type=int, default=128, help="serving: number of requests")
@@ -249,6 +250,8 @@ def main():
         return bench_serving(args, dev)
     if args.workload in ("image2048", "volume256"):
         return bench_image(args, dev)
+    if args.workload == "build":
+        return bench_build(args, dev)
     result = bench_slice(args, dev, g)
     if graphs is not None:
         leg = batched_leg(args, dev, "batch64", graphs)
@@ -569,6 +572,54 @@ def bench_image(args, dev):
         result["parity"] = {"graph_equal": bool(np.array_equal(row_ptr.cpu().numpy(), ref_ptr)
                                                 and np.array_equal(col_idx.cpu().numpy(), ref_col)),
                             "means_equal": bool(np.array_equal(means.cpu().numpy(), ref_means))}
+    print(json.dumps(result), flush=True)
+
+
+def bench_build(args, dev):
+    """Neighbourhood construction (maximal cliques, 1-neighbourhoods, owners,
+    packed device layout) on the device against the host builder, for the
+    100k-region slice and one 500k-vertex power-law graph; the device build
+    starts from the CSR resident in device memory and ends with the layout
+    there, the host build from the CSR in host memory."""
+    import numpy as np
+    import torch
+
+    from paper_1809_05018_amd import pmrf, synth
+
+    log("generating the 100k-region slice and a 500k-vertex power-law graph")
+    graphs = {"slice2048_100k": synth.workload_large(), "powerlaw_500k": synth.powerlaw_graph(4, 500_000)}
+    steps = max(1, args.steps)
+    rows = {}
+    for name, g in graphs.items():
+        rp = torch.from_numpy(np.asarray(g.row_ptr, np.int32)).to(dev)
+        ci = torch.from_numpy(np.asarray(g.col_idx, np.int32)).to(dev)
+        for _ in range(max(1, args.warmup)):
+            d = pmrf.pmrf_build_neighborhoods_device(g.n, rp, ci)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            d = pmrf.pmrf_build_neighborhoods_device(g.n, rp, ci)
+        dev_s = (time.perf_counter() - t0) / steps
+        host_runs = max(1, min(3, steps))
+        t0 = time.perf_counter()
+        for _ in range(host_runs):
+            h = pmrf.pmrf_build_neighborhoods(g.n, g.row_ptr, g.col_idx)
+        host_s = (time.perf_counter() - t0) / host_runs
+        a, b = d.upload(dev), h.upload(dev)
+        same = (d.device_bytes == h.device_bytes and bool(torch.equal(a[: h.device_bytes], b[: h.device_bytes])))
+        rows[name] = {"n": g.n, "nnz": int(g.row_ptr[-1]), "H": d.H, "M": d.M, "max_hood": d.max_hood,
+                      "device_ms": dev_s * 1e3, "host_ms": host_s * 1e3, "host_over_device": host_s / dev_s,
+                      "layout_equal_to_host_builder": same}
+        log(f"{name}: device {dev_s * 1e3:.2f} ms, host {host_s * 1e3:.1f} ms, layout equal {same}")
+    first = rows["slice2048_100k"]
+    result = {"metric": "neighbourhood construction time (device builder)", "value": first["device_ms"],
+              "unit": "ms", "n_gpus": 1, "steps": steps, "warmup": args.warmup, "ms_per_step": first["device_ms"],
+              "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+              "data": "synthetic", "config": {"workload": "build", "graphs": list(rows)}, "graphs": rows,
+              "roofline": None,
+              "roofline_note": "a chain of short passes with host waits between them (level counts, sizes): "
+                               "latency bound, not bandwidth bound",
+              "cpu_baseline": None}
     print(json.dumps(result), flush=True)
 
 
