@@ -666,9 +666,14 @@ def bench_serving(args, dev):
                       "iters_per_step": 10, "arrival_rate_rps": lam, "hbm_budget_bytes": budget},
            "p50_s": st.p50_s, "p99_s": st.p99_s, "mean_s": st.mean_s, "throughput_rps": st.throughput_rps,
            "capacity_rps": cap.throughput_rps, "max_active": st.max_active, "steps": st.steps,
-           "host_build_s_mean": st.build_s_mean, "wall_s": st.wall_s,
+           "builder": "device", "build_s_mean": st.build_s_mean, "wall_s": st.wall_s,
            "launches": dict(launches, note="batched calls during the timed run: HIP graphs captured, replayed, and "
                                          "calls launched directly (an argument set seen once runs directly)")}
+    # the same arrivals with the neighbourhoods built on the host
+    hst = serve.Server(serve.GpuExecutor(dev, builder="host"), budget, iters_per_step=10).run(make(arr))
+    log(f"host builder at the same rate: p50 {hst.p50_s:.3f} s, p99 {hst.p99_s:.3f} s, build {hst.build_s_mean:.3f} s")
+    out["host_builder_same_arrivals"] = {"p50_s": hst.p50_s, "p99_s": hst.p99_s, "mean_s": hst.mean_s,
+                                         "throughput_rps": hst.throughput_rps, "build_s_mean": hst.build_s_mean}
     print(json.dumps(out), flush=True)
 
 

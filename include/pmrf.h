@@ -110,6 +110,15 @@ pmrf_status pmrf_build_neighborhoods(int32_t n, const int32_t *row_ptr, const in
 pmrf_status pmrf_build_neighborhoods_device(int32_t n, const int32_t *d_row_ptr, const int32_t *d_col_idx, int32_t k,
                                             void *hip_stream, pmrf_hoods **out);
 
+/* Device memory held by a structure from pmrf_build_neighborhoods_device:
+ * *d_layout = its own copy of the layout (info.device_bytes bytes, on the
+ * device it was built on, 256-byte aligned), which may be passed wherever an
+ * uploaded buffer is expected (d_hoodbuf) while the object lives;
+ * *held_bytes = all device memory the object holds (layout and canonical
+ * arrays).  A host-built structure gives NULL and 0.  Either output may be
+ * NULL.  Errors: PMRF_EINVAL (hoods NULL). */
+pmrf_status pmrf_hoods_device_buffer(const pmrf_hoods *hoods, void **d_layout, int64_t *held_bytes);
+
 pmrf_status pmrf_hoods_get_info(const pmrf_hoods *hoods, pmrf_hoods_info *info);
 
 /* Host copies of the canonical structure (for inspection and tests):

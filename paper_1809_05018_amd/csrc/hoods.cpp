@@ -466,6 +466,15 @@ extern "C" pmrf_status pmrf_hoods_export(const pmrf_hoods *h, int64_t *hood_ptr,
   return PMRF_OK;
 }
 
+extern "C" pmrf_status pmrf_hoods_device_buffer(const pmrf_hoods *h, void **d_layout, int64_t *held_bytes) {
+  clear_error();
+  if (!h) return fail(PMRF_EINVAL, "hoods is NULL");
+  if (d_layout) *d_layout = h->on_device ? h->dev_layout : nullptr;
+  if (held_bytes)
+    *held_bytes = h->on_device ? h->layout.total + 4 * (2 * (h->H + 1) + h->dev_clique_total + h->M + h->n) : 0;
+  return PMRF_OK;
+}
+
 extern "C" pmrf_status pmrf_hoods_upload(const pmrf_hoods *h, void *d_buf, int64_t bytes, void *stream) {
   clear_error();
   if (!h || !d_buf) return fail(PMRF_EINVAL, "NULL argument");

@@ -38,7 +38,7 @@ EXPORTED = (
     "pmrf_em_batch_workspace_bytes", "pmrf_em_batch", "pmrf_set_launch", "pmrf_get_launch",
     "pmrf_profile_begin", "pmrf_profile_end", "pmrf_image_graph_workspace_bytes", "pmrf_image_graph",
     "pmrf_labels_to_pixels", "pmrf_confusion", "pmrf_volume_graph_workspace_bytes", "pmrf_volume_graph",
-    "pmrf_launch_stats", "pmrf_em_run_noalloc", "pmrf_build_neighborhoods_device",
+    "pmrf_launch_stats", "pmrf_em_run_noalloc", "pmrf_build_neighborhoods_device", "pmrf_hoods_device_buffer",
 )
 
 
@@ -83,6 +83,7 @@ def _load():
     lib.pmrf_abi_version.restype = c_int32
     lib.pmrf_build_neighborhoods.argtypes = [c_int32, P(c_int32), P(c_int32), c_int32, P(c_void_p)]
     lib.pmrf_build_neighborhoods_device.argtypes = [c_int32, c_void_p, c_void_p, c_int32, c_void_p, P(c_void_p)]
+    lib.pmrf_hoods_device_buffer.argtypes = [c_void_p, P(c_void_p), P(c_int64)]
     lib.pmrf_hoods_get_info.argtypes = [c_void_p, P(HoodsInfo)]
     lib.pmrf_hoods_export.argtypes = [c_void_p, P(c_int64), P(c_int32), P(c_int64), P(c_int32), P(c_int64)]
     lib.pmrf_hoods_upload.argtypes = [c_void_p, c_void_p, c_int64, c_void_p]
@@ -185,6 +186,12 @@ class Hoods:
         hi = np.zeros(max(1, K), np.int32)
         _check(lib.pmrf_replicate_indices(self.handle, int(L), _p(tl, c_int32), _p(oi, c_int64), _p(hi, c_int32)))
         return tl[:K], oi[:K], hi[:K]
+
+    def device_held(self):
+        """(layout pointer, bytes held) of a device-built structure, else (None, 0)."""
+        p, b = c_void_p(), c_int64()
+        _check(lib.pmrf_hoods_device_buffer(self.handle, ctypes.byref(p), ctypes.byref(b)))
+        return p.value, b.value
 
     def upload(self, device=None, stream=None):
         """Device copy of the layout as a uint8 torch tensor."""

@@ -34,6 +34,7 @@ from __future__ import annotations
 
 import concurrent.futures as cf
 import dataclasses
+import threading
 import time
 
 import numpy as np
@@ -69,7 +70,7 @@ class GpuExecutor:
     """Device side of the server: one pmrf.Problem per active request, one
     batch workspace sized exactly for each step."""
 
-    def __init__(self, device="cuda"):
+    def __init__(self, device="cuda", builder="device"):
         import torch
 
         from . import pmrf
@@ -77,10 +78,22 @@ class GpuExecutor:
         self.torch, self.pmrf = torch, pmrf
         self.device = torch.device(device)
         self.ws = None
+        if builder not in ("device", "host"):
+            raise ValueError("builder is 'device' or 'host'")
+        self.builder = builder
+        self._local = threading.local()
 
     def build(self, req: Request):
-        """Host work (thread safe): neighbourhood construction."""
-        return self.pmrf.pmrf_build_neighborhoods(req.n, req.row_ptr, req.col_idx)
+        """Neighbourhood construction (thread safe).  On the device each build
+        thread has a stream of its own, so builds overlap the running steps."""
+        pm, torch = self.pmrf, self.torch
+        if self.builder == "host":
+            return pm.pmrf_build_neighborhoods(req.n, req.row_ptr, req.col_idx)
+        s = getattr(self._local, "stream", None)
+        if s is None:
+            s = self._local.stream = torch.cuda.Stream(self.device)
+        with torch.cuda.stream(s):
+            return pm.pmrf_build_neighborhoods_device(req.n, req.row_ptr, req.col_idx, stream=s)
 
     def open(self, req: Request, hoods):
         pm = self.pmrf
@@ -103,7 +116,7 @@ class GpuExecutor:
             return (nbytes + 511) // 512 * 512
 
         return (t(max(256, hoods.device_bytes)) + t(8 * n1) + t(4 * n1) + 2 * t(8 * req.L) + t(8 * H1)
-                + t(8 * pm.NCOUNTERS) + t(8 * T) + t(16 * T))
+                + t(8 * pm.NCOUNTERS) + t(8 * T) + t(16 * T) + hoods.device_held()[1])
 
     def _params(self, req: Request, k: int, first: bool):
         todo = min(k, req.iters - req.done_iters)

@@ -41,6 +41,8 @@ def check_graph(n, rp, ci, k=1, what=""):
     assert np.array_equal(ex["owner"], og.owner()), what + " owners"
     h = pmrf.pmrf_build_neighborhoods(n, rp, ci, k)
     assert (d.tiles, d.device_bytes) == (h.tiles, h.device_bytes), what
+    ptr, held = d.device_held()
+    assert ptr is not None and ptr % 256 == 0 and held >= d.device_bytes + 4 * (d.M + d.n), what
     a, b = layout_bytes(d), layout_bytes(h)
     diff = np.flatnonzero(a != b)
     assert diff.size == 0, f"{what}: layouts differ at bytes {diff[:8]} of {a.size}"

@@ -73,6 +73,7 @@ def test_builder_k_neighbourhoods_match_oracle():
 def test_builder_edge_cases():
     h = pmrf.pmrf_build_neighborhoods(0, np.zeros(1, np.int32), np.zeros(0, np.int32))
     assert (h.n, h.H, h.M) == (0, 0, 0) and h.device_bytes >= 256
+    assert h.device_held() == (None, 0)  # a host-built structure holds no device memory
     rp, ci = pins.csr(5, [])
     h = compare_with_oracle(5, rp, ci)
     assert h.H == 5 and h.M == 5
