@@ -18,7 +18,8 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "pmrf_oracle.c")
-LIB = os.path.join(HERE, "liboracle.so")
+# ORACLE_LIB names another build of the oracle (an instrumented one, say)
+LIB = os.environ.get("ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 
 _lib = None
 

@@ -16,7 +16,8 @@ from ctypes import POINTER, Structure, c_char_p, c_double, c_int32, c_int64, c_v
 
 import numpy as np
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpmrf.so")
+# PMRF_LIB names another build of the library (an instrumented host build, say)
+LIB_PATH = os.environ.get("PMRF_LIB") or os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpmrf.so")
 
 PMRF_OK = 0
 PMRF_EINVAL = -1
