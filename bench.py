@@ -207,6 +207,9 @@ def main():
     ap.add_argument("--launch", default=None,
                     help="pin the launch shape 'mode,waves_per_block,blocks_per_cu' instead of autotuning "
                          "(for profiles of one shape)")
+    ap.add_argument("--workers", type=int, default=0,
+                    help="processes drawing the batch inputs (0: the cores available, at most 16; 1 draws in "
+                         "this process with a progress line per graph, as profiler runs need)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (scale for the HBM byte counters)")
     args = ap.parse_args()
@@ -220,7 +223,8 @@ def main():
 
     from paper_1809_05018_amd import synth
 
-    workers = max(1, min(16, host_cpu()["cores_available"]))
+    workers = args.workers if args.workers > 0 else max(1, min(16, host_cpu()["cores_available"]))
+    progress = (lambda i, k: log(f"  drew {i}/{k}")) if workers == 1 else None
     # inputs are drawn before the GPU is touched (worker processes are forked)
     graphs = None
     if args.workload == "slice2048_100k":
@@ -228,13 +232,13 @@ def main():
         g = synth.workload_large()
         if not args.no_batch:
             log("generating 64 slices (sides log-uniform in [512, 2560])")
-            graphs = synth.workload_batch(64, 3, workers=workers)
+            graphs = synth.workload_batch(64, 3, workers=workers, progress=progress)
     elif args.workload == "batch64":
         log("generating 64 slices (sides log-uniform in [512, 2560])")
-        graphs = synth.workload_batch(64, 3, workers=workers)
+        graphs = synth.workload_batch(64, 3, workers=workers, progress=progress)
     elif args.workload == "powerlaw16":
         log("generating 16 power-law graphs of 500k vertices")
-        graphs = synth.workload_skewed(16, 500_000, 4, workers=workers)
+        graphs = synth.workload_skewed(16, 500_000, 4, workers=workers, progress=progress)
 
     import torch
 

@@ -223,18 +223,24 @@ def batch_sides(count: int = 64, seed: int = 3, lo: int = 512, hi: int = 2560):
     return [(int(s), int(round(s * s / 26.2))) for s in sides]
 
 
-def _draw_all(fn, args, workers: int):
+def _draw_all(fn, args, workers: int, progress=None):
     """fn(*a) for every a in args, in order; with workers > 1 in forked worker
-    processes (each draw has its own seed, so the result is the same)."""
+    processes (each draw has its own seed, so the result is the same).
+    ``progress(i, count)`` is called after each serial draw."""
     if workers <= 1 or len(args) <= 1:
-        return [fn(*a) for a in args]
+        out = []
+        for i, a in enumerate(args):
+            out.append(fn(*a))
+            if progress:
+                progress(i + 1, len(args))
+        return out
     import multiprocessing as mp
 
     with mp.get_context("fork").Pool(min(workers, len(args))) as pool:
         return pool.starmap(fn, args, chunksize=1)
 
 
-def workload_batch(count: int = 64, seed: int = 3, scale: float = 1.0, workers: int = 1):
+def workload_batch(count: int = 64, seed: int = 3, scale: float = 1.0, workers: int = 1, progress=None):
     """Uneven slices for the batched path (``scale`` shrinks sides for tests).
     ``workers`` > 1 draws the slices in forked processes: call it before the
     process touches a GPU."""
@@ -243,13 +249,13 @@ def workload_batch(count: int = 64, seed: int = 3, scale: float = 1.0, workers: 
         s2 = max(32, int(round(s * scale)))
         r2 = max(16, int(round(s2 * s2 / 26.2)))
         args.append((seed * 1000 + i, s2, r2, 2, f"batch{i}_{s2}"))
-    return _draw_all(image_graph, args, workers)
+    return _draw_all(image_graph, args, workers, progress)
 
 
-def workload_skewed(count: int = 16, n: int = 500_000, seed: int = 4, workers: int = 1):
+def workload_skewed(count: int = 16, n: int = 500_000, seed: int = 4, workers: int = 1, progress=None):
     """Power-law graphs, L=4 phases (``workers`` as for ``workload_batch``)."""
     args = [(seed * 1000 + i, n, 4, 3, 30, 2.5, 20.0, f"powerlaw{i}") for i in range(count)]
-    return _draw_all(powerlaw_graph, args, workers)
+    return _draw_all(powerlaw_graph, args, workers, progress)
 
 
 def serving_requests(count: int = 256, seed: int = 5, rmin: int = 1000, rmax: int = 1_000_000):
