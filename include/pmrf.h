@@ -349,8 +349,9 @@ pmrf_status pmrf_profile_end(double *total_ms, int64_t *launches);
  * pixel values over its pixel count (0 for a region without pixels), *nnz
  * (host) the number of adjacency entries.  d_ws: a device workspace of at
  * least pmrf_image_graph_workspace_bytes(width, height, n) bytes.  The call
- * waits for the stream twice (the sort sizes come back to the host) and
- * returns with the outputs enqueued.  Errors: PMRF_EINVAL (NULL or negative
+ * waits for the stream once (the entry count and the id check come back to the
+ * host; every intermediate size stays on the device) and returns with the
+ * outputs enqueued.  Errors: PMRF_EINVAL (NULL or negative
  * argument, a region id outside [0, n): nothing written), PMRF_ENOMEM
  * (workspace too small; col_capacity below the entry count, which is then in
  * *nnz: nothing else written), PMRF_EUNSUPPORTED (more than 2^28 pixels),

@@ -38,6 +38,7 @@
 #include <vector>
 
 #include "pmrf_internal.h"
+#include "prims.h"
 
 using namespace pmrf;
 
@@ -102,163 +103,10 @@ int64_t blocks_for(int64_t items, int64_t per_block, int64_t cap = 1 << 20) {
   return std::max<int64_t>(1, std::min<int64_t>(cap, (items + per_block - 1) / per_block));
 }
 
-// ------------------------------------------------------------ wave and block
+using pmrf_prims::block_excl_scan;
+using pmrf_prims::shfl_down64;
+
 __device__ __forceinline__ int64_t imin64(int64_t a, int64_t b) { return a < b ? a : b; }
-__device__ __forceinline__ int32_t shfl_up(int32_t v, int d) { return __shfl_up(v, d, 64); }
-__device__ __forceinline__ int64_t shfl_down64(int64_t v, int d) {
-  const uint32_t lo = (uint32_t)__shfl_down((int32_t)(uint32_t)v, d, 64);
-  const uint32_t hi = (uint32_t)__shfl_down((int32_t)(uint32_t)((uint64_t)v >> 32), d, 64);
-  return (int64_t)(((uint64_t)hi << 32) | lo);
-}
-__device__ __forceinline__ int64_t shfl_up(int64_t v, int d) {
-  const uint32_t lo = (uint32_t)__shfl_up((int32_t)(uint32_t)v, d, 64);
-  const uint32_t hi = (uint32_t)__shfl_up((int32_t)(uint32_t)((uint64_t)v >> 32), d, 64);
-  return (int64_t)(((uint64_t)hi << 32) | lo);
-}
-
-// Exclusive prefix sum over the block (blockDim a multiple of 64, at most
-// 1024); lds holds one value per wave.  Returns the thread's prefix and sets
-// *total.  Ends with a barrier, so lds may be reused at once.
-template <class T>
-__device__ T block_excl_scan(T v, T *lds, T *total) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  T inc = v;
-  for (int d = 1; d < 64; d <<= 1) {
-    const T u = shfl_up(inc, d);
-    if (lane >= d) inc += u;
-  }
-  if (lane == 63) lds[w] = inc;
-  __syncthreads();
-  T off = 0, tot = 0;
-  for (int i = 0; i < nw; ++i) {
-    const T x = lds[i];
-    if (i < w) off += x;
-    tot += x;
-  }
-  __syncthreads();
-  *total = tot;
-  return off + inc - v;
-}
-
-// ------------------------------------------------------------------- scans
-constexpr int kScanPer = 8;
-constexpr int kScanTile = kBT * kScanPer;
-
-template <class T>
-__global__ void __launch_bounds__(kBT) k_scan_reduce(const T *in, int64_t n, T *sums) {
-  __shared__ T lds[kBT / 64];
-  const int64_t base = (int64_t)blockIdx.x * kScanTile;
-  T s = 0;
-  for (int i = 0; i < kScanPer; ++i) {
-    const int64_t k = base + i * kBT + threadIdx.x;
-    if (k < n) s += in[k];
-  }
-  T tot;
-  block_excl_scan(s, lds, &tot);
-  if (threadIdx.x == 0) sums[blockIdx.x] = tot;
-}
-
-// One block: exclusive prefix of the tile sums in place; the grand total goes
-// to sums[nt] and out[n].
-template <class T>
-__global__ void __launch_bounds__(kBT) k_scan_sums(T *sums, int64_t nt, T *out, int64_t n) {
-  __shared__ T lds[kBT / 64];
-  T carry = 0;
-  for (int64_t b = 0; b < nt; b += kBT) {
-    const int64_t k = b + threadIdx.x;
-    const T v = k < nt ? sums[k] : T(0);
-    T tot;
-    const T ex = block_excl_scan(v, lds, &tot);
-    if (k < nt) sums[k] = carry + ex;
-    carry += tot;
-  }
-  if (threadIdx.x == 0) {
-    sums[nt] = carry;
-    out[n] = carry;
-  }
-}
-
-// Each thread takes kScanPer consecutive items (in and out may alias).
-template <class T>
-__global__ void __launch_bounds__(kBT) k_scan_down(const T *in, T *out, int64_t n, const T *sums) {
-  __shared__ T lds[kBT / 64];
-  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
-  T v[kScanPer];
-  T s = 0;
-  for (int i = 0; i < kScanPer; ++i) {
-    v[i] = base + i < n ? in[base + i] : T(0);
-    s += v[i];
-  }
-  T tot;
-  T ex = block_excl_scan(s, lds, &tot) + sums[blockIdx.x];
-  for (int i = 0; i < kScanPer; ++i) {
-    if (base + i < n) out[base + i] = ex;
-    ex += v[i];
-  }
-}
-
-// ------------------------------------------------------------- radix sort
-// Stable LSD sort of (key, value) pairs by key, 8 bits per pass.  Within a
-// tile of 4096 pairs, items are ranked round by round (256 per round, in
-// index order); equal digits inside a wave are found with eight ballots.
-constexpr int kSortPer = 16;
-constexpr int kSortTile = kBT * kSortPer;
-
-__global__ void __launch_bounds__(kBT) k_sort_hist(const uint32_t *keys, int64_t n, int shift, int32_t *hist,
-                                                   int64_t ntiles) {
-  __shared__ int32_t cnt[256];
-  cnt[threadIdx.x] = 0;
-  __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * kSortTile;
-  for (int r = 0; r < kSortPer; ++r) {
-    const int64_t k = base + r * kBT + threadIdx.x;
-    if (k < n) atomicAdd(&cnt[(keys[k] >> shift) & 255u], 1);
-  }
-  __syncthreads();
-  hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = cnt[threadIdx.x];
-}
-
-__global__ void __launch_bounds__(kBT) k_sort_scatter(const uint32_t *kin, const int32_t *vin, uint32_t *kout,
-                                                      int32_t *vout, int64_t n, int shift, const int32_t *offs,
-                                                      int64_t ntiles) {
-  __shared__ int32_t base[256];
-  __shared__ int32_t wc[kBT / 64][256];
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  base[t] = offs[(int64_t)t * ntiles + blockIdx.x];
-  for (int i = 0; i < kBT / 64; ++i) wc[i][t] = 0;
-  __syncthreads();
-  const uint64_t below = (uint64_t(1) << lane) - 1;
-  for (int r = 0; r < kSortPer; ++r) {
-    const int64_t k = (int64_t)blockIdx.x * kSortTile + r * kBT + t;
-    const bool ok = k < n;
-    const uint32_t key = ok ? kin[k] : 0u;
-    const int32_t val = ok ? vin[k] : 0;
-    const int d = (int)((key >> shift) & 255u);
-    uint64_t m = __ballot(ok);
-    for (int b = 0; b < 8; ++b) {
-      const bool bit = (d >> b) & 1;
-      const uint64_t bb = __ballot(bit);
-      m &= bit ? bb : ~bb;
-    }
-    const int rank = __popcll(m & below);
-    if (ok && rank == 0) wc[w][d] = __popcll(m);
-    __syncthreads();
-    if (ok) {
-      int32_t pos = base[d] + rank;
-      for (int i = 0; i < w; ++i) pos += wc[i][d];
-      kout[pos] = key;
-      vout[pos] = val;
-    }
-    __syncthreads();
-    int32_t add = 0;
-    for (int i = 0; i < kBT / 64; ++i) {
-      add += wc[i][t];
-      wc[i][t] = 0;
-    }
-    base[t] += add;
-    __syncthreads();
-  }
-}
 
 // ---------------------------------------------------------- small kernels
 __global__ void k_iota(int32_t *a, int64_t n) {
@@ -777,11 +625,8 @@ struct Builder {
   // be out)
   template <class T>
   void scan(const T *in, T *out, int64_t n) {
-    const int64_t nt = (n + kScanTile - 1) / kScanTile;
-    Buf<T> sums(nt + 1);
-    if (nt) k_scan_reduce<T><<<nt, kBT, 0, s>>>(in, n, sums.p);
-    k_scan_sums<T><<<1, kBT, 0, s>>>(sums.p, nt, out, n);
-    if (nt) k_scan_down<T><<<nt, kBT, 0, s>>>(in, out, n, sums.p);
+    Buf<T> sums(pmrf_prims::scan_scratch(n));
+    pmrf_prims::scan<T>(s, in, out, n, nullptr, sums.p);
     check();
     sync();  // sums is released on return
   }
@@ -797,24 +642,15 @@ struct Builder {
   // stable sort of (keys, vals) by the low `bits` bits of the keys, in place
   void sort_pairs(uint32_t *keys, int32_t *vals, int64_t n, int bits) {
     if (n <= 1) return;
-    const int64_t ntiles = (n + kSortTile - 1) / kSortTile;
     Buf<uint32_t> k2(n);
-    Buf<int32_t> v2(n), hist(256 * ntiles + 1);
-    uint32_t *ka = keys, *kb = k2.p;
-    int32_t *va = vals, *vb = v2.p;
-    int passes = 0;
-    for (int shift = 0; shift < bits; shift += 8, ++passes) {
-      k_sort_hist<<<ntiles, kBT, 0, s>>>(ka, n, shift, hist.p, ntiles);
-      check();
-      scan(hist.p, hist.p, 256 * ntiles);
-      k_sort_scatter<<<ntiles, kBT, 0, s>>>(ka, va, kb, vb, n, shift, hist.p, ntiles);
-      check();
-      std::swap(ka, kb);
-      std::swap(va, vb);
-    }
-    if (passes & 1) {
-      copy(keys, ka, n);
-      copy(vals, va, n);
+    Buf<int32_t> v2(n), hist(pmrf_prims::sort_hist_entries(n)),
+        hsums(pmrf_prims::scan_scratch(256 * pmrf_prims::sort_tiles(n)));
+    const bool other = pmrf_prims::sort_pairs<uint32_t, true>(s, keys, vals, k2.p, v2.p, n, nullptr, bits, hist.p,
+                                                                hsums.p);
+    check();
+    if (other) {
+      copy(keys, k2.p, n);
+      copy(vals, v2.p, n);
     }
     sync();
   }
