@@ -561,7 +561,7 @@ def bench_image(args, dev):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "whole graph call",
                      "alg_bytes_per_launch": b_alg,
-                     "note": "wall time of the whole step, which waits for the host twice (sort sizes)"},
+                     "note": "wall time of the whole step, which waits for the host once (entry count, id check)"},
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:
