@@ -240,8 +240,8 @@ bool sort_pairs(hipStream_t s, K *keys, int32_t *vals, K *k2, int32_t *v2, int64
 // grid of G blocks, block b taking the contiguous items [b * chunk, (b + 1) *
 // chunk) with chunk = ceil(count / G), so the histogram holds 256 x G entries
 // whatever the bound.
-constexpr int kFixedBlocks = 256;
-static_assert(kFixedBlocks == kBT, "a histogram row is scanned by one block of kBT threads");
+constexpr int kFixedBlocks = 1024;
+static_assert(kFixedBlocks == 4 * kBT, "a histogram row is scanned by one block, four entries a thread");
 
 __device__ __forceinline__ void fixed_range(int64_t nb, const int64_t *dn, int64_t &lo, int64_t &hi) {
   const int64_t n = item_count(nb, dn);
@@ -264,13 +264,15 @@ __global__ void __launch_bounds__(kBT) k_fsort_hist(const K *keys, int64_t nb, c
 }
 
 // Row d of the histogram (the G blocks' counts of digit d) to its exclusive
-// prefix sums, the row total to tot[d]; one block per digit.
+// prefix sums, the row total to tot[d]; one block per digit, thread t holding
+// entries 4 t .. 4 t + 3.
 __global__ void __launch_bounds__(kBT) k_fsort_rows(int32_t *hist, int32_t *tot) {
   __shared__ int32_t lds[kBT / 64];
-  int32_t *row = hist + (int64_t)blockIdx.x * kFixedBlocks;
-  const int32_t v = row[threadIdx.x];
+  int4 *row = reinterpret_cast<int4 *>(hist + (int64_t)blockIdx.x * kFixedBlocks);
+  const int4 v = row[threadIdx.x];
   int32_t total;
-  row[threadIdx.x] = block_excl_scan(v, lds, &total);
+  const int32_t ex = block_excl_scan(v.x + v.y + v.z + v.w, lds, &total);
+  row[threadIdx.x] = make_int4(ex, ex + v.x, ex + v.x + v.y, ex + v.x + v.y + v.z);
   if (threadIdx.x == 0) tot[blockIdx.x] = total;
 }
 
