@@ -1278,11 +1278,8 @@ __global__ void k_write_desc(DescPack pack, GraphDev *dst) {
   if (i < pack.count) dst[pack.first + i] = pack.d[i];
 }
 
-// Set up the state of every graph from the caller's starting parameters.
-__global__ void k_setup(const GraphDev *graphs, int B) {
-  int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= B) return;
-  const GraphDev &G = graphs[g];
+// The run state of one graph from the caller's starting parameters.
+__device__ void setup_graph(const GraphDev &G) {
   GraphState *st = G.st;
   st->done = 0;
   st->stop[0] = 0;
@@ -1309,11 +1306,9 @@ __global__ void k_setup(const GraphDev *graphs, int B) {
 }
 
 // The workspace vertex records from the caller's intensities and starting
-// labels (label buffer 0), once per run.
-__global__ void k_vr_init(const GraphDev *graphs, int B) {
-  const GraphDev &G = graphs[find_graph(graphs, B, blockIdx.x, kGridVertex)];
-  const int b = blockIdx.x - G.vblock0;
-  const int stride = G.vnblocks * blockDim.x;
+// labels (label buffer 0): block b of the graph's nb vertex blocks.
+__device__ void vr_init_part(const GraphDev &G, int b, int nb) {
+  const int stride = nb * blockDim.x;
   for (int v = b * blockDim.x + threadIdx.x; v < G.n; v += stride) {
     VertexRec r;
     r.y = G.y[v];
@@ -1321,6 +1316,29 @@ __global__ void k_vr_init(const GraphDev *graphs, int B) {
     r.x[1] = 0;
     G.vr[v] = r;
   }
+}
+
+// Set up the state of every graph from the caller's starting parameters.
+__global__ void k_setup(const GraphDev *graphs, int B) {
+  int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= B) return;
+  setup_graph(graphs[g]);
+}
+
+// The vertex records of every graph, once per run.
+__global__ void k_vr_init(const GraphDev *graphs, int B) {
+  const GraphDev &G = graphs[find_graph(graphs, B, blockIdx.x, kGridVertex)];
+  vr_init_part(G, blockIdx.x - G.vblock0, G.vnblocks);
+}
+
+// A single graph's start in one launch: its descriptor (a kernel argument)
+// to device memory for the later kernels, its run state, its vertex records.
+__global__ void k_start1(const GraphDev g1, GraphDev *dst) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *dst = g1;
+    setup_graph(g1);
+  }
+  vr_init_part(g1, blockIdx.x, gridDim.x);
 }
 
 // Graph of every slot-kernel block, written once per run (batches only):
@@ -2221,19 +2239,24 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
   // Everything the run enqueues; descriptors travel as kernel arguments, so no
   // host buffer must outlive the call and the sequence can be captured.
   auto enqueue = [&](hipStream_t s) -> pmrf_status {
-    for (int first = 0; first < B; first += kDescPerPack) {
-      DescPack pack{};
-      pack.first = first;
-      pack.count = std::min(kDescPerPack, B - first);
-      for (int k = 0; k < pack.count; ++k) pack.d[k] = desc[first + k];
-      hipLaunchKernelGGL(k_write_desc, dim3(1), dim3(64), 0, s, pack, d_desc);
+    const GraphDev *gd = d_desc;
+    if (B == 1) {
+      hipLaunchKernelGGL(k_start1, dim3(blocks_vert), dim3(256), 0, s, desc[0], d_desc);
+      HIP_TRY(hipGetLastError());
+    } else {
+      for (int first = 0; first < B; first += kDescPerPack) {
+        DescPack pack{};
+        pack.first = first;
+        pack.count = std::min(kDescPerPack, B - first);
+        for (int k = 0; k < pack.count; ++k) pack.d[k] = desc[first + k];
+        hipLaunchKernelGGL(k_write_desc, dim3(1), dim3(64), 0, s, pack, d_desc);
+        HIP_TRY(hipGetLastError());
+      }
+      hipLaunchKernelGGL(k_setup, dim3((B + 63) / 64), dim3(64), 0, s, gd, B);
+      HIP_TRY(hipGetLastError());
+      hipLaunchKernelGGL(k_vr_init, dim3(blocks_vert), dim3(256), 0, s, gd, B);
       HIP_TRY(hipGetLastError());
     }
-    const GraphDev *gd = d_desc;
-    hipLaunchKernelGGL(k_setup, dim3((B + 63) / 64), dim3(64), 0, s, gd, B);
-    HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_vr_init, dim3(blocks_vert), dim3(256), 0, s, gd, B);
-    HIP_TRY(hipGetLastError());
     if (B > 1 && blocks_iter > 0) {
       hipLaunchKernelGGL(k_block_graph, dim3(B), dim3(256), 0, s, gd, block_graph);
       HIP_TRY(hipGetLastError());
