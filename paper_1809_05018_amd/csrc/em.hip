@@ -1912,6 +1912,44 @@ __global__ void k_final(const GraphDev *graphs, int B) {
   }
 }
 
+// A fused single-graph run of T >= 1 iterations ends in one launch: block 0
+// folds the records of iteration T - 1 and then writes the parameters and
+// counters; every block copies its share of the labels and neighbourhood
+// sums.  Which label buffer is final follows from the stop flag the last
+// iteration launch wrote (it cannot change in this launch): set, the run had
+// stopped before iteration T - 1 and its iteration count is already in the
+// state; clear, iteration T - 1 ran, so T iterations did.
+__global__ __launch_bounds__(kFoldThreads) void k_finish1(const GraphDev g1, int T) {
+  __shared__ FoldLds sh;
+  const GraphDev &G = g1;
+  GraphState *st = G.st;
+  const int iters = st->stop[(T - 1) & 1] ? st->iters : T;
+  const int stride = gridDim.x * blockDim.x;
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < G.n; v += stride) G.x0[v] = G.vr[v].x[iters & 1];
+  if (G.out_S && iters > 0) {
+    const double *src = G.ring + (size_t)((iters - 1) % (G.W + 1)) * G.H;
+    for (int h = blockIdx.x * blockDim.x + threadIdx.x; h < G.H; h += stride) G.out_S[G.perm[h]] = src[h];
+  }
+  if (blockIdx.x != 0) return;
+  fold_iteration(G, T, sh, blockDim.x >> 6, wave_id(), threadIdx.x & 63);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int l = 0; l < G.L; ++l) {
+      G.out_mu[l] = st->th[iters & 1][l].mu;
+      G.out_sigma[l] = st->th[iters & 1][l].sigma;
+    }
+    int64_t *c = G.out_ctr;
+    c[PMRF_CTR_STATUS] = st->status;
+    c[PMRF_CTR_ITERS] = iters;
+    c[PMRF_CTR_MAP_CONV] = st->map_conv;
+    c[PMRF_CTR_EM_CONV] = st->em_conv;
+    c[PMRF_CTR_NEAR_TIES] = st->ties_total;
+    c[PMRF_CTR_EVALS] = G.M * (int64_t)G.L * (int64_t)iters;
+    c[6] = 0;
+    c[7] = 0;
+  }
+}
+
 // ------------------------------------------------------------------- host side
 std::mutex g_launch_mu;
 pmrf_launch g_launch{0, 0, 0, 0};
@@ -2220,6 +2258,8 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
   const bool fused = B == 1 && blocks_pk == 0 && !persist && lm <= kFusedMaxLabels && !any_rule &&
                      desc[0].nsuper <= kFoldLanes && desc[0].nslot == desc[0].nsuper && desc[0].nchunks >= 1 &&
                      shape.waves_per_block >= kFoldLanes / 64;
+  // a fused run ends with the last fold and the result copies in one launch
+  const bool fused_finish = fused && max_iters >= 1;
   // dynamic LDS of the slot kernel: the staged range, then the waves' regions
   // (which hold the fused fold's partials before any chunk is computed); of
   // the packet kernel: the waves' regions
@@ -2371,7 +2411,7 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
       }
       // the parameter update of iteration t: here, or (fused) inside the next
       // iteration launch and after the last one
-      if (!fused || t + 1 == max_iters) {
+      if (!fused || (t + 1 == max_iters && !fused_finish)) {
         if (B == 1)
           hipLaunchKernelGGL((k_fold<true>), dim3(B), dim3(kFoldThreads), 0, s, gd, desc[0], B, t + 1);
         else
@@ -2379,7 +2419,10 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
         HIP_TRY(hipGetLastError());
       }
     }
-    hipLaunchKernelGGL(k_final, dim3(blocks_vert), dim3(256), 0, s, gd, B);
+    if (fused_finish)
+      hipLaunchKernelGGL(k_finish1, dim3(blocks_vert), dim3(kFoldThreads), 0, s, desc[0], max_iters);
+    else
+      hipLaunchKernelGGL(k_final, dim3(blocks_vert), dim3(256), 0, s, gd, B);
     HIP_TRY(hipGetLastError());
     return PMRF_OK;
   };
