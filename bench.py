@@ -282,15 +282,12 @@ def bench_slice(args, dev, g):
     prob.set_state(x0, np.zeros(L), np.ones(L))
     prob.run(pmrf.pmrf_em_params(L=L, beta=beta, max_iters=0, init_from_labels=True))
     torch.cuda.synchronize()
-    x0_dev = prob.labels.clone()
-    mu0, s0 = prob.mu.clone(), prob.sigma.clone()
+    state0 = prob.state.clone()  # starting labels and parameters
     params = pmrf.pmrf_em_params(L=L, beta=beta, max_iters=iters)
     prob.prepare(params)
 
     def step():
-        prob.labels.copy_(x0_dev)
-        prob.mu.copy_(mu0)
-        prob.sigma.copy_(s0)
+        prob.state.copy_(state0)
         prob.run(params)
 
     for _ in range(args.warmup):

@@ -401,9 +401,16 @@ class Problem:
         self.hoodbuf = self.hoods.upload(self.device)
         self.y = torch.zeros(max(1, self.n), dtype=torch.float64, device=self.device)
         self.y[: self.n].copy_(torch.as_tensor(np.ascontiguousarray(y, dtype=np.float64)))
-        self.labels = torch.zeros(max(1, self.n), dtype=torch.int32, device=self.device)
-        self.mu = torch.zeros(self.L, dtype=torch.float64, device=self.device)
-        self.sigma = torch.ones(self.L, dtype=torch.float64, device=self.device)
+        # labels, mu and sigma are views of one buffer (`state`), so a caller
+        # can save and restore the whole starting state with one copy
+        n1 = max(1, self.n)
+        off_mu = (4 * n1 + 255) // 256 * 256
+        off_sg = off_mu + (8 * self.L + 255) // 256 * 256
+        self.state = torch.zeros(off_sg + 8 * self.L, dtype=torch.uint8, device=self.device)
+        self.labels = self.state[: 4 * n1].view(torch.int32)
+        self.mu = self.state[off_mu: off_mu + 8 * self.L].view(torch.float64)
+        self.sigma = self.state[off_sg: off_sg + 8 * self.L].view(torch.float64)
+        self.sigma.fill_(1.0)
         self.hood_energy = torch.zeros(max(1, self.hoods.H), dtype=torch.float64, device=self.device)
         self.counters = torch.zeros(NCOUNTERS, dtype=torch.int64, device=self.device)
         self.trace = None
