@@ -142,7 +142,7 @@ __device__ __forceinline__ uint32_t set_slot(uint64_t key) {
 
 // ids of pixels [p, p + kTileSeg) of one row, cnt of them valid (-1 past cnt)
 __device__ __forceinline__ void load_ids(const int32_t *__restrict__ reg, int64_t p, int cnt, int32_t *id) {
-  if (cnt == kTileSeg && (p & 3) == 0) {
+  if (cnt == kTileSeg && ((uintptr_t)(reg + p) & 15) == 0) {
     const int4 a = *reinterpret_cast<const int4 *>(reg + p), b = *reinterpret_cast<const int4 *>(reg + p + 4);
     id[0] = a.x, id[1] = a.y, id[2] = a.z, id[3] = a.w, id[4] = b.x, id[5] = b.y, id[6] = b.z, id[7] = b.w;
   } else {
@@ -313,8 +313,11 @@ __global__ __launch_bounds__(kImgThreads) void k_sort_back(const int32_t *__rest
 // each run of equal ids once.  When the valid ids of the tile span fewer than
 // kTileTable values (neighbouring regions have neighbouring ids in the usual
 // oversegmentations) the runs are added in an LDS table indexed by id -
-// (smallest id) and each non-empty entry goes to memory with one atomic;
-// otherwise every run does.  Integer sums, so the totals do not depend on the
+// (smallest id), count and sum packed in one 64-bit word (a tile has at most
+// kTileRows * kTileCols pixels, so both fit in 32 bits: one LDS atomic per
+// run), and each non-empty entry goes to memory with one atomic per array;
+// otherwise every run does.  A block's LDS (16 KB) leaves room for eight
+// blocks per compute unit.  Integer sums, so the totals do not depend on the
 // order.  Ids outside [0, n) are skipped (the pair pass counts them).
 constexpr int kTileTable = 2048;
 
@@ -323,8 +326,8 @@ __global__ __launch_bounds__(kImgThreads) void k_region_sums(const int32_t *__re
                                                               int32_t rows, int32_t n,
                                                               unsigned long long *__restrict__ sums,
                                                               unsigned long long *__restrict__ counts) {
-  __shared__ unsigned long long tsum[kTileTable];
-  __shared__ unsigned int tcnt[kTileTable];
+  static_assert((uint64_t)kTileRows * kTileCols * 255 < (1ull << 32), "a tile's sum fits in 32 bits");
+  __shared__ unsigned long long tab[kTileTable];  // (count << 32) | sum
   __shared__ int id_lo, id_hi;
   const int64_t tiles_x = (width + kTileCols - 1) / kTileCols;
   const int64_t R = (int64_t)(blockIdx.x / tiles_x) * kTileRows + threadIdx.x / 16;
@@ -337,7 +340,7 @@ __global__ __launch_bounds__(kImgThreads) void k_region_sums(const int32_t *__re
   }
   int32_t id[kTileSeg];
   uint32_t px[kTileSeg];
-  if (cnt == kTileSeg && (p0 & 7) == 0) {
+  if (cnt == kTileSeg && ((uintptr_t)(reg + p0) & 15) == 0 && ((uintptr_t)(pix + p0) & 7) == 0) {
     const int4 a = *reinterpret_cast<const int4 *>(reg + p0), b = *reinterpret_cast<const int4 *>(reg + p0 + 4);
     const uint2 q = *reinterpret_cast<const uint2 *>(pix + p0);
     id[0] = a.x, id[1] = a.y, id[2] = a.z, id[3] = a.w, id[4] = b.x, id[5] = b.y, id[6] = b.z, id[7] = b.w;
@@ -373,10 +376,7 @@ __global__ __launch_bounds__(kImgThreads) void k_region_sums(const int32_t *__re
   const int base = id_lo, span = id_hi - base + 1;
   const bool table = id_hi >= 0 && span <= kTileTable;  // the same for every thread
   if (table) {
-    for (int i = threadIdx.x; i < span; i += blockDim.x) {
-      tsum[i] = 0;
-      tcnt[i] = 0;
-    }
+    for (int i = threadIdx.x; i < span; i += blockDim.x) tab[i] = 0;
   }
   __syncthreads();
   int32_t cur = -1;
@@ -385,8 +385,7 @@ __global__ __launch_bounds__(kImgThreads) void k_region_sums(const int32_t *__re
   auto flush = [&]() {
     if (k && cur >= 0 && cur < n) {
       if (table) {
-        atomicAdd(&tsum[cur - base], sm);
-        atomicAdd(&tcnt[cur - base], k);
+        atomicAdd(&tab[cur - base], ((unsigned long long)k << 32) | sm);
       } else {
         atomicAdd(&sums[cur], sm);
         atomicAdd(&counts[cur], (unsigned long long)k);
@@ -409,11 +408,13 @@ __global__ __launch_bounds__(kImgThreads) void k_region_sums(const int32_t *__re
   flush();
   if (table) {
     __syncthreads();
-    for (int i = threadIdx.x; i < span; i += blockDim.x)
-      if (tcnt[i]) {
-        atomicAdd(&sums[base + i], tsum[i]);
-        atomicAdd(&counts[base + i], (unsigned long long)tcnt[i]);
+    for (int i = threadIdx.x; i < span; i += blockDim.x) {
+      const unsigned long long e = tab[i];
+      if (e) {
+        atomicAdd(&sums[base + i], e & 0xffffffffull);
+        atomicAdd(&counts[base + i], e >> 32);
       }
+    }
   }
 }
 
@@ -435,21 +436,28 @@ __global__ __launch_bounds__(kImgThreads) void k_paint(const int32_t *__restrict
 }
 
 // Confusion counts: counts[a * k + b] = #pixels with a[p] = a, b[p] = b (both
-// below k <= 16).  Each thread takes kConfPer consecutive pixels (vector loads
-// where aligned).  For k * k <= 16 the thread keeps its counts as 16-bit
-// fields of four 64-bit words (bin j in word j / 4) and the wave adds the
-// words across lanes, so each wave makes one LDS atomic per bin; otherwise
-// each pixel adds to the block's LDS histogram.  Then one integer atomic per
-// bin and block.
-constexpr int kConfPer = 64;
+// below k <= 16).  Each thread takes kConfPer consecutive pixels per round
+// (one 16-byte load of each image where the address allows); a block has
+// kConfThreads threads and there are at most as many blocks as compute units,
+// so the image is read in one round of loads where it fits.  Three ways to
+// count, by k:
+//  * k = 2 (two-phase segmentations, the verification metrics): four bytes at
+//    a time; a byte pair counts when both bytes are 0 or 1, and the four bins
+//    follow from population counts of a & b, a & ~b and ~a & b over those
+//    bytes;
+//  * k * k <= 16: 16-bit per-lane counters, four to a 64-bit word (bin j in
+//    word j / 4);
+//  * otherwise: an LDS atomic per pixel.
+// Lane counts are summed over the wave (only the k * k bins in use), each wave
+// adds its sums to the block's LDS histogram, and each block adds that to
+// memory with one integer atomic per non-empty bin.
+constexpr int kConfPer = 16;
+constexpr int kConfThreads = 1024;
 
 __device__ __forceinline__ void conf_load(const uint8_t *__restrict__ x, int64_t p, int cnt, uint32_t *w) {
-  if (cnt == kConfPer && (p & 15) == 0) {
-#pragma unroll
-    for (int q = 0; q < kConfPer / 16; ++q) {
-      const uint4 v = *reinterpret_cast<const uint4 *>(x + p + 16 * q);
-      w[4 * q] = v.x, w[4 * q + 1] = v.y, w[4 * q + 2] = v.z, w[4 * q + 3] = v.w;
-    }
+  if (cnt == kConfPer && ((uintptr_t)(x + p) & 15) == 0) {
+    const uint4 v = *reinterpret_cast<const uint4 *>(x + p);
+    w[0] = v.x, w[1] = v.y, w[2] = v.z, w[3] = v.w;
   } else {
 #pragma unroll
     for (int q = 0; q < kConfPer / 4; ++q) {
@@ -457,33 +465,39 @@ __device__ __forceinline__ void conf_load(const uint8_t *__restrict__ x, int64_t
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int j = 4 * q + i;
-        word |= (uint32_t)(j < cnt ? x[p + j] : (uint8_t)255) << (8 * i);
+        word |= (uint32_t)(j < cnt ? x[p + j] : (uint8_t)255) << (8 * i);  // 255 is never counted
       }
       w[q] = word;
     }
   }
 }
 
-__global__ __launch_bounds__(kImgThreads) void k_confusion(const uint8_t *__restrict__ a,
-                                                            const uint8_t *__restrict__ b, int64_t npix, int32_t k,
-                                                            unsigned long long *__restrict__ counts) {
+__device__ __forceinline__ unsigned int conf_wave_sum(unsigned int v) {
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(kConfThreads) void k_confusion(const uint8_t *__restrict__ a,
+                                                             const uint8_t *__restrict__ b, int64_t npix, int32_t k,
+                                                             unsigned long long *__restrict__ counts) {
   __shared__ unsigned int hist[16 * 16];
   for (int i = threadIdx.x; i < 256; i += blockDim.x) hist[i] = 0;
   __syncthreads();
   const int kk = k * k;
-  const bool small = kk <= 16;
-  uint64_t acc[4] = {0, 0, 0, 0};  // bin j: bits 16 (j % 4) .. of acc[j / 4]
   const int lane = threadIdx.x & 63;
-  // the lane counts of a bin go to the wave's sum and the block histogram
-  // (fields are unpacked before the cross-lane sum; a field holds at most
-  // kConfPer per round, and this runs at least every kConfFlush rounds)
+  const int mode = k == 2 ? 0 : kk <= 16 ? 1 : 2;  // the same for every thread
+  unsigned int n11 = 0, n10 = 0, n01 = 0, nv = 0;  // k = 2
+  uint64_t acc[4] = {0, 0, 0, 0};                  // k * k <= 16: bin j in bits 16 (j % 4) .. of acc[j / 4]
+  // sums the 16-bit lane fields of acc into the histogram (a field holds at
+  // most kConfPer per round, and this runs at least every kConfFlush rounds)
   auto flush = [&]() {
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      unsigned int v = (unsigned int)((acc[j >> 2] >> (16 * (j & 3))) & 0xffffu);
-      for (int d = 32; d > 0; d >>= 1) v += __shfl_down(v, d, 64);
-      if (lane == 0 && v && j < kk) atomicAdd(&hist[j], v);
-    }
+    for (int j = 0; j < 16; ++j)
+      if (j < kk) {
+        const unsigned int v = conf_wave_sum((unsigned int)((acc[j >> 2] >> (16 * (j & 3))) & 0xffffu));
+        if (lane == 0 && v) atomicAdd(&hist[j], v);
+      }
     acc[0] = acc[1] = acc[2] = acc[3] = 0;
   };
   constexpr int kConfFlush = 0xffff / kConfPer;
@@ -497,7 +511,19 @@ __global__ __launch_bounds__(kImgThreads) void k_confusion(const uint8_t *__rest
     uint32_t wa[kConfPer / 4], wb[kConfPer / 4];
     conf_load(a, p0, cnt, wa);
     conf_load(b, p0, cnt, wb);
-    if (small) {
+    if (mode == 0) {
+#pragma unroll
+      for (int i = 0; i < kConfPer / 4; ++i) {
+        // bit 7 of a byte of `bad` is set when either byte of the pair is >= 2
+        const uint32_t hi = (wa[i] | wb[i]) & 0xFEFEFEFEu;
+        const uint32_t bad = ((hi & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | hi;
+        const uint32_t ok = (~bad >> 7) & 0x01010101u;
+        n11 += __popc(wa[i] & wb[i] & ok);
+        n10 += __popc(wa[i] & ~wb[i] & ok);
+        n01 += __popc(~wa[i] & wb[i] & ok);
+        nv += __popc(ok);
+      }
+    } else if (mode == 1) {
 #pragma unroll
       for (int i = 0; i < kConfPer; ++i) {
         const int x = (wa[i / 4] >> (8 * (i % 4))) & 255, y = (wb[i / 4] >> (8 * (i % 4))) & 255;
@@ -509,6 +535,10 @@ __global__ __launch_bounds__(kImgThreads) void k_confusion(const uint8_t *__rest
         acc[2] += word == 2 ? inc : 0ull;
         acc[3] += word == 3 ? inc : 0ull;
       }
+      if (++rounds == kConfFlush) {
+        flush();
+        rounds = 0;
+      }
     } else {
 #pragma unroll
       for (int i = 0; i < kConfPer; ++i) {
@@ -516,23 +546,35 @@ __global__ __launch_bounds__(kImgThreads) void k_confusion(const uint8_t *__rest
         if (x < k && y < k) atomicAdd(&hist[x * k + y], 1u);
       }
     }
-    if (small && ++rounds == kConfFlush) {
-      flush();
-      rounds = 0;
-    }
   }
-  if (small) flush();
+  if (mode == 0) {
+    // bins (0,0), (0,1), (1,0), (1,1)
+    const unsigned int s11 = conf_wave_sum(n11), s10 = conf_wave_sum(n10), s01 = conf_wave_sum(n01),
+                       sv = conf_wave_sum(nv);
+    if (lane == 0 && sv) {
+      atomicAdd(&hist[0], sv - s11 - s10 - s01);
+      atomicAdd(&hist[1], s01);
+      atomicAdd(&hist[2], s10);
+      atomicAdd(&hist[3], s11);
+    }
+  } else if (mode == 1) {
+    flush();
+  }
   __syncthreads();
   for (int i = threadIdx.x; i < kk; i += blockDim.x)
     if (hist[i]) atomicAdd(&counts[i], (unsigned long long)hist[i]);
 }
 
-int grid_for(int64_t work, int per_cu = 8) {
+int cu_count() {
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     cus = 256;
+  return cus;
+}
+
+int grid_for(int64_t work, int per_cu = 8) {
   const int64_t need = (work + kImgThreads - 1) / kImgThreads;
-  return (int)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)cus * per_cu));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)cu_count() * per_cu));
 }
 
 pmrf_status workspace_bytes(int32_t width, int32_t height, int32_t depth, int32_t n, int64_t *bytes) {
@@ -685,10 +727,11 @@ extern "C" pmrf_status pmrf_confusion(const uint8_t *d_a, const uint8_t *d_b, in
   hipLaunchKernelGGL(k_zero, dim3(1), dim3(kImgThreads), 0, s, (unsigned long long *)d_counts, (int64_t)k * k);
   IMG_TRY(hipGetLastError());
   if (npixels > 0) {
-    // few blocks (each thread then takes several rounds): every block ends with
-    // one device-scope atomic per bin, all on the same k * k addresses
-    hipLaunchKernelGGL(k_confusion, dim3(grid_for((npixels + kConfPer - 1) / kConfPer, 1)), dim3(kImgThreads), 0, s,
-                       d_a, d_b, npixels, k,
+    // at most one block per compute unit: every block ends with one
+    // device-scope atomic per bin, all on the same k * k addresses
+    const int64_t per_block = (int64_t)kConfThreads * kConfPer;
+    const int blocks = (int)std::min<int64_t>((npixels + per_block - 1) / per_block, cu_count());
+    hipLaunchKernelGGL(k_confusion, dim3(blocks), dim3(kConfThreads), 0, s, d_a, d_b, npixels, k,
                        (unsigned long long *)d_counts);
     IMG_TRY(hipGetLastError());
   }

@@ -41,6 +41,24 @@ def test_full_size_slice():
     check_graph(lab, img, int(lab.max()) + 1, "slice2048_100k")
 
 
+def test_views_off_vector_boundaries():
+    # ids and pixels that start 4 and 3 bytes past an aligned address take the
+    # scalar loads; the results are the same
+    img, lab, _ = synth.image_slice(14, 300, 3000)
+    n = int(lab.max()) + 1
+    rb = torch.zeros(lab.size + 1, dtype=torch.int32, device="cuda")
+    pb = torch.zeros(img.size + 3, dtype=torch.uint8, device="cuda")
+    r = rb[1:].view(lab.shape)
+    p = pb[3:].view(img.shape)
+    r.copy_(torch.from_numpy(lab.astype(np.int32)))
+    p.copy_(torch.from_numpy(img))
+    row_ptr, col_idx, means = pmrf.image_graph(r, p, n)
+    ref_ptr, ref_col = oi.region_graph(lab, n)
+    assert np.array_equal(row_ptr.cpu().numpy(), ref_ptr)
+    assert np.array_equal(col_idx.cpu().numpy(), ref_col)
+    assert np.array_equal(means.cpu().numpy(), oi.region_means(lab, img, n))
+
+
 def test_edge_shapes():
     rng = np.random.default_rng(3)
     for h, w in [(1, 1), (1, 37), (41, 1), (3, 3)]:
@@ -93,6 +111,24 @@ def test_paint_and_confusion_match_oracle():
     big = torch.randint(0, 3, (1 << 22,), dtype=torch.uint8, device="cuda")
     c = pmrf.confusion(big, big.flip(0).contiguous(), 3).cpu().numpy()
     assert np.array_equal(c, oi.confusion(big.cpu().numpy(), big.flip(0).cpu().numpy(), 3))
+
+
+def test_confusion_large_ragged_and_unaligned():
+    # more pixels than one round of loads, a ragged tail, views that start off
+    # a 16-byte boundary, values >= k in both images; every counting path
+    g = torch.Generator().manual_seed(12)
+    n = (1 << 22) + 4099
+    a = torch.randint(0, 4, (n + 3,), generator=g, dtype=torch.uint8)
+    b = torch.randint(0, 3, (n + 5,), generator=g, dtype=torch.uint8)
+    a[7] = 255
+    b[100] = 200
+    da, db = a.cuda(), b.cuda()
+    for k in (1, 2, 3, 5):
+        for oa, ob in ((0, 0), (3, 5), (1, 0)):
+            va, vb = da[oa:oa + n], db[ob:ob + n]
+            c = pmrf.confusion(va, vb, k).cpu().numpy()
+            ref = oi.confusion(a[oa:oa + n].numpy(), b[ob:ob + n].numpy(), k)
+            assert np.array_equal(c, ref), (k, oa, ob)
 
 
 def test_image_to_segmentation():
