@@ -407,13 +407,13 @@ __global__ void k_lastbits(const int32_t *occ_ptr, const int32_t *occ, int32_t n
 }
 
 // ------------------------------------------------------------- packing
-// Next-fit packing of the processing order: a neighbourhood of at most 32
+// Next-fit packing of the processing order: a neighbourhood of at most 64
 // members joins the open packet when it fits in the 64 lanes, else opens a
-// new one; a larger one takes a packet of its own and closes the open one.
+// new one; a LARGE one takes a packet of its own and closes the open one.
 // The state is the open packet's fill (0: none), so each block of kFitBlock
 // neighbourhoods is summarised by its effect on every entry state.
 __device__ __forceinline__ void fit_step(int32_t s, int32_t &fill, int32_t &opened) {
-  if (s <= 32) {
+  if (s <= kWave) {
     if (fill == 0 || fill + s > kWave) ++opened, fill = 0;
     fill += s;
   } else {
@@ -467,23 +467,39 @@ __global__ void __launch_bounds__(64) k_fit_assign(const int32_t *psize, int64_t
     fit_step(s, fill, opened);
     cur += opened;
     tile_of[b0 + i] = cur;
-    pos_of[b0 + i] = s <= 32 ? fill - s : 0;
+    pos_of[b0 + i] = s <= kWave ? fill - s : 0;
   }
 }
 
 __device__ __forceinline__ int32_t words_of(int32_t s) { return s <= 32 ? 1 : (s + 31) / 32; }
 
-__global__ void k_mask_words(const int32_t *psize, int64_t H, int64_t *mw, int32_t *mid) {
+// a packet holding a neighbourhood above 32 members is MID
+__global__ void k_tile_mid(const int32_t *psize, int64_t H, const int32_t *tile_of, int32_t *t_mid, int32_t *mid) {
   for (int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; h < H; h += (int64_t)gridDim.x * blockDim.x) {
     const int32_t s = psize[h];
-    mw[h] = (int64_t)s * words_of(s);
-    if (s > 32 && s <= kWave) *mid = 1;
+    if (s > 32 && s <= kWave) {
+      t_mid[tile_of[h]] = 1;
+      *mid = 1;
+    }
+  }
+}
+
+// adjacency words per element of each neighbourhood (its packet's: two in a
+// MID packet, one in a SMALL one; a LARGE neighbourhood's own) and the
+// neighbourhood's share of the mask array
+__global__ void k_mask_words(const int32_t *psize, int64_t H, const int32_t *tile_of, const int32_t *t_mid,
+                             int64_t *mw, int32_t *hw) {
+  for (int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; h < H; h += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t s = psize[h];
+    const int32_t w = s > kWave ? words_of(s) : t_mid[tile_of[h]] ? 2 : 1;
+    hw[h] = w;
+    mw[h] = (int64_t)s * w;
   }
 }
 
 // packet fields set by its first neighbourhood; lanes and start bits gathered
 __global__ void k_tile_hoods(const int32_t *psize, int64_t H, const int32_t *tile_of, const int32_t *pos_of,
-                             const int32_t *pptr, const int64_t *moff, TileDesc *tiles,
+                             const int32_t *pptr, const int64_t *moff, const int32_t *hw, TileDesc *tiles,
                              unsigned long long *t_start, int32_t *t_nelem) {
   for (int64_t hp = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; hp < H; hp += (int64_t)gridDim.x * blockDim.x) {
     const int32_t s = psize[hp], T = tile_of[hp], pos = pos_of[hp];
@@ -492,8 +508,8 @@ __global__ void k_tile_hoods(const int32_t *psize, int64_t H, const int32_t *til
       t.elem_start = pptr[hp];
       t.hood_start = (int32_t)hp;
       t.mask_start = (int32_t)moff[hp];
-      t.kind = s <= 32 ? kSmall : s <= kWave ? kMid : kLarge;
-      t.words = (uint8_t)words_of(s);
+      t.kind = s > kWave ? kLarge : hw[hp] == 2 ? kMid : kSmall;
+      t.words = (uint8_t)hw[hp];
     }
     atomicOr(&t_start[T], 1ull << pos);
     atomicMax(&t_nelem[T], pos + s);
@@ -512,11 +528,12 @@ __global__ void k_tile_finish(int64_t ntiles, const unsigned long long *t_start,
 // words marks member p as a neighbour, its own bit marks the owner element
 __global__ void k_masks(int64_t M, const int32_t *pe_hood, const int32_t *pptr, const int32_t *perm,
                         const int32_t *hptr, const int32_t *dev_vid, const int32_t *owner, const int32_t *rp,
-                        const int32_t *ci, const int64_t *moff, uint32_t *mask, unsigned long long *A) {
+                        const int32_t *ci, const int64_t *moff, const int32_t *hw, uint32_t *mask,
+                        unsigned long long *A) {
   unsigned long long a = 0;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < M; e += (int64_t)gridDim.x * blockDim.x) {
     const int32_t hp = pe_hood[e], p0 = pptr[hp], s = pptr[hp + 1] - p0, j = (int32_t)e - p0;
-    const int32_t nw = words_of(s);
+    const int32_t nw = hw[hp];
     const int32_t v = dev_vid[e];
     const int32_t *mem = dev_vid + p0;
     uint32_t *w = mask + moff[hp] + (int64_t)j * nw;
@@ -536,11 +553,11 @@ __global__ void k_masks(int64_t M, const int32_t *pe_hood, const int32_t *pptr, 
 
 // slot layout of the packets before the first LARGE one
 __global__ void k_slots(int64_t Ms, const int32_t *pe_hood, const int32_t *pptr, const int32_t *tile_of,
-                        const int32_t *pos_of, const int32_t *dev_vid, const int64_t *moff, const uint32_t *mask,
-                        int32_t *svid, uint32_t *smask, uint32_t *smask_hi) {
+                        const int32_t *pos_of, const int32_t *dev_vid, const int64_t *moff, const int32_t *hw,
+                        const uint32_t *mask, int32_t *svid, uint32_t *smask, uint32_t *smask_hi) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < Ms; e += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t hp = pe_hood[e], p0 = pptr[hp], s = pptr[hp + 1] - p0, j = (int32_t)e - p0;
-    const int32_t nw = words_of(s);
+    const int32_t hp = pe_hood[e], p0 = pptr[hp], j = (int32_t)e - p0;
+    const int32_t nw = hw[hp];
     const int64_t slot = (int64_t)tile_of[hp] * kWave + pos_of[hp] + j;
     const uint32_t *w = mask + moff[hp] + (int64_t)j * nw;
     svid[slot] = (int32_t)((uint32_t)dev_vid[e] | ((uint32_t)j << kSlotJShift));
@@ -847,9 +864,11 @@ void build_on_device(int32_t n, const int32_t *rp, const int32_t *ci, int32_t k,
     ntiles = B.read(B.scal.p);
   }
   Buf<int64_t> moff(H + 1);
-  Buf<int32_t> midf(1);
+  Buf<int32_t> midf(1), t_mid(std::max<int64_t>(1, ntiles)), hw(H);
   B.zero(midf.p, 1);
-  k_mask_words<<<blocks_for(H, kBT), kBT, 0, st>>>(psize.p, H, moff.p, midf.p);
+  B.zero(t_mid.p, std::max<int64_t>(1, ntiles));
+  k_tile_mid<<<blocks_for(H, kBT), kBT, 0, st>>>(psize.p, H, tile_of.p, t_mid.p, midf.p);
+  k_mask_words<<<blocks_for(H, kBT), kBT, 0, st>>>(psize.p, H, tile_of.p, t_mid.p, moff.p, hw.p);
   B.check();
   B.scan(moff.p, moff.p, H);
   const int64_t mask_words = B.read(moff.p + H);
@@ -916,23 +935,23 @@ void build_on_device(int32_t n, const int32_t *rp, const int32_t *ci, int32_t k,
     Buf<int32_t> t_nelem(ntiles);
     B.zero(t_start.p, ntiles);
     B.zero(t_nelem.p, ntiles);
-    k_tile_hoods<<<blocks_for(H, kBT), kBT, 0, st>>>(psize.p, H, tile_of.p, pos_of.p, pptr.p, moff.p, tiles, t_start.p,
-                                                     t_nelem.p);
+    k_tile_hoods<<<blocks_for(H, kBT), kBT, 0, st>>>(psize.p, H, tile_of.p, pos_of.p, pptr.p, moff.p, hw.p, tiles,
+                                                     t_start.p, t_nelem.p);
     k_tile_finish<<<blocks_for(ntiles, kBT), kBT, 0, st>>>(ntiles, t_start.p, t_nelem.p, tiles);
     B.check();
     B.sync();
   }
   // adjacency words and the in-neighbourhood adjacency count
   B.zero(B.scal.p, 1);
-  k_masks<<<blocks_for(M, kBT), kBT, 0, st>>>(M, pe_hood.p, pptr.p, perm.p, hptr.p, dvid, owner.p, rp, ci, moff.p, mask,
-                                             reinterpret_cast<unsigned long long *>(B.scal.p));
+  k_masks<<<blocks_for(M, kBT), kBT, 0, st>>>(M, pe_hood.p, pptr.p, perm.p, hptr.p, dvid, owner.p, rp, ci, moff.p, hw.p,
+                                             mask, reinterpret_cast<unsigned long long *>(B.scal.p));
   B.check();
   hd->A = B.read(B.scal.p);
   // slot layout, chunk headers, superchunk ranges
   k_fill<int32_t><<<blocks_for(slots, kBT), kBT, 0, st>>>(svid, slots, (int32_t)kSlotEmpty);
   const int64_t Ms = ns < H ? B.read(pptr.p + ns) : M;
-  k_slots<<<blocks_for(Ms, kBT), kBT, 0, st>>>(Ms, pe_hood.p, pptr.p, tile_of.p, pos_of.p, dvid, moff.p, mask, svid,
-                                              smask, smask_hi);
+  k_slots<<<blocks_for(Ms, kBT), kBT, 0, st>>>(Ms, pe_hood.p, pptr.p, tile_of.p, pos_of.p, dvid, moff.p, hw.p, mask,
+                                              svid, smask, smask_hi);
   if (nchunks) k_chunks<<<blocks_for(nchunks, kBT), kBT, 0, st>>>(tiles, ntiles, nchunks, (int32_t)H, chdr);
   k_srange<<<nsuper, kBT, 0, st>>>(svid, slots, sc * kChunkTiles * kWave, srange);
   B.check();

@@ -1817,10 +1817,15 @@ __device__ __forceinline__ void iter_superchunk_fused(const GraphDev &G, int b, 
 // without a dependent load); otherwise each block looks its graph up in
 // graphs[0 .. B).  FUSED (single graph, t >= 1, not persistent): the launch
 // also does the parameter update of iteration t - 1 (iter_superchunk_fused).
+// Not persistent and not fused, the launch also takes the superchunks that hold
+// a LARGE packet: workgroups [0, npk) play packet blocks 0 .. npk - 1 (first,
+// so the longest blocks start first), [npk, npk_pad) return at once, and the
+// slot blocks follow; npk_pad is a multiple of the XCD count, so the slot
+// blocks keep their XCD placement.
 template <int LMAX, bool PERSIST, bool SINGLE, bool FUSED = false, bool ANY = false>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(LMAX <= 2 ? (SINGLE ? PMRF_ITER_WAVES_PER_EU : PMRF_BATCH_WAVES_PER_EU) : 1, 8))) void k_iter(
     const GraphDev *__restrict__ graphs, const int32_t *__restrict__ block_graph, const GraphDev g1, int B,
-    int nsuper_total, int t) {
+    int nsuper_total, int t, int npk, int npk_pad) {
   static_assert(!FUSED || (SINGLE && !PERSIST), "the fused launch is for one graph, one block per superchunk");
   // dynamic LDS: one region of kWaveLds doubles per wave, after (fused
   // launch) the staged range (kStageCap doubles, then kStageCap bytes)
@@ -1839,7 +1844,16 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(LMAX <= 2 
     iter_superchunk_fused<LMAX>(g1, xcd_block(blockIdx.x, gridDim.x), t, part, sy, sx, wbase, mb, od, oa, fl, nw,
                                 wave, lane);
   } else if constexpr (!PERSIST) {
-    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    if ((int)blockIdx.x < npk_pad) {
+      if ((int)blockIdx.x < npk) {
+        const GraphDev &G = graphs[find_graph(graphs, B, blockIdx.x, kGridPacket)];
+        const int i = blockIdx.x - G.pblock0;
+        iter_superchunk<LMAX, true, false, ANY>(G, packet_c0(G, i), packet_c1(G, i), t, part, mb, pl, od, oa, nw,
+                                                wave, lane);
+      }
+      return;
+    }
+    const int blk = xcd_block(blockIdx.x - npk_pad, gridDim.x - npk_pad);
     if constexpr (SINGLE) {
       iter_superchunk<LMAX, false, true, ANY>(g1, slot_c0(g1, blk), slot_c1(g1, blk), t, part, mb, pl, od, oa, nw,
                                          wave, lane);
@@ -2275,6 +2289,12 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     grid_iter = std::max(1, std::min(blocks_iter, cus * shape.blocks_per_cu));
   }
+  // not persistent: the packet superchunks ride in the iteration launch
+  // (their blocks first), so they run beside the slot blocks
+  const bool merge_pk = !persist && blocks_pk > 0 && blocks_iter > 0;
+  const int npk = merge_pk ? blocks_pk : 0;
+  const int npk_pad = merge_pk ? (blocks_pk + kXcds - 1) / kXcds * kXcds : 0;
+  if (merge_pk) grid_iter = blocks_iter + npk_pad;
 
   // Everything the run enqueues; descriptors travel as kernel arguments, so no
   // host buffer must outlive the call and the sequence can be captured.
@@ -2313,7 +2333,7 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
       // the iteration's first kernel carries the start event, its last the stop event
       hipEvent_t ev0 = nullptr, ev1 = nullptr;
       if (events && (blocks_iter > 0 || blocks_pk > 0)) HIP_TRY(prof_pair(&ev0, &ev1));
-      hipEvent_t slot_start = ev0, slot_stop = blocks_pk > 0 ? nullptr : ev1;
+      hipEvent_t slot_start = ev0, slot_stop = blocks_pk > 0 && !merge_pk ? nullptr : ev1;
       hipEvent_t pk_start = blocks_iter > 0 ? nullptr : ev0, pk_stop = ev1;
 // plain launches unless the iteration is being timed (graph capture never is)
 #define PMRF_LAUNCH(KERNEL, GRID, LDS, START, STOP, ...)                                                     \
@@ -2328,46 +2348,46 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
   do {                                                                                                        \
     if (any_rule && B == 1)                                                                                   \
       PMRF_LAUNCH_LDS((k_iter<LM, false, true, false, true>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, \
-                      desc[0], B, blocks_iter, t);                                                            \
+                      desc[0], B, blocks_iter, t, npk, npk_pad);                                                            \
     else if (any_rule)                                                                                        \
       PMRF_LAUNCH_LDS((k_iter<LM, false, false, false, true>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, \
-                      desc[0], B, blocks_iter, t);                                                            \
+                      desc[0], B, blocks_iter, t, npk, npk_pad);                                                            \
     else if (fused && t > 0)                                                                                  \
       PMRF_LAUNCH((k_iter<LM, false, true, true>), dim3(grid_iter), lds_fused, slot_start, slot_stop, gd, block_graph, \
-                  desc[0], B, blocks_iter, t);                                                                \
+                  desc[0], B, blocks_iter, t, npk, npk_pad);                                                                \
     else if (persist && B == 1)                                                                               \
       PMRF_LAUNCH_LDS((k_iter<LM, true, true>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, desc[0], B,           \
-                  blocks_iter, t);                                                                            \
+                  blocks_iter, t, npk, npk_pad);                                                                            \
     else if (persist)                                                                                         \
       PMRF_LAUNCH_LDS((k_iter<LM, true, false>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, desc[0], B,          \
-                  blocks_iter, t);                                                                            \
+                  blocks_iter, t, npk, npk_pad);                                                                            \
     else if (B == 1)                                                                                          \
       PMRF_LAUNCH_LDS((k_iter<LM, false, true>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, desc[0], B,          \
-                  blocks_iter, t);                                                                            \
+                  blocks_iter, t, npk, npk_pad);                                                                            \
     else                                                                                                      \
       PMRF_LAUNCH_LDS((k_iter<LM, false, false>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, desc[0], B,         \
-                  blocks_iter, t);                                                                            \
+                  blocks_iter, t, npk, npk_pad);                                                                            \
   } while (0)
 #define PMRF_LAUNCH_ITER_UNFUSED(LM)                                                                          \
   do {                                                                                                        \
     if (any_rule && B == 1)                                                                                   \
       PMRF_LAUNCH_LDS((k_iter<LM, false, true, false, true>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, \
-                      desc[0], B, blocks_iter, t);                                                            \
+                      desc[0], B, blocks_iter, t, npk, npk_pad);                                                            \
     else if (any_rule)                                                                                        \
       PMRF_LAUNCH_LDS((k_iter<LM, false, false, false, true>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, \
-                      desc[0], B, blocks_iter, t);                                                            \
+                      desc[0], B, blocks_iter, t, npk, npk_pad);                                                            \
     else if (persist && B == 1)                                                                               \
       PMRF_LAUNCH_LDS((k_iter<LM, true, true>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, desc[0], B,           \
-                  blocks_iter, t);                                                                            \
+                  blocks_iter, t, npk, npk_pad);                                                                            \
     else if (persist)                                                                                         \
       PMRF_LAUNCH_LDS((k_iter<LM, true, false>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, desc[0], B,          \
-                  blocks_iter, t);                                                                            \
+                  blocks_iter, t, npk, npk_pad);                                                                            \
     else if (B == 1)                                                                                          \
       PMRF_LAUNCH_LDS((k_iter<LM, false, true>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, desc[0], B,          \
-                  blocks_iter, t);                                                                            \
+                  blocks_iter, t, npk, npk_pad);                                                                            \
     else                                                                                                      \
       PMRF_LAUNCH_LDS((k_iter<LM, false, false>), dim3(grid_iter), slot_start, slot_stop, gd, block_graph, desc[0], B,         \
-                  blocks_iter, t);                                                                            \
+                  blocks_iter, t, npk, npk_pad);                                                                            \
   } while (0)
 #define PMRF_LAUNCH_PK(LM)                                                                                      \
   do {                                                                                                          \
@@ -2385,7 +2405,7 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
         }
         HIP_TRY(hipGetLastError());
       }
-      if (blocks_pk > 0) {
+      if (blocks_pk > 0 && !merge_pk) {
         switch (lm) {
           case 2: PMRF_LAUNCH_PK(2); break;
           case 4: PMRF_LAUNCH_PK(4); break;

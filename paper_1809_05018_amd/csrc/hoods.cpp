@@ -269,41 +269,64 @@ extern "C" pmrf_status pmrf_build_neighborhoods(int32_t n, const int32_t *row_pt
         hd->lastbits[e >> 6] |= 1ull << (e & 63);
       }
     }
-    // work packets and adjacency words, in processing order
-    std::vector<int32_t> loc(n, -1);
-    auto open_tile = [&](uint8_t kind, uint8_t words, int64_t hp) {
-      TileDesc t{};
-      t.start_mask = 0;
-      t.elem_start = hd->hood_ptr32[hp];
-      t.hood_start = (int32_t)hp;
-      t.mask_start = (int32_t)hd->mask.size();
-      t.nelem = 0;
-      t.kind = kind;
-      t.words = words;
-      hd->tiles.push_back(t);
-    };
-    bool small_open = false;
+    // work packets, in processing order: next-fit over the neighbourhoods of
+    // at most 64 members (one joins the open packet while its lanes hold it,
+    // else opens a new one); a packet holding a neighbourhood above 32 members
+    // is MID (two adjacency words per element), else SMALL (one).  A LARGE
+    // neighbourhood takes a packet of its own.
+    std::vector<int32_t> tile_of((size_t)H), pos_of((size_t)H);
+    bool open = false;
     for (int64_t hp = 0; hp < H; ++hp) {
-      const int64_t h = hd->perm[hp];
-      int64_t o = hd->hood_ptr[h];  // canonical element offset (owner indices are canonical)
-      int32_t s = (int32_t)(hd->hood_ptr[h + 1] - o);
-      uint8_t words;
-      if (s <= 32) {
-        words = 1;
-        if (!small_open || hd->tiles.back().nelem + s > kWave) { open_tile(kSmall, 1, hp); small_open = true; }
+      const int32_t s = (int32_t)(hd->hood_ptr[hd->perm[hp] + 1] - hd->hood_ptr[hd->perm[hp]]);
+      if (s <= kWave) {
+        if (!open || hd->tiles.back().nelem + s > kWave) {
+          TileDesc t{};
+          t.elem_start = hd->hood_ptr32[hp];
+          t.hood_start = (int32_t)hp;
+          t.kind = kSmall;
+          t.words = 1;
+          hd->tiles.push_back(t);
+          open = true;
+        }
         TileDesc &t = hd->tiles.back();
+        pos_of[hp] = t.nelem;
         t.start_mask |= uint64_t(1) << t.nelem;
         t.nelem = (int16_t)(t.nelem + s);
+        if (s > 32) {
+          t.kind = kMid;
+          t.words = 2;
+        }
       } else {
-        small_open = false;
-        words = (uint8_t)((s + 31) / 32);
-        open_tile(s <= 64 ? kMid : kLarge, words, hp);
-        hd->tiles.back().start_mask = 1;
-        hd->tiles.back().nelem = (int16_t)s;
+        open = false;
+        TileDesc t{};
+        t.elem_start = hd->hood_ptr32[hp];
+        t.hood_start = (int32_t)hp;
+        t.kind = kLarge;
+        t.words = (uint8_t)((s + 31) / 32);
+        t.start_mask = 1;
+        t.nelem = (int16_t)s;
+        hd->tiles.push_back(t);
+        pos_of[hp] = 0;
       }
+      tile_of[hp] = (int32_t)hd->tiles.size() - 1;
+    }
+    int64_t words_total = 0;
+    for (TileDesc &t : hd->tiles) {
+      t.mask_start = (int32_t)words_total;
+      words_total += (int64_t)t.nelem * t.words;
+    }
+    // adjacency words: bit p of an element's words marks member p of its
+    // neighbourhood as a neighbour, its own bit marks the owner element
+    hd->mask.assign((size_t)words_total, 0u);
+    std::vector<int32_t> loc(n, -1);
+    for (int64_t hp = 0; hp < H; ++hp) {
+      const int64_t h = hd->perm[hp];
+      const int64_t o = hd->hood_ptr[h];  // canonical element offset (owner indices are canonical)
+      const int32_t s = (int32_t)(hd->hood_ptr[h + 1] - o);
+      const TileDesc &t = hd->tiles[tile_of[hp]];
+      const int words = t.words;
       for (int32_t j = 0; j < s; ++j) loc[hd->hood_vid[o + j]] = j;
-      size_t base = hd->mask.size();
-      hd->mask.resize(base + (size_t)s * words, 0u);
+      const size_t base = (size_t)t.mask_start + (size_t)pos_of[hp] * words;
       for (int32_t j = 0; j < s; ++j) {
         int32_t v = hd->hood_vid[o + j];
         uint32_t *w = hd->mask.data() + base + (size_t)j * words;
