@@ -1817,11 +1817,12 @@ __device__ __forceinline__ void iter_superchunk_fused(const GraphDev &G, int b, 
 // without a dependent load); otherwise each block looks its graph up in
 // graphs[0 .. B).  FUSED (single graph, t >= 1, not persistent): the launch
 // also does the parameter update of iteration t - 1 (iter_superchunk_fused).
-// Not persistent and not fused, the launch also takes the superchunks that hold
-// a LARGE packet: workgroups [0, npk) play packet blocks 0 .. npk - 1 (first,
-// so the longest blocks start first), [npk, npk_pad) return at once, and the
-// slot blocks follow; npk_pad is a multiple of the XCD count, so the slot
-// blocks keep their XCD placement.
+// Not persistent and not fused (and not the batched two-label kernel, whose
+// registers are budgeted for five waves per SIMD), the launch also takes the
+// superchunks that hold a LARGE packet: workgroups [0, npk) play packet blocks
+// 0 .. npk - 1 (first, so the longest blocks start first), [npk, npk_pad)
+// return at once, and the slot blocks follow; npk_pad is a multiple of the XCD
+// count, so the slot blocks keep their XCD placement.
 template <int LMAX, bool PERSIST, bool SINGLE, bool FUSED = false, bool ANY = false>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(LMAX <= 2 ? (SINGLE ? PMRF_ITER_WAVES_PER_EU : PMRF_BATCH_WAVES_PER_EU) : 1, 8))) void k_iter(
     const GraphDev *__restrict__ graphs, const int32_t *__restrict__ block_graph, const GraphDev g1, int B,
@@ -1844,16 +1845,19 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(LMAX <= 2 
     iter_superchunk_fused<LMAX>(g1, xcd_block(blockIdx.x, gridDim.x), t, part, sy, sx, wbase, mb, od, oa, fl, nw,
                                 wave, lane);
   } else if constexpr (!PERSIST) {
-    if ((int)blockIdx.x < npk_pad) {
-      if ((int)blockIdx.x < npk) {
-        const GraphDev &G = graphs[find_graph(graphs, B, blockIdx.x, kGridPacket)];
-        const int i = blockIdx.x - G.pblock0;
-        iter_superchunk<LMAX, true, false, ANY>(G, packet_c0(G, i), packet_c1(G, i), t, part, mb, pl, od, oa, nw,
-                                                wave, lane);
+    if constexpr (SINGLE || LMAX > 2) {
+      if ((int)blockIdx.x < npk_pad) {
+        if ((int)blockIdx.x < npk) {
+          const GraphDev &G = graphs[find_graph(graphs, B, blockIdx.x, kGridPacket)];
+          const int i = blockIdx.x - G.pblock0;
+          iter_superchunk<LMAX, true, false, ANY>(G, packet_c0(G, i), packet_c1(G, i), t, part, mb, pl, od, oa, nw,
+                                                  wave, lane);
+        }
+        return;
       }
-      return;
     }
-    const int blk = xcd_block(blockIdx.x - npk_pad, gridDim.x - npk_pad);
+    const int pad = SINGLE || LMAX > 2 ? npk_pad : 0;
+    const int blk = xcd_block(blockIdx.x - pad, gridDim.x - pad);
     if constexpr (SINGLE) {
       iter_superchunk<LMAX, false, true, ANY>(g1, slot_c0(g1, blk), slot_c1(g1, blk), t, part, mb, pl, od, oa, nw,
                                          wave, lane);
@@ -2290,8 +2294,9 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
     grid_iter = std::max(1, std::min(blocks_iter, cus * shape.blocks_per_cu));
   }
   // not persistent: the packet superchunks ride in the iteration launch
-  // (their blocks first), so they run beside the slot blocks
-  const bool merge_pk = !persist && blocks_pk > 0 && blocks_iter > 0;
+  // (their blocks first), so they run beside the slot blocks (the batched
+  // two-label kernel excepted)
+  const bool merge_pk = !persist && blocks_pk > 0 && blocks_iter > 0 && (B == 1 || lm > 2);
   const int npk = merge_pk ? blocks_pk : 0;
   const int npk_pad = merge_pk ? (blocks_pk + kXcds - 1) / kXcds * kXcds : 0;
   if (merge_pk) grid_iter = blocks_iter + npk_pad;
