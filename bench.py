@@ -472,8 +472,10 @@ def batched_leg(args, dev, workload, graphs):
                         "frac": achieved / HBM_PEAK_GBS,
                         "traffic": measured_traffic(BATCH_COUNTERS_FILE if workload == "batch64"
                                                     else POWERLAW_COUNTERS_FILE),
-                        "kernel": f"k_iter<{4 if L > 2 else 2}> batched (the superchunks of neighbourhoods "
-                                  "above 64 members in the same launch)",
+                        "kernel": (f"k_iter<{4 if L > 2 else 2}> batched" +
+                                   (" (the superchunks of neighbourhoods above 64 members in the same launch)"
+                                    if L > 2 else " (+ k_iter_packets where a graph has neighbourhoods above 64 "
+                                    "members)")),
                         "alg_bytes_per_launch": b_iter, "avg_launch_us": avg * 1e6, "launches_timed": launches,
                         "timing": "HIP events around each EM iteration's work kernels, one batched run"},
            "cpu_baseline": None}
