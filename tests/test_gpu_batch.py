@@ -98,17 +98,20 @@ def test_batch_rejects_small_workspace_without_writing():
     assert torch.equal(prob.labels, before)
 
 
-def test_batch_with_a_graph_on_the_packet_kernel_only():
-    """A graph whose window (6) sends every chunk to the packet kernel has no
-    slot-kernel blocks; the graphs after it in the batch must still find their
-    own blocks (block-to-graph table) and every result equals its solo run."""
-    specs = [(synth.image_graph(620, 300, 3000, 2), 3), (synth.image_graph(621, 256, 1500, 2), 6),
-             (synth.image_graph(622, 400, 5000, 2), 3), (synth.image_graph(623, 128, 400, 2), 6)]
+@pytest.mark.parametrize("L", [2, 3])
+def test_batch_with_a_graph_on_the_packet_kernel_only(L):
+    """A graph whose window (6) sends every chunk to the packet path has no
+    slot blocks; the graphs after it in the batch must still find their own
+    blocks (block-to-graph table) and every result equals its solo run.  With
+    two labels the packet superchunks take a launch of their own, with three
+    (the four-label kernels) they ride in the iteration launch."""
+    specs = [(synth.image_graph(620, 300, 3000, L), 3), (synth.image_graph(621, 256, 1500, L), 6),
+             (synth.image_graph(622, 400, 5000, L), 3), (synth.image_graph(623, 128, 400, L), 6)]
     solos, probs = [], []
     for g, W in specs:
-        x0, mu0, s0 = init_state(g, 2)
-        prob = pmrf.Problem(g.n, g.row_ptr, g.col_idx, g.y, 2)
-        params = pmrf.pmrf_em_params(L=2, beta=0.5, max_iters=10, conv_window=W)
+        x0, mu0, s0 = init_state(g, L)
+        prob = pmrf.Problem(g.n, g.row_ptr, g.col_idx, g.y, L)
+        params = pmrf.pmrf_em_params(L=L, beta=0.5, max_iters=10, conv_window=W)
         prob.set_state(x0, mu0, s0)
         prob.run(params)
         solos.append(prob.results(params))

@@ -60,6 +60,29 @@ def test_builder_matches_oracle_workloads():
     assert h.max_hood > 64  # exercises the multi-chunk packet layout
 
 
+def next_fit_packets(sizes):
+    """Packets of the processing order: neighbourhoods of at most 64 members
+    (canonical order) packed next-fit into 64 lanes, then one packet per
+    larger neighbourhood."""
+    packets, fill = 0, 0
+    for s in sizes[sizes <= 64]:
+        if packets == 0 or fill + s > 64:
+            packets, fill = packets + 1, 0
+        fill += s
+    return packets + int(np.sum(sizes > 64))
+
+
+def test_packet_count_follows_next_fit():
+    for g in (synth.powerlaw_graph(41, 4000, phases=4, dmax=60), synth.workload_small()):
+        h = pmrf.pmrf_build_neighborhoods(g.n, g.row_ptr, g.col_idx)
+        sizes = np.diff(h.export()["hood_ptr"])
+        assert h.tiles == next_fit_packets(sizes), g.name
+    g = synth.workload_small()
+    h = pmrf.pmrf_build_neighborhoods(g.n, g.row_ptr, g.col_idx, 2)  # MID neighbourhoods among small ones
+    sizes = np.diff(h.export()["hood_ptr"])
+    assert np.any((sizes > 32) & (sizes <= 64)) and h.tiles == next_fit_packets(sizes)
+
+
 def test_builder_k_neighbourhoods_match_oracle():
     for k in (2, 3):
         for n, rp, ci in pins.random_small_graphs(count=40):
