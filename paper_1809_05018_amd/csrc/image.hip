@@ -76,7 +76,7 @@ struct ImgPlan {
   size_t hist = 0;           // int32: radix histogram
   size_t s64 = 0, s32 = 0;   // scan scratch, int64 and int32
   size_t zero_lo = 0;        // [zero_lo, zero_hi) cleared at the start:
-  size_t fdeg = 0, bdeg = 0, cur = 0;  //   int32[n] each: forward / backward counts, fill cursors
+  size_t fdeg = 0, bdeg = 0, cur = 0;  //   int32[n] each: forward run ends, backward counts, fill cursors
   size_t sums = 0, counts = 0;         //   uint64[n] each
   size_t scal = 0;                     //   int64[8]: bad ids, unique pairs
   size_t zero_hi = 0;
@@ -251,26 +251,31 @@ __global__ __launch_bounds__(kImgThreads) void k_pack(const uint64_t *__restrict
 
 // Forward / backward counts of the unique pairs (u, v), u < v, and the list
 // index where each row's forward pairs start.
+// The unique pairs are sorted, so row a's forward neighbours are one run of
+// the list: its first element writes fstart[a], its last fend[a] = index + 1
+// (fend is zeroed beforehand, so 0 marks a row without forward neighbours);
+// only the backward counts need atomics.
 __global__ __launch_bounds__(kImgThreads) void k_degrees(const uint64_t *__restrict__ u, int64_t P,
                                                           const long long *__restrict__ m, int B,
-                                                          int32_t *__restrict__ fdeg, int32_t *__restrict__ bdeg,
+                                                          int32_t *__restrict__ fend, int32_t *__restrict__ bdeg,
                                                           int32_t *__restrict__ fstart) {
   const int64_t c = min((int64_t)*m, P);
   const uint64_t low = ((uint64_t)1 << B) - 1;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < c; i += (int64_t)gridDim.x * blockDim.x) {
     const uint64_t k = u[i];
     const int32_t a = (int32_t)(k >> B), b = (int32_t)(k & low);
-    atomicAdd(&fdeg[a], 1);
     atomicAdd(&bdeg[b], 1);
     if (i == 0 || (int32_t)(u[i - 1] >> B) != a) fstart[a] = (int32_t)i;
+    if (i + 1 == c || (int32_t)(u[i + 1] >> B) != a) fend[a] = (int32_t)(i + 1);
   }
 }
 
-__global__ __launch_bounds__(kImgThreads) void k_row_sizes(const int32_t *__restrict__ fdeg,
+__global__ __launch_bounds__(kImgThreads) void k_row_sizes(const int32_t *__restrict__ fend,
+                                                            const int32_t *__restrict__ fstart,
                                                             const int32_t *__restrict__ bdeg, int32_t n,
                                                             int32_t *__restrict__ rp) {
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
-    rp[v] = fdeg[v] + bdeg[v];
+    rp[v] = (fend[v] ? fend[v] - fstart[v] : 0) + bdeg[v];
 }
 
 // Row a: its backward neighbours (below a) first, then its forward ones in
@@ -649,7 +654,7 @@ pmrf_status region_graph(const int32_t *d_regions, const uint8_t *d_pixels, int3
   }
   if (n > 0) {
     hipLaunchKernelGGL(k_row_sizes, dim3(grid_for(n)), dim3(kImgThreads), 0, s, (const int32_t *)fdeg,
-                       (const int32_t *)bdeg, n, rp);
+                       (const int32_t *)fstart, (const int32_t *)bdeg, n, rp);
     IMG_TRY(hipGetLastError());
   }
   pp::scan<int32_t>(s, rp, rp, n, nullptr, s32);
