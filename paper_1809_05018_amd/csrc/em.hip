@@ -1775,9 +1775,11 @@ __device__ __forceinline__ void iter_superchunk_fused(const GraphDev &G, int b, 
   }
   if (sg.on) stage_rest(c, sg, si, sy, sx);
   __syncthreads();
+  // stage 2: one row of 64 virtual lanes per wave (16 * words <= 256 lanes),
+  // then the update in wave 0
+  fold_stage2(scr, words, fl.tot, nw, wave, lane);
+  __syncthreads();
   if (wave == 0) {
-    fold_stage2(scr, words, fl.tot, 1, 0, lane);
-    wave_lds_sync();
     const bool stop = finish_iteration(G, t, fl.tot, pv, writer, lane);
     if (lane < LMAX) {
       const bool ok = lane < G.L;
