@@ -320,8 +320,8 @@ pmrf_status pmrf_launch_stats(int64_t *captures, int64_t *replays, int64_t *dire
 /* ------------------------------------------------------------------------
  * Kernel timing for measurement.  Between pmrf_profile_begin and
  * pmrf_profile_end the work kernels of every EM iteration made by this
- * process (the energy / argmin / sum / label / statistics kernels: the slot
- * kernel, and the packet kernel where a graph has one) carry a pair of HIP
+ * process (the energy / argmin / sum / label / statistics kernels: the
+ * iteration kernel, and a separate packet kernel where one runs) carry a pair of HIP
  * events on their stream, which the runtime stamps with the first kernel's
  * dispatch begin and the last one's end (hipExtLaunchKernel).
  * pmrf_profile_end waits for the last event and returns the summed

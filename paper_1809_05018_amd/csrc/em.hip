@@ -146,7 +146,7 @@ struct GraphDev {
   int32_t n, H, ntiles, nchunks, nsuper, L, P, W, max_iters, early_exit, init_from_labels;
   int32_t sc;        // chunks per superchunk (record)
   int32_t bc;        // chunks per slot-kernel block (a multiple of sc)
-  int32_t nslot;     // superchunks on the slot kernel: [0, nslot); the rest take the packet kernel
+  int32_t nslot;     // superchunks on the slot path: [0, nslot); the rest take the packet path
   int32_t slot_end;  // first chunk past the slot kernel's superchunks
   double beta, tol, sigma_min, tie_eps;
   int32_t block0, nblocks;    // slot-kernel blocks of this graph: chunks [bc b, bc (b + 1)) of [0, slot_end)
@@ -1644,7 +1644,7 @@ __device__ __forceinline__ void store_records(const GraphDev &G, int c0, int c1,
 }
 
 // One EM iteration over every graph of the launch.  A block takes chunks
-// [c0, c1) of a graph (whole superchunks: one on the packet kernel and for a
+// [c0, c1) of a graph (whole superchunks: one on the packet path and for a
 // single graph, up to 16 chunks' worth in a batch); its waves take the chunks
 // in turn, leave each chunk's statistics in LDS, and the block adds them in
 // chunk order into one record per superchunk (buffer t & 1).  PACKET: the
@@ -2099,7 +2099,7 @@ int64_t max_records(const pmrf_hoods *h, const pmrf_em_params &p) {
 
 // Superchunks of a graph that take the slot kernel: those before the first
 // LARGE packet (all of them when there is none), none when the window is
-// longer than kPreWindow; the rest take the packet kernel.
+// longer than kPreWindow; the rest take the packet path.
 int32_t slot_supers(const pmrf_hoods *h, const pmrf_em_params &params) {
   const int64_t per_super = (int64_t)kChunkTiles * superchunk_chunks(h);
   int32_t nslot = h->slot_tiles == h->ntiles ? (int32_t)n_super(h) : (int32_t)(h->slot_tiles / per_super);
@@ -2282,7 +2282,7 @@ pmrf_status run_items(int B, const pmrf_em_item *items, void *d_ws, int64_t ws_b
   const bool fused_finish = fused && max_iters >= 1;
   // dynamic LDS of the slot kernel: the staged range, then the waves' regions
   // (which hold the fused fold's partials before any chunk is computed); of
-  // the packet kernel: the waves' regions
+  // the packet path: the waves' regions
   const size_t lds_pk = (size_t)(kWaveLds * shape.waves_per_block) * 8;
   const size_t lds_fused = (size_t)kStageDoubles * 8 + std::max(lds_pk, (size_t)rec_words(lm) * kFoldLanes * 8);
   const bool events = g_prof.on && !no_alloc;
