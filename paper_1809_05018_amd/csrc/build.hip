@@ -304,15 +304,19 @@ __global__ void __launch_bounds__(kBT) k_sort_unique(int32_t *cand, const int64_
   extern __shared__ int32_t s[];
   __shared__ int32_t lds[kBT / 64];
   const int t = threadIdx.x, bd = blockDim.x;
-  const int per = P / bd;
   for (int64_t h = blockIdx.x; h < H; h += gridDim.x) {
     const int64_t b = cptr[h];
     const int32_t cnt = (int32_t)(cptr[h + 1] - b);
-    for (int i = t; i < P; i += bd) s[i] = i < cnt ? cand[b + i] : INT_MAX;
+    // this neighbourhood's network: the power of two at or above its count
+    // (P, the largest, sizes the LDS)
+    int32_t Ph = 2;
+    while (Ph < cnt) Ph <<= 1;
+    const int per = (Ph + bd - 1) / bd;
+    for (int i = t; i < Ph; i += bd) s[i] = i < cnt ? cand[b + i] : INT_MAX;
     __syncthreads();
-    for (int kk = 2; kk <= P; kk <<= 1)
+    for (int kk = 2; kk <= Ph; kk <<= 1)
       for (int j = kk >> 1; j > 0; j >>= 1) {
-        for (int i = t; i < (P >> 1); i += bd) {
+        for (int i = t; i < (Ph >> 1); i += bd) {
           const int lo = ((i & ~(j - 1)) << 1) | (i & (j - 1)), hi = lo + j;
           const int32_t x = s[lo], y = s[hi];
           if ((x > y) == ((lo & kk) == 0)) s[lo] = y, s[hi] = x;
