@@ -396,9 +396,16 @@ __global__ void k_place_proc(const int32_t *perm, int64_t H, const int32_t *hptr
   }
 }
 
-__global__ void k_count_ids(const int32_t *ids, int64_t M, int32_t *cnt) {
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < M; e += (int64_t)gridDim.x * blockDim.x)
-    atomicAdd(&cnt[ids[e]], 1);
+// ptr[v] = the first index of v in the sorted ids (the insertion point where
+// v is absent), ptr[n] = M: each run start writes the entries of the ids after
+// the previous element's up to its own, the last element those past its id.
+__global__ void k_run_starts(const uint32_t *keys, int64_t M, int32_t n, int32_t *ptr) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < M; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t cur = keys[e], prev = e ? (int64_t)keys[e - 1] : -1;
+    for (int64_t v = prev + 1; v <= cur; ++v) ptr[v] = (int32_t)e;
+    if (e == M - 1)
+      for (int64_t v = cur + 1; v <= n; ++v) ptr[v] = (int32_t)M;
+  }
 }
 
 // bit e of lastbits: element e holds its vertex's last occurrence
@@ -927,9 +934,9 @@ void build_on_device(int32_t n, const int32_t *rp, const int32_t *ci, int32_t k,
     B.copy(keys.p, reinterpret_cast<const uint32_t *>(hvid.p), M);
     B.sort_pairs(keys.p, canon_pe.p, M, id_bits(n));
     B.copy(occ, canon_pe.p, M);
-    k_count_ids<<<blocks_for(M, kBT), kBT, 0, st>>>(hvid.p, M, occ_ptr);
+    // (an empty graph keeps the zeroed pointers)
+    if (M) k_run_starts<<<blocks_for(M, kBT), kBT, 0, st>>>(keys.p, M, n, occ_ptr);
     B.check();
-    B.scan(occ_ptr, occ_ptr, n);
     if (n) k_lastbits<<<G, kBT, 0, st>>>(occ_ptr, occ, n, lastbits);
     B.check();
   }
