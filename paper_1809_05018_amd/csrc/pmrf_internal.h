@@ -28,7 +28,7 @@ enum TileKind : uint8_t { kSmall = 0, kMid = 1, kLarge = 2 };
 struct TileDesc {
   uint64_t start_mask;  // bit i set: lane i starts a neighbourhood (SMALL/MID); 1 for LARGE
   int32_t elem_start;   // first element
-  int32_t hood_start;   // canonical id of the first neighbourhood
+  int32_t hood_start;   // processing index of the first neighbourhood
   int32_t mask_start;   // first adjacency word
   int16_t nelem;        // elements in the packet (<= 64, or the neighbourhood size for LARGE)
   uint8_t kind;         // TileKind
