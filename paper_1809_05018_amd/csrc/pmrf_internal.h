@@ -16,15 +16,16 @@ constexpr int kMaxHood = 1024;
 constexpr int kMaxHoodRadius = 8;  // k of the k-neighbourhoods
 constexpr int kMaxWindow = 8;
 
-// Work packet kinds.  A SMALL tile packs whole neighbourhoods of at most 32
-// members into the 64 lanes of one wave (one 32-bit adjacency word per
-// element); a MID tile holds one neighbourhood of 33..64 members (two words);
-// a LARGE tile holds one neighbourhood of 65..1024 members processed in
-// 64-element chunks (ceil(s/32) words per element).
+// Work packet kinds.  SMALL and MID tiles pack whole neighbourhoods of at most
+// 64 members into the 64 lanes of one wave (next-fit in processing order); a
+// tile holding one of 33..64 members is MID (two 32-bit adjacency words per
+// element, for every element of the tile), else SMALL (one word).  A LARGE
+// tile holds one neighbourhood of 65..1024 members processed in 64-element
+// pieces (ceil(s/32) words per element).
 enum TileKind : uint8_t { kSmall = 0, kMid = 1, kLarge = 2 };
 
 // One wave-sized work packet.  Elements of the packet are contiguous in the
-// element arrays; neighbourhoods inside it are consecutive in canonical order.
+// element arrays; neighbourhoods inside it are consecutive in processing order.
 struct TileDesc {
   uint64_t start_mask;  // bit i set: lane i starts a neighbourhood (SMALL/MID); 1 for LARGE
   int32_t elem_start;   // first element
