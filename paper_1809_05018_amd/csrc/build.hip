@@ -548,15 +548,38 @@ __global__ void k_masks(int64_t M, const int32_t *pe_hood, const int32_t *pptr, 
     const int32_t v = dev_vid[e];
     const int32_t *mem = dev_vid + p0;
     uint32_t *w = mask + moff[hp] + (int64_t)j * nw;
-    for (int q = 0; q < nw; ++q) w[q] = 0u;
-    for (int32_t q = rp[v]; q < rp[v + 1]; ++q) {
-      const int32_t p = find_sorted(mem, s, ci[q]);
-      if (p >= 0) {
-        w[p >> 5] |= 1u << (p & 31);
-        ++a;
+    const bool own = owner[v] == hptr[perm[hp]] + j;
+    const int32_t q0 = rp[v], q1 = rp[v + 1];
+    if (nw <= 2) {
+      // at most 64 members: both words in registers, written once; the graph
+      // neighbours' ids requested eight at a time
+      uint64_t bits = own ? 1ull << j : 0ull;
+      for (int32_t qb = q0; qb < q1; qb += 8) {
+        int32_t nb[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) nb[i] = qb + i < q1 ? ci[qb + i] : -1;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int32_t p = nb[i] >= 0 ? find_sorted(mem, s, nb[i]) : -1;
+          if (p >= 0) {
+            bits |= 1ull << p;
+            ++a;
+          }
+        }
       }
+      w[0] = (uint32_t)bits;
+      if (nw == 2) w[1] = (uint32_t)(bits >> 32);
+    } else {
+      for (int q = 0; q < nw; ++q) w[q] = 0u;
+      for (int32_t q = q0; q < q1; ++q) {
+        const int32_t p = find_sorted(mem, s, ci[q]);
+        if (p >= 0) {
+          w[p >> 5] |= 1u << (p & 31);
+          ++a;
+        }
+      }
+      if (own) w[j >> 5] |= 1u << (j & 31);
     }
-    if (owner[v] == hptr[perm[hp]] + j) w[j >> 5] |= 1u << (j & 31);
   }
   for (int d = 32; d > 0; d >>= 1) a += (unsigned long long)shfl_down64((int64_t)a, d);
   if ((threadIdx.x & 63) == 0 && a) atomicAdd(A, a);
