@@ -101,7 +101,10 @@ pmrf_status pmrf_build_neighborhoods(int32_t n, const int32_t *row_ptr, const in
  * equals pmrf_build_neighborhoods' in every exported array and in the layout
  * pmrf_hoods_upload writes, byte for byte; its layout and canonical arrays
  * stay in device memory owned by the object (hipMalloc; released by
- * pmrf_hoods_free), and pmrf_hoods_upload copies device to device.  The
+ * pmrf_hoods_free), and pmrf_hoods_upload copies device to device.  Its
+ * temporaries come stream-ordered from a memory pool the library creates
+ * per device (freeing them synchronises nothing else), which keeps up to
+ * 1 GiB of freed blocks for the next build until the process ends.  The
  * caller keeps ownership of the CSR, which is not needed afterwards.
  * Errors: as pmrf_build_neighborhoods, plus PMRF_EUNSUPPORTED when one
  * neighbourhood gathers more than 8192 candidate entries (its members'

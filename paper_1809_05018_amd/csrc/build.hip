@@ -34,6 +34,8 @@
 #include <climits>
 #include <cstdint>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -63,25 +65,83 @@ struct BuildError {
                        std::string("HIP: ") + hipGetErrorString(e_)};                                \
   } while (0)
 
-// Device array owned by the builder (released when it goes out of scope) or
-// handed over to the result.
+// Temporaries of a build come from a memory pool of the library's own, one per
+// device, stream-ordered on the build's stream (hipMallocFromPoolAsync /
+// hipFreeAsync): no device-wide synchronisation when a temporary is freed,
+// and freed blocks are reused by the next build.  The pool keeps up to
+// kPoolKeep bytes between builds.  The arrays handed over to the result are
+// plain hipMalloc allocations (freed with the result).
+constexpr uint64_t kPoolKeep = uint64_t(1) << 30;
+std::mutex g_pool_mu;
+std::map<int, hipMemPool_t> g_pools;
+
+hipMemPool_t build_pool() {
+  int dev = 0;
+  BTRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  auto it = g_pools.find(dev);
+  if (it != g_pools.end()) return it->second;
+  hipMemPoolProps props{};
+  props.allocType = hipMemAllocationTypePinned;
+  props.handleTypes = hipMemHandleTypeNone;
+  props.location.type = hipMemLocationTypeDevice;
+  props.location.id = dev;
+  hipMemPool_t pool = nullptr;
+  BTRY(hipMemPoolCreate(&pool, &props));
+  uint64_t keep = kPoolKeep;
+  BTRY(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep));
+  g_pools[dev] = pool;
+  return pool;
+}
+
+// the stream and pool of the build running on this thread (set by BuildScope)
+thread_local hipStream_t t_build_stream = nullptr;
+thread_local hipMemPool_t t_build_pool = nullptr;
+
+struct BuildScope {
+  BuildScope(hipStream_t s) {
+    t_build_pool = build_pool();
+    t_build_stream = s;
+  }
+  ~BuildScope() {
+    t_build_pool = nullptr;
+    t_build_stream = nullptr;
+  }
+};
+
+enum BufKind { kTemp = 0, kKeep = 1 };
+
+// Device array owned by the builder (released when it goes out of scope:
+// kTemp, from the build's pool) or handed over to the result (kKeep).
 template <class T>
 struct Buf {
   T *p = nullptr;
   int64_t n = 0;
+  bool pooled = false;
+  hipStream_t s = nullptr;
   Buf() = default;
-  explicit Buf(int64_t count) { alloc(count); }
-  void alloc(int64_t count) {
+  explicit Buf(int64_t count, BufKind kind = kTemp) { alloc(count, kind); }
+  void alloc(int64_t count, BufKind kind = kTemp) {
     release();
     n = count;
-    BTRY(hipMalloc(&p, (size_t)std::max<int64_t>(1, count) * sizeof(T)));
+    const size_t bytes = (size_t)std::max<int64_t>(1, count) * sizeof(T);
+    if (kind == kTemp && t_build_pool) {
+      s = t_build_stream;
+      BTRY(hipMallocFromPoolAsync(reinterpret_cast<void **>(&p), bytes, t_build_pool, s));
+      pooled = true;
+    } else {
+      BTRY(hipMalloc(&p, bytes));
+      pooled = false;
+    }
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) (void)(pooled ? hipFreeAsync(p, s) : hipFree(p));
     p = nullptr;
     n = 0;
+    pooled = false;
   }
   T *take() {
+    if (pooled) throw BuildError{PMRF_EDEVICE, "internal: a pooled temporary cannot be handed over"};
     T *q = p;
     p = nullptr;
     n = 0;
@@ -90,11 +150,11 @@ struct Buf {
   ~Buf() { release(); }
   Buf(const Buf &) = delete;
   Buf &operator=(const Buf &) = delete;
-  Buf(Buf &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr, o.n = 0; }
+  Buf(Buf &&o) noexcept : p(o.p), n(o.n), pooled(o.pooled), s(o.s) { o.p = nullptr, o.n = 0, o.pooled = false; }
   Buf &operator=(Buf &&o) noexcept {
     release();
-    p = o.p, n = o.n;
-    o.p = nullptr, o.n = 0;
+    p = o.p, n = o.n, pooled = o.pooled, s = o.s;
+    o.p = nullptr, o.n = 0, o.pooled = false;
     return *this;
   }
 };
@@ -716,6 +776,7 @@ int id_bits(int64_t n) {
 int64_t waves_grid(int64_t items) { return blocks_for(items, kBT / 64); }
 
 void build_on_device(int32_t n, const int32_t *rp, const int32_t *ci, int32_t k, hipStream_t st, pmrf_hoods *hd) {
+  BuildScope scope(st);
   Builder B(st);
   const int64_t G = blocks_for(std::max<int32_t>(n, 1), kBT);
 
@@ -792,7 +853,7 @@ void build_on_device(int32_t n, const int32_t *rp, const int32_t *ci, int32_t k,
   if (H >= (int64_t(1) << 30)) throw BuildError{PMRF_EUNSUPPORTED, "more than 2^30 maximal cliques"};
 
   // ---- 3. canonical order
-  Buf<int32_t> cptr(H + 1), first(n);
+  Buf<int32_t> cptr(H + 1, kKeep), first(n);
   {
     Buf<Level> dlev((int64_t)levels.size());
     if (!levels.empty())
@@ -807,7 +868,7 @@ void build_on_device(int32_t n, const int32_t *rp, const int32_t *ci, int32_t k,
     }
     B.scan(cptr.p, cptr.p, H);
     const int64_t ctotal = B.read(cptr.p + H);
-    Buf<int32_t> cvid(ctotal);
+    Buf<int32_t> cvid(ctotal, kKeep);
     for (size_t li = 0; li < levels.size(); ++li)
       k_place_cliques<<<blocks_for(levels[li].count, kBT), kBT, 0, st>>>(levels[li].c, levels[li].count, levels[li].k,
                                                                           ranks[li].p, cptr.p, cvid.p);
@@ -845,7 +906,7 @@ void build_on_device(int32_t n, const int32_t *rp, const int32_t *ci, int32_t k,
       int32_t P = 64;
       while (P < mx) P <<= 1;
       const int bd = std::min(256, std::max(64, P / 2));
-      Buf<int32_t> usize(H + 1), nptr(H + 1);
+      Buf<int32_t> usize(H + 1), nptr(H + 1, kKeep);
       if (H) {
         k_sort_unique<<<std::min<int64_t>(H, 1 << 16), bd, (size_t)P * 4, st>>>(cand.p, hcp.p, H, P, usize.p);
         B.check();
@@ -857,7 +918,7 @@ void build_on_device(int32_t n, const int32_t *rp, const int32_t *ci, int32_t k,
         throw BuildError{PMRF_EUNSUPPORTED, "a neighbourhood has " + std::to_string(max_hood) + " members (limit 1024)"};
       if (M >= (int64_t(1) << 31) / 2)
         throw BuildError{PMRF_EUNSUPPORTED, "more than 2^30 neighbourhood elements in one graph"};
-      Buf<int32_t> nvid(M);
+      Buf<int32_t> nvid(M, kKeep);
       k_copy_segs<int64_t><<<waves_grid(H), kBT, 0, st>>>(cand.p, hcp.p, nptr.p, usize.p, H, nvid.p);
       B.check();
       B.sync();
@@ -870,7 +931,7 @@ void build_on_device(int32_t n, const int32_t *rp, const int32_t *ci, int32_t k,
   hd->H = H;
   hd->M = M;
   hd->max_hood = (int32_t)max_hood;
-  Buf<int32_t> owner(n);
+  Buf<int32_t> owner(n, kKeep);
   if (n) k_owner<<<G, kBT, 0, st>>>(first.p, n, hptr.p, hvid.p, owner.p);
   B.check();
   first.release();
@@ -929,7 +990,7 @@ void build_on_device(int32_t n, const int32_t *rp, const int32_t *ci, int32_t k,
   z.nocc_ptr = (int64_t)n + 1;
   z.nocc = std::max<int64_t>(1, M);
   const DeviceLayout L = layout_of(z);
-  Buf<char> lay(L.total);
+  Buf<char> lay(L.total, kKeep);
   B.zero(lay.p, L.total);
   char *base = lay.p;
   TileDesc *tiles = reinterpret_cast<TileDesc *>(base + L.tiles_off);
