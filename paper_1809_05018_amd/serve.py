@@ -10,7 +10,9 @@ plus the exact workspace of the next batched call over the active set and the
 candidate (``pmrf_em_batch_workspace_bytes``).  A request that could not fit
 even alone is refused on its own (``Request.error``) and the others go on.
 Neighbourhoods of arriving requests are built on host worker threads while the
-device steps.
+device steps.  (The device builder's temporaries come from the library's own
+memory pool, which keeps up to 1 GiB of freed blocks per device; that reserve
+is outside ``hbm_budget``.)
 
 Splitting a request's iterations over several batched calls gives the same
 labels, parameters, energy trace and neighbourhood sums as one call with all
